@@ -1,0 +1,924 @@
+/* FP64 CPU oracle for the layered-field method.  TEST INFRASTRUCTURE ONLY:
+ * loaded by the tests, the smoke check and the benchmark's CPU baseline, never
+ * by the library.  See oracle.h for conventions.
+ *
+ * Written for readability against the paper, not for speed: every function
+ * follows the passage it cites, in the paper's order and notation, with plain
+ * loops.  Readings of points the paper leaves open are marked "Reading:".
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+void orc_free(void* p) { free(p); }
+
+/* ---- small growable arrays ------------------------------------------------ */
+
+typedef struct { int32_t* a; int64_t n, cap; } vi32;
+typedef struct { double* a; int64_t n, cap; } vf64;
+typedef struct { int64_t* a; int64_t n, cap; } vi64;
+
+static int vi32_push(vi32* v, int32_t x) {
+  if (v->n == v->cap) {
+    int64_t c = v->cap ? 2 * v->cap : 64;
+    int32_t* p = (int32_t*)realloc(v->a, (size_t)c * sizeof(int32_t));
+    if (!p) return ORC_ENOMEM;
+    v->a = p; v->cap = c;
+  }
+  v->a[v->n++] = x;
+  return ORC_OK;
+}
+static int vf64_push(vf64* v, double x) {
+  if (v->n == v->cap) {
+    int64_t c = v->cap ? 2 * v->cap : 64;
+    double* p = (double*)realloc(v->a, (size_t)c * sizeof(double));
+    if (!p) return ORC_ENOMEM;
+    v->a = p; v->cap = c;
+  }
+  v->a[v->n++] = x;
+  return ORC_OK;
+}
+static int vi64_push(vi64* v, int64_t x) {
+  if (v->n == v->cap) {
+    int64_t c = v->cap ? 2 * v->cap : 64;
+    int64_t* p = (int64_t*)realloc(v->a, (size_t)c * sizeof(int64_t));
+    if (!p) return ORC_ENOMEM;
+    v->a = p; v->cap = c;
+  }
+  v->a[v->n++] = x;
+  return ORC_OK;
+}
+
+static int cmp_i64(const void* x, const void* y) {
+  int64_t a = *(const int64_t*)x, b = *(const int64_t*)y;
+  return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* sort + unique an int64 key array in place, returns the new length */
+static int64_t sort_unique_i64(int64_t* a, int64_t n) {
+  if (n == 0) return 0;
+  qsort(a, (size_t)n, sizeof(int64_t), cmp_i64);
+  int64_t m = 1;
+  for (int64_t i = 1; i < n; ++i)
+    if (a[i] != a[m - 1]) a[m++] = a[i];
+  return m;
+}
+
+static void sub3(const double* a, const double* b, double* o) {
+  o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+static void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static double norm3(const double* a) { return sqrt(dot3(a, a)); }
+
+static int check_faces(int32_t n_v, int32_t n_f, const int32_t* F) {
+  if (n_v <= 0 || n_f < 0 || (n_f > 0 && !F)) return ORC_EINVAL;
+  for (int64_t f = 0; f < n_f; ++f) {
+    int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= n_v || b >= n_v || c >= n_v) return ORC_EINVAL;
+    if (a == b || b == c || a == c) return ORC_EINVAL;
+  }
+  return ORC_OK;
+}
+
+/* ---- operator --------------------------------------------------------------
+ * Section 3.2, "Laplacian computation": the mesh Laplacian is precomputed
+ * once.  Reading: an unnormalised operator approximating +nabla^2 (positive
+ * off-diagonals, zero row sums) so that the growth predicate of Algorithm 1
+ * (field Laplacian > 0) fires ahead of a front.  op 0: graph weights 1 per
+ * edge.  op 1: cotangent weights, half the sum of the cotangents of the two
+ * angles opposite the edge. */
+
+typedef struct { int32_t i, j, f; double w; } trip;
+
+static int cmp_trip(const void* x, const void* y) {
+  const trip* a = (const trip*)x;
+  const trip* b = (const trip*)y;
+  if (a->i != b->i) return a->i < b->i ? -1 : 1;
+  if (a->j != b->j) return a->j < b->j ? -1 : 1;
+  if (a->f != b->f) return a->f < b->f ? -1 : 1;
+  return 0;
+}
+
+int orc_operator(int32_t n_v, const double* V, int32_t n_f, const int32_t* F, int32_t op,
+                 int64_t* ptr, int32_t** col_out, double** val_out) {
+  if (check_faces(n_v, n_f, F) || (op != 0 && op != 1) || (op == 1 && !V)) return ORC_EINVAL;
+  int64_t nt = 6 * (int64_t)n_f;
+  trip* t = (trip*)malloc((size_t)(nt ? nt : 1) * sizeof(trip));
+  if (!t) return ORC_ENOMEM;
+  int64_t k = 0;
+  for (int32_t f = 0; f < n_f; ++f) {
+    const int32_t* c = F + 3 * (int64_t)f;
+    for (int corner = 0; corner < 3; ++corner) {
+      /* the corner opposite edge (p, q) */
+      int32_t o = c[corner], p = c[(corner + 1) % 3], q = c[(corner + 2) % 3];
+      double w = 1.0;
+      if (op == 1) {
+        double u[3], v[3], x[3];
+        sub3(V + 3 * (int64_t)p, V + 3 * (int64_t)o, u);
+        sub3(V + 3 * (int64_t)q, V + 3 * (int64_t)o, v);
+        cross3(u, v, x);
+        double s = norm3(x);
+        if (s == 0.0) { free(t); return ORC_EINVAL; }
+        w = 0.5 * dot3(u, v) / s;
+      }
+      t[k].i = p; t[k].j = q; t[k].f = f; t[k].w = w; ++k;
+      t[k].i = q; t[k].j = p; t[k].f = f; t[k].w = w; ++k;
+    }
+  }
+  qsort(t, (size_t)nt, sizeof(trip), cmp_trip);
+
+  /* merge duplicates: one entry per ordered vertex pair */
+  int64_t m = 0;
+  for (int64_t a = 0; a < nt;) {
+    int64_t b = a;
+    double s = 0.0;
+    while (b < nt && t[b].i == t[a].i && t[b].j == t[a].j) { s += t[b].w; ++b; }
+    t[m].i = t[a].i; t[m].j = t[a].j; t[m].w = (op == 0) ? 1.0 : s;
+    ++m;
+    a = b;
+  }
+  int64_t nnz = m + n_v;
+  int32_t* col = (int32_t*)malloc((size_t)nnz * sizeof(int32_t));
+  double* val = (double*)malloc((size_t)nnz * sizeof(double));
+  if (!col || !val) { free(t); free(col); free(val); return ORC_ENOMEM; }
+  int64_t e = 0, r = 0;
+  for (int32_t i = 0; i < n_v; ++i) {
+    ptr[i] = e;
+    int64_t r0 = r;
+    double diag = 0.0;
+    while (r < m && t[r].i == i) { diag -= t[r].w; ++r; }
+    int placed = 0;
+    for (int64_t s = r0; s < r; ++s) {
+      if (!placed && t[s].j > i) { col[e] = i; val[e] = diag; ++e; placed = 1; }
+      col[e] = t[s].j; val[e] = t[s].w; ++e;
+    }
+    if (!placed) { col[e] = i; val[e] = diag; ++e; }
+  }
+  ptr[n_v] = e;
+  free(t);
+  *col_out = col;
+  *val_out = val;
+  return ORC_OK;
+}
+
+/* ---- initialisation -------------------------------------------------------
+ * Algorithm 1, first line, and the Initialization paragraph of Section 3.2:
+ * a seeded vertex holds 1 in its own layer; every other vertex holds 1 in
+ * the base layer (column n_s). */
+int orc_init(int32_t n_v, const int32_t* seeds, int32_t n_s, int64_t* ptr, int32_t** col_out,
+             double** val_out) {
+  if (n_v <= 0 || n_s < 0 || (n_s > 0 && !seeds)) return ORC_EINVAL;
+  int32_t* owner = (int32_t*)malloc((size_t)n_v * sizeof(int32_t));
+  int32_t* col = (int32_t*)malloc((size_t)n_v * sizeof(int32_t));
+  double* val = (double*)malloc((size_t)n_v * sizeof(double));
+  if (!owner || !col || !val) { free(owner); free(col); free(val); return ORC_ENOMEM; }
+  for (int32_t i = 0; i < n_v; ++i) owner[i] = n_s;
+  for (int32_t k = 0; k < n_s; ++k) {
+    int32_t s = seeds[k];
+    if (s < 0 || s >= n_v || owner[s] != n_s) { free(owner); free(col); free(val); return ORC_EINVAL; }
+    owner[s] = k;
+  }
+  for (int32_t i = 0; i < n_v; ++i) { ptr[i] = i; col[i] = owner[i]; val[i] = 1.0; }
+  ptr[n_v] = n_v;
+  free(owner);
+  *col_out = col;
+  *val_out = val;
+  return ORC_OK;
+}
+
+/* ---- coefficient matrices a, w, e ------------------------------------------
+ * Equation (2) sums over pairs i<j, so a layer does not interact with itself:
+ * the diagonals are zero.  Off the diagonal the paper uses one value per
+ * matrix (w = 0.2 with a ratio of 5 to a).  Reading for the base layer b:
+ * it diffuses like any layer (a), it carries no penalty w ("allow cells to
+ * evolve freely"), and the band term is antisymmetric, +e for a cell against
+ * the base and -e for the base against a cell.  base_mode 1 instead treats
+ * the base as an ordinary layer. */
+
+static double coef_a(int32_t j, int32_t l, int32_t b, const orc_params* P) {
+  (void)b;
+  return j == l ? 0.0 : P->a;
+}
+static double coef_w(int32_t j, int32_t l, int32_t b, const orc_params* P) {
+  if (j == l) return 0.0;
+  if (P->base_mode == 0 && (j == b || l == b)) return 0.0;
+  return P->w;
+}
+static double coef_e(int32_t j, int32_t k, int32_t b, const orc_params* P) {
+  if (j == k) return 0.0;
+  if (P->base_mode == 1 || (j != b && k != b)) return P->e;
+  return (j == b) ? -P->e : P->e;
+}
+
+static void isort_i32(int32_t* a, int32_t n) {
+  for (int32_t i = 1; i < n; ++i) {
+    int32_t x = a[i], j = i - 1;
+    while (j >= 0 && a[j] > x) { a[j + 1] = a[j]; --j; }
+    a[j + 1] = x;
+  }
+}
+
+/* ---- one time step ----------------------------------------------------------
+ * Algorithm 1, body of the time loop:
+ *   L_t = Phi L^T                                   (SpGEMM)
+ *   for every vertex i (column of Phi):
+ *     irows = (Phi(:,i) > 0) or (Phi(:,i) = 0 and L_t(:,i) > 0);  n_i = |irows|
+ *     for j, k, l over irows:
+ *       sum = sum_l 1/2 (a_jl - a_kl) L_t(l,i) + (w_jl - w_kl) Phi(l,i)
+ *       d  += -(mu/n_i) (sum - e_jk sqrt(Phi(j,i) Phi(k,i)))
+ *     Phi(j,i) += d dt, clamped to [0, 1]
+ *   normalise each column by the sum of its nonzeros.
+ * Equations (11)-(13) are the same update written as a PDE.
+ * Reading (Jacobi): every value of the step is computed from the fields of
+ * the previous step; Section 4 describes the update as producing an updated
+ * copy of Phi-hat.  Reading (prune): after normalisation entries below theta
+ * are dropped (theta = 0 keeps every positive entry); zeros are never stored.
+ * In U = Phi^T terms, L_t(l,i) = sum_u L(i,u) U(u,l). */
+int orc_step(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc, const double* Lv,
+             const int64_t* Up, const int32_t* Uc, const double* Uv, const orc_params* P,
+             int64_t* Op, int32_t** Oc, double** Ov, double* margin, int32_t* skel,
+             int64_t* events) {
+  if (n_v <= 0 || n_s < 0 || !P) return ORC_EINVAL;
+  const int32_t n_r = n_s + 1, b = n_s;
+  double* lam = (double*)calloc((size_t)n_r, sizeof(double));
+  double* phi = (double*)calloc((size_t)n_r, sizeof(double));
+  char* touched = (char*)calloc((size_t)n_r, 1);
+  int32_t* list = (int32_t*)malloc((size_t)n_r * sizeof(int32_t));
+  int32_t* irows = (int32_t*)malloc((size_t)n_r * sizeof(int32_t));
+  double* pre = (double*)malloc((size_t)n_r * sizeof(double));
+  double* upd = (double*)malloc((size_t)n_r * sizeof(double));
+  vi32 oc = {0, 0, 0};
+  vf64 ov = {0, 0, 0};
+  int rc = ORC_OK;
+  int64_t ev = 0;
+  if (!lam || !phi || !touched || !list || !irows || !pre || !upd) { rc = ORC_ENOMEM; goto done; }
+
+  for (int32_t i = 0; i < n_v; ++i) {
+    int32_t nt = 0;
+    /* column i of L_t = Phi L^T, accumulated over the vertices u of row i of L */
+    for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) {
+      int32_t u = Lc[q];
+      double wu = Lv[q];
+      for (int64_t p = Up[u]; p < Up[u + 1]; ++p) {
+        int32_t l = Uc[p];
+        if (l < 0 || l >= n_r) { rc = ORC_EINVAL; goto done; }
+        if (!touched[l]) { touched[l] = 1; list[nt++] = l; lam[l] = 0.0; phi[l] = 0.0; }
+        lam[l] += wu * Uv[p];
+      }
+    }
+    /* column i of Phi */
+    for (int64_t p = Up[i]; p < Up[i + 1]; ++p) {
+      int32_t l = Uc[p];
+      if (l < 0 || l >= n_r || Uv[p] < 0.0) { rc = ORC_EINVAL; goto done; }
+      if (!touched[l]) { touched[l] = 1; list[nt++] = l; lam[l] = 0.0; phi[l] = 0.0; }
+      phi[l] = Uv[p];
+    }
+    isort_i32(list, nt);
+
+    /* rows of interest */
+    double mg = INFINITY;
+    int32_t n = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+      int32_t l = list[t];
+      if (phi[l] > 0.0 || (phi[l] == 0.0 && lam[l] > 0.0)) irows[n++] = l;
+      if (phi[l] == 0.0 && fabs(lam[l]) < mg) mg = fabs(lam[l]);
+    }
+    if (skel) skel[i] = n;
+
+    /* update: triple loop over the rows of interest (Jacobi: reads phi, lam) */
+    for (int32_t jj = 0; jj < n; ++jj) {
+      int32_t j = irows[jj];
+      double d = 0.0;
+      for (int32_t kk = 0; kk < n; ++kk) {
+        int32_t k = irows[kk];
+        double sum = 0.0;
+        for (int32_t ll = 0; ll < n; ++ll) {
+          int32_t l = irows[ll];
+          sum += 0.5 * (coef_a(j, l, b, P) - coef_a(k, l, b, P)) * lam[l] +
+                 (coef_w(j, l, b, P) - coef_w(k, l, b, P)) * phi[l];
+        }
+        d += -(P->mu / n) * (sum - coef_e(j, k, b, P) * sqrt(phi[j] * phi[k]));
+      }
+      double v = phi[j] + d * P->dt;
+      pre[jj] = v;
+      if (v > 1.0) v = 1.0;
+      if (v <= 0.0) v = 0.0;
+      upd[jj] = v;
+    }
+
+    /* normalise the column by the sum of its nonzeros */
+    double s = 0.0;
+    for (int32_t jj = 0; jj < n; ++jj) s += upd[jj];
+    Op[i] = oc.n;
+    if (n > 0 && s > 0.0) {
+      for (int32_t jj = 0; jj < n; ++jj) {
+        double v = upd[jj] / s;
+        if (P->theta > 0.0) {
+          if (fabs(v - P->theta) < mg) mg = fabs(v - P->theta);
+        } else if (fabs(pre[jj]) < mg) {
+          mg = fabs(pre[jj]);
+        }
+        if (v > 0.0 && v >= P->theta) {
+          if (vi32_push(&oc, irows[jj]) || vf64_push(&ov, v)) { rc = ORC_ENOMEM; goto done; }
+        }
+      }
+    } else if (n > 0) {
+      ++ev; /* every value clamped to zero: the column is left empty */
+    }
+    if (margin) margin[i] = mg;
+    for (int32_t t = 0; t < nt; ++t) touched[list[t]] = 0;
+  }
+  Op[n_v] = oc.n;
+  if (events) *events = ev;
+  /* hand the arrays over even when empty */
+  if (!oc.a) { oc.a = (int32_t*)malloc(sizeof(int32_t)); ov.a = (double*)malloc(sizeof(double)); }
+  *Oc = oc.a;
+  *Ov = ov.a;
+  oc.a = 0;
+  ov.a = 0;
+done:
+  free(lam); free(phi); free(touched); free(list); free(irows); free(pre); free(upd);
+  free(oc.a); free(ov.a);
+  return rc;
+}
+
+/* ---- labels -------------------------------------------------------------------
+ * The sharp visualisation (Figure 10, Section 7) shows, per vertex, the field
+ * with the largest influence: the argmax over the cell layers. */
+int orc_labels(int32_t n_v, int32_t n_s, const int64_t* Up, const int32_t* Uc, const double* Uv,
+               int32_t* labels, double* gap) {
+  if (n_v <= 0 || !labels) return ORC_EINVAL;
+  for (int32_t i = 0; i < n_v; ++i) {
+    /* columns are ascending, so a strict comparison keeps the lowest id */
+    int32_t best = -1;
+    double b1 = 0.0, b2 = 0.0;
+    for (int64_t p = Up[i]; p < Up[i + 1]; ++p) {
+      if (Uc[p] >= n_s) continue; /* the base layer is not a cell */
+      if (best < 0 || Uv[p] > b1) { best = Uc[p]; b1 = Uv[p]; }
+    }
+    for (int64_t p = Up[i]; p < Up[i + 1]; ++p)
+      if (Uc[p] < n_s && Uc[p] != best && Uv[p] > b2) b2 = Uv[p];
+    labels[i] = best;
+    if (gap) gap[i] = best < 0 ? INFINITY : b1 - b2;
+  }
+  return ORC_OK;
+}
+
+/* ---- Lloyd-like re-seeding ------------------------------------------------------
+ * Section 5: the centre of mass of a cell is the area-weighted average of the
+ * barycentres of all triangles having a vertex in the cell; it is projected
+ * back onto the cell along the area-weighted average of the triangle normals;
+ * among several intersections the one closest to the centre is taken; on a
+ * miss the seed stays.  Readings: the cell is the support of its layer
+ * (entries > 0); the projection line runs both ways from the centre and is
+ * tested against the cell's own triangles with closed edges; equal distances
+ * go to the lower face id; the new seed is the hit face's vertex nearest the
+ * hit point (lower id on ties).  Seed collisions: when several cells pick the
+ * same vertex the lowest cell id keeps it and the others stay; a mover that
+ * lands on the seed of a cell that stays also stays; repeated until no two
+ * seeds coincide. */
+
+/* line orig + s*dir against triangle (p0,p1,p2); returns 1 on a hit */
+static int line_tri(const double* orig, const double* dir, const double* p0, const double* p1,
+                    const double* p2, double* s_out, double* edge_out) {
+  double e1[3], e2[3], h[3], sv[3], q[3];
+  sub3(p1, p0, e1);
+  sub3(p2, p0, e2);
+  cross3(dir, e2, h);
+  double det = dot3(e1, h);
+  if (det == 0.0) { *edge_out = 0.0; return 0; }
+  double inv = 1.0 / det;
+  sub3(orig, p0, sv);
+  double u = inv * dot3(sv, h);
+  cross3(sv, e1, q);
+  double v = inv * dot3(dir, q);
+  double s = inv * dot3(e2, q);
+  double w = 1.0 - u - v;
+  double m = fabs(u);
+  if (fabs(v) < m) m = fabs(v);
+  if (fabs(w) < m) m = fabs(w);
+  *edge_out = m;
+  *s_out = s;
+  return (u >= 0.0 && v >= 0.0 && w >= 0.0) ? 1 : 0;
+}
+
+int orc_lloyd(int32_t n_v, const double* V, int32_t n_f, const int32_t* F, int32_t n_s,
+              const int64_t* Up, const int32_t* Uc, const double* Uv, const int32_t* seeds_in,
+              int32_t* seeds_out, int32_t* status, double* margin) {
+  if (check_faces(n_v, n_f, F) || !V || n_s <= 0 || !seeds_in || !seeds_out) return ORC_EINVAL;
+  /* faces of every cell, in increasing face id */
+  vi32* fl = (vi32*)calloc((size_t)n_s, sizeof(vi32));
+  int32_t* cand = (int32_t*)malloc((size_t)n_s * sizeof(int32_t));
+  int32_t* st = (int32_t*)malloc((size_t)n_s * sizeof(int32_t));
+  int32_t* owner = (int32_t*)malloc((size_t)n_v * sizeof(int32_t));
+  int rc = ORC_OK;
+  if (!fl || !cand || !st || !owner) { rc = ORC_ENOMEM; goto done; }
+  for (int32_t f = 0; f < n_f; ++f) {
+    int32_t cells[64];
+    int nc = 0;
+    for (int k = 0; k < 3; ++k) {
+      int32_t v = F[3 * (int64_t)f + k];
+      for (int64_t p = Up[v]; p < Up[v + 1]; ++p) {
+        int32_t c = Uc[p];
+        if (c >= n_s || !(Uv[p] > 0.0)) continue;
+        int seen = 0;
+        for (int t = 0; t < nc; ++t) seen |= (cells[t] == c);
+        if (!seen) {
+          if (nc == 64) { rc = ORC_EINVAL; goto done; }
+          cells[nc++] = c;
+        }
+      }
+    }
+    for (int t = 0; t < nc; ++t)
+      if (vi32_push(&fl[cells[t]], f)) { rc = ORC_ENOMEM; goto done; }
+  }
+
+  for (int32_t c = 0; c < n_s; ++c) {
+    double sa = 0.0, sb[3] = {0, 0, 0}, sn[3] = {0, 0, 0};
+    for (int64_t t = 0; t < fl[c].n; ++t) {
+      const int32_t* fv = F + 3 * (int64_t)fl[c].a[t];
+      const double *x0 = V + 3 * (int64_t)fv[0], *x1 = V + 3 * (int64_t)fv[1],
+                   *x2 = V + 3 * (int64_t)fv[2];
+      double e1[3], e2[3], cr[3];
+      sub3(x1, x0, e1);
+      sub3(x2, x0, e2);
+      cross3(e1, e2, cr);
+      double area = 0.5 * norm3(cr);
+      sa += area;
+      for (int d = 0; d < 3; ++d) {
+        sb[d] += area * (x0[d] + x1[d] + x2[d]) / 3.0;
+        sn[d] += 0.5 * cr[d]; /* area times unit normal */
+      }
+    }
+    double mg = INFINITY;
+    cand[c] = seeds_in[c];
+    st[c] = 1;
+    double nn = norm3(sn);
+    if (fl[c].n > 0 && sa > 0.0 && nn > 0.0) {
+      double ctr[3] = {sb[0] / sa, sb[1] / sa, sb[2] / sa};
+      double dir[3] = {sn[0] / nn, sn[1] / nn, sn[2] / nn};
+      int32_t bf = -1;
+      double bs = INFINITY, second = INFINITY;
+      double* es = (double*)malloc((size_t)fl[c].n * sizeof(double));
+      double* ss = (double*)malloc((size_t)fl[c].n * sizeof(double));
+      int* hit = (int*)malloc((size_t)fl[c].n * sizeof(int));
+      if (!es || !ss || !hit) { free(es); free(ss); free(hit); rc = ORC_ENOMEM; goto done; }
+      for (int64_t t = 0; t < fl[c].n; ++t) {
+        int32_t f = fl[c].a[t];
+        const int32_t* fv = F + 3 * (int64_t)f;
+        double s = INFINITY, e = 0.0;
+        hit[t] = line_tri(ctr, dir, V + 3 * (int64_t)fv[0], V + 3 * (int64_t)fv[1],
+                          V + 3 * (int64_t)fv[2], &s, &e);
+        es[t] = e;
+        ss[t] = s;
+        if (hit[t]) {
+          double a = fabs(s);
+          if (a < bs) { second = bs; bs = a; bf = f; }
+          else if (a < second) second = a;
+        }
+      }
+      /* margins: hit choice, and edge tests of faces that could win */
+      if (bf >= 0) {
+        double g = (second - bs) / (1.0 + bs);
+        if (g < mg) mg = g;
+      }
+      for (int64_t t = 0; t < fl[c].n; ++t) {
+        if (ss[t] == INFINITY || bf < 0 || fabs(ss[t]) <= bs * (1.0 + 1e-6) + 1e-12) {
+          if (es[t] < mg) mg = es[t];
+        }
+      }
+      free(es); free(ss); free(hit);
+      if (bf >= 0) {
+        const int32_t* fv = F + 3 * (int64_t)bf;
+        double hp[3] = {ctr[0], ctr[1], ctr[2]};
+        /* the hit point, recomputed from the chosen face's line parameter */
+        double sbest = INFINITY, e = 0.0;
+        line_tri(ctr, dir, V + 3 * (int64_t)fv[0], V + 3 * (int64_t)fv[1], V + 3 * (int64_t)fv[2],
+                 &sbest, &e);
+        for (int d = 0; d < 3; ++d) hp[d] += sbest * dir[d];
+        int32_t bv = -1;
+        double bd = INFINITY, bd2 = INFINITY;
+        for (int k = 0; k < 3; ++k) {
+          double dv[3];
+          sub3(V + 3 * (int64_t)fv[k], hp, dv);
+          double dd = dot3(dv, dv);
+          if (dd < bd || (dd == bd && fv[k] < bv)) { bd2 = bd; bd = dd; bv = fv[k]; }
+          else if (dd < bd2) bd2 = dd;
+        }
+        double g = (bd2 - bd) / (1.0 + bd);
+        if (g < mg) mg = g;
+        cand[c] = bv;
+        st[c] = 0;
+      }
+    }
+    if (margin) margin[c] = mg;
+  }
+
+  /* seed collisions, resolved to a fixed point */
+  for (int32_t i = 0; i < n_v; ++i) owner[i] = -1;
+  for (;;) {
+    int changed = 0;
+    for (int32_t i = 0; i < n_v; ++i) owner[i] = -1;
+    /* a cell that stays holds its seed before any mover is considered */
+    for (int32_t c = 0; c < n_s; ++c)
+      if (cand[c] == seeds_in[c]) owner[cand[c]] = c;
+    for (int32_t c = 0; c < n_s; ++c) {
+      if (cand[c] == seeds_in[c]) continue;
+      if (owner[cand[c]] == -1) owner[cand[c]] = c;
+    }
+    for (int32_t c = 0; c < n_s; ++c) {
+      if (owner[cand[c]] != c) { cand[c] = seeds_in[c]; st[c] = 2; changed = 1; }
+    }
+    if (!changed) break;
+  }
+  for (int32_t c = 0; c < n_s; ++c) {
+    seeds_out[c] = cand[c];
+    if (status) status[c] = st[c];
+  }
+done:
+  if (fl) for (int32_t c = 0; c < n_s; ++c) free(fl[c].a);
+  free(fl); free(cand); free(st); free(owner);
+  return rc;
+}
+
+/* ---- dual mesh -------------------------------------------------------------------
+ * Section 5.1 (cell neighbourhoods) and 5.2 (mesh construction).
+ *   Phibar = [U >= tau] on the cell layers (tau = 0.25)
+ *   A_v = Phibar Phibar^T without diagonal     (cells sharing a vertex)
+ *   B   = Phibar Mbar (logical)                 (cells touching a face)
+ *   A_t = B B^T without diagonal                (cells sharing a face)
+ *   candidates = A_t and not A_v; a candidate is confirmed when the two
+ *   cells' tau-isolines cross on one of their common faces; a confirmed
+ *   candidate whose cells already share two or more neighbours is dropped.
+ *   Dual triangles are the 3-cliques of the curated adjacency; a triangle
+ *   covering a cell of exactly three mutually adjacent neighbours is removed;
+ *   triangles are then oriented consistently by edge-neighbour propagation.
+ * Readings: the shared-neighbour count uses A_v (order-free); the isoline of
+ * a cell on a face is the segment between the linearly interpolated tau
+ * crossings on its edges (a vertex at exactly tau counts as inside); each
+ * component's lowest triangle is oriented along the summed vertex normals at
+ * its three seeds. */
+
+static int cmp_pair(const void* x, const void* y) {
+  const int32_t* a = (const int32_t*)x;
+  const int32_t* b = (const int32_t*)y;
+  if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+  if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;
+  return 0;
+}
+
+/* symmetric CSR over n cells from a list of unordered pair keys p*n+q (p<q) */
+static int pairs_to_csr(int64_t* keys, int64_t nk, int32_t n, int64_t** ptr_out,
+                        int32_t** col_out) {
+  nk = sort_unique_i64(keys, nk);
+  int32_t* pr = (int32_t*)malloc((size_t)(2 * nk + 1) * 2 * sizeof(int32_t));
+  int64_t* ptr = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  int32_t* col = (int32_t*)malloc((size_t)(2 * nk + 1) * sizeof(int32_t));
+  if (!pr || !ptr || !col) { free(pr); free(ptr); free(col); return ORC_ENOMEM; }
+  for (int64_t k = 0; k < nk; ++k) {
+    int32_t p = (int32_t)(keys[k] / n), q = (int32_t)(keys[k] % n);
+    pr[4 * k] = p; pr[4 * k + 1] = q;
+    pr[4 * k + 2] = q; pr[4 * k + 3] = p;
+  }
+  qsort(pr, (size_t)(2 * nk), 2 * sizeof(int32_t), cmp_pair);
+  for (int64_t k = 0; k < 2 * nk; ++k) { ptr[pr[2 * k] + 1]++; col[k] = pr[2 * k + 1]; }
+  for (int32_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  free(pr);
+  *ptr_out = ptr;
+  *col_out = col;
+  return ORC_OK;
+}
+
+static int csr_has(const int64_t* ptr, const int32_t* col, int32_t p, int32_t q) {
+  for (int64_t t = ptr[p]; t < ptr[p + 1]; ++t)
+    if (col[t] == q) return 1;
+  return 0;
+}
+
+static int64_t csr_common(const int64_t* ptr, const int32_t* col, int32_t p, int32_t q) {
+  int64_t a = ptr[p], b = ptr[q], n = 0;
+  while (a < ptr[p + 1] && b < ptr[q + 1]) {
+    if (col[a] == col[b]) { ++n; ++a; ++b; }
+    else if (col[a] < col[b]) ++a;
+    else ++b;
+  }
+  return n;
+}
+
+static double u_at(const int64_t* Up, const int32_t* Uc, const double* Uv, int32_t v, int32_t c) {
+  for (int64_t p = Up[v]; p < Up[v + 1]; ++p)
+    if (Uc[p] == c) return Uv[p];
+  return 0.0;
+}
+
+/* tau-isoline of a field on one face, as a segment in barycentric
+ * coordinates (weights of corners 1 and 2).  Returns 0 when the face is not
+ * crossed. */
+static int iso_segment(const double f[3], double tau, double seg[4]) {
+  int in[3] = {f[0] >= tau, f[1] >= tau, f[2] >= tau};
+  if (in[0] == in[1] && in[1] == in[2]) return 0;
+  int m = 0;
+  for (int e = 0; e < 3; ++e) {
+    int a = e, b = (e + 1) % 3;
+    if (in[a] == in[b]) continue;
+    double t = (tau - f[a]) / (f[b] - f[a]);
+    double bary[3] = {0, 0, 0};
+    bary[a] = 1.0 - t;
+    bary[b] = t;
+    seg[2 * m] = bary[1];
+    seg[2 * m + 1] = bary[2];
+    ++m;
+  }
+  return m == 2;
+}
+
+static double orient2(const double* a, const double* b, const double* c) {
+  return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
+}
+static int on_seg(const double* a, const double* b, const double* c) {
+  /* c collinear with a-b: is it within the bounding box? */
+  return fmin(a[0], b[0]) <= c[0] && c[0] <= fmax(a[0], b[0]) && fmin(a[1], b[1]) <= c[1] &&
+         c[1] <= fmax(a[1], b[1]);
+}
+/* closed segment intersection; *mg gets the smallest |determinant| used */
+static int seg_cross(const double* P, const double* Q, double* mg) {
+  const double *p0 = P, *p1 = P + 2, *q0 = Q, *q1 = Q + 2;
+  double d1 = orient2(q0, q1, p0), d2 = orient2(q0, q1, p1);
+  double d3 = orient2(p0, p1, q0), d4 = orient2(p0, p1, q1);
+  double m = fabs(d1);
+  if (fabs(d2) < m) m = fabs(d2);
+  if (fabs(d3) < m) m = fabs(d3);
+  if (fabs(d4) < m) m = fabs(d4);
+  if (m < *mg) *mg = m;
+  if (((d1 > 0 && d2 < 0) || (d1 < 0 && d2 > 0)) && ((d3 > 0 && d4 < 0) || (d3 < 0 && d4 > 0)))
+    return 1;
+  if (d1 == 0 && on_seg(q0, q1, p0)) return 1;
+  if (d2 == 0 && on_seg(q0, q1, p1)) return 1;
+  if (d3 == 0 && on_seg(p0, p1, q0)) return 1;
+  if (d4 == 0 && on_seg(p0, p1, q1)) return 1;
+  return 0;
+}
+
+void orc_dual_free(orc_dual* d) {
+  if (!d) return;
+  free(d->av_ptr); free(d->av_col); free(d->at_ptr); free(d->at_col);
+  free(d->ad_ptr); free(d->ad_col); free(d->cand); free(d->cand_state);
+  free(d->cand_margin); free(d->tri);
+  memset(d, 0, sizeof(*d));
+}
+
+int orc_dual_mesh(int32_t n_v, const double* V, int32_t n_f, const int32_t* F, int32_t n_s,
+                  const int64_t* Up, const int32_t* Uc, const double* Uv, const int32_t* seeds,
+                  double tau, orc_dual* out) {
+  if (check_faces(n_v, n_f, F) || !V || n_s <= 0 || !seeds || !out) return ORC_EINVAL;
+  memset(out, 0, sizeof(*out));
+  int rc = ORC_OK;
+  vi64 kv = {0, 0, 0}, kt = {0, 0, 0}, kd = {0, 0, 0}, bf = {0, 0, 0}, ek = {0, 0, 0};
+  vi32 cand = {0, 0, 0}, cst = {0, 0, 0}, tri = {0, 0, 0};
+  vf64 cmg = {0, 0, 0};
+  int64_t *bptr = 0, *tptr = 0;
+  int32_t *bcol = 0, *orient = 0, *fq = 0, *eface = 0;
+  char *removed = 0, *done_ = 0;
+  double* vn = 0;
+  const int64_t NS = n_s;
+
+  /* Phibar rows: thresholded cells of each vertex */
+#define THR(p) (Uc[p] < n_s && Uv[p] >= tau)
+  /* A_v: pairs of cells above tau at one vertex */
+  for (int32_t v = 0; v < n_v; ++v)
+    for (int64_t a = Up[v]; a < Up[v + 1]; ++a)
+      for (int64_t b = a + 1; b < Up[v + 1]; ++b)
+        if (THR(a) && THR(b)) {
+          int32_t p = Uc[a] < Uc[b] ? Uc[a] : Uc[b], q = Uc[a] < Uc[b] ? Uc[b] : Uc[a];
+          if (p != q && vi64_push(&kv, p * NS + q)) { rc = ORC_ENOMEM; goto done; }
+        }
+  if ((rc = pairs_to_csr(kv.a, kv.n, n_s, &out->av_ptr, &out->av_col))) goto done;
+
+  /* B = Phibar Mbar: cells touching each face; A_t = B B^T */
+  for (int32_t f = 0; f < n_f; ++f) {
+    int32_t cells[96];
+    int nc = 0;
+    for (int k = 0; k < 3; ++k) {
+      int32_t v = F[3 * (int64_t)f + k];
+      for (int64_t p = Up[v]; p < Up[v + 1]; ++p) {
+        if (!THR(p)) continue;
+        int seen = 0;
+        for (int t = 0; t < nc; ++t) seen |= (cells[t] == Uc[p]);
+        if (!seen) {
+          if (nc == 96) { rc = ORC_EINVAL; goto done; }
+          cells[nc++] = Uc[p];
+        }
+      }
+    }
+    isort_i32(cells, nc);
+    for (int a = 0; a < nc; ++a) {
+      if (vi64_push(&bf, cells[a] * (int64_t)n_f + f)) { rc = ORC_ENOMEM; goto done; }
+      for (int b = a + 1; b < nc; ++b)
+        if (vi64_push(&kt, cells[a] * NS + cells[b])) { rc = ORC_ENOMEM; goto done; }
+    }
+  }
+  if ((rc = pairs_to_csr(kt.a, kt.n, n_s, &out->at_ptr, &out->at_col))) goto done;
+  /* rows of B: faces of each cell, ascending */
+  bf.n = sort_unique_i64(bf.a, bf.n);
+  bptr = (int64_t*)calloc((size_t)n_s + 1, sizeof(int64_t));
+  bcol = (int32_t*)malloc((size_t)(bf.n + 1) * sizeof(int32_t));
+  if (!bptr || !bcol) { rc = ORC_ENOMEM; goto done; }
+  for (int64_t k = 0; k < bf.n; ++k) {
+    bptr[bf.a[k] / n_f + 1]++;
+    bcol[k] = (int32_t)(bf.a[k] % n_f);
+  }
+  for (int32_t c = 0; c < n_s; ++c) bptr[c + 1] += bptr[c];
+
+  /* candidates: A_t entries (p<q) absent from A_v */
+  for (int32_t p = 0; p < n_s; ++p)
+    for (int64_t t = out->at_ptr[p]; t < out->at_ptr[p + 1]; ++t) {
+      int32_t q = out->at_col[t];
+      if (q <= p || csr_has(out->av_ptr, out->av_col, p, q)) continue;
+      /* isoline crossing on a common face */
+      double mg = INFINITY;
+      int crossed = 0;
+      int64_t a = bptr[p], b = bptr[q];
+      while (a < bptr[p + 1] && b < bptr[q + 1]) {
+        if (bcol[a] < bcol[b]) { ++a; continue; }
+        if (bcol[a] > bcol[b]) { ++b; continue; }
+        int32_t f = bcol[a];
+        double fp[3], fq3[3], sp[4], sq[4];
+        for (int k = 0; k < 3; ++k) {
+          int32_t v = F[3 * (int64_t)f + k];
+          fp[k] = u_at(Up, Uc, Uv, v, p);
+          fq3[k] = u_at(Up, Uc, Uv, v, q);
+        }
+        if (iso_segment(fp, tau, sp) && iso_segment(fq3, tau, sq))
+          crossed |= seg_cross(sp, sq, &mg);
+        ++a; ++b;
+      }
+      int state = 0;
+      if (crossed) state = csr_common(out->av_ptr, out->av_col, p, q) >= 2 ? 2 : 1;
+      if (vi32_push(&cand, p) || vi32_push(&cand, q) || vi32_push(&cst, state) ||
+          vf64_push(&cmg, mg)) { rc = ORC_ENOMEM; goto done; }
+      if (state == 1 && vi64_push(&kd, p * NS + q)) { rc = ORC_ENOMEM; goto done; }
+    }
+  out->n_cand = cst.n;
+  out->cand = cand.a; cand.a = 0;
+  out->cand_state = cst.a; cst.a = 0;
+  out->cand_margin = cmg.a; cmg.a = 0;
+
+  /* curated adjacency = A_v plus the kept candidates */
+  for (int32_t p = 0; p < n_s; ++p)
+    for (int64_t t = out->av_ptr[p]; t < out->av_ptr[p + 1]; ++t)
+      if (out->av_col[t] > p && vi64_push(&kd, p * NS + out->av_col[t])) { rc = ORC_ENOMEM; goto done; }
+  if ((rc = pairs_to_csr(kd.a, kd.n, n_s, &out->ad_ptr, &out->ad_col))) goto done;
+  const int64_t* dp = out->ad_ptr;
+  const int32_t* dc = out->ad_col;
+
+  /* triangles: 3-cliques i<j<k, in lexicographic order */
+  for (int32_t i = 0; i < n_s; ++i)
+    for (int64_t a = dp[i]; a < dp[i + 1]; ++a) {
+      int32_t j = dc[a];
+      if (j <= i) continue;
+      for (int64_t b = a + 1; b < dp[i + 1]; ++b) {
+        int32_t k = dc[b];
+        if (k > j && csr_has(dp, dc, j, k))
+          if (vi32_push(&tri, i) || vi32_push(&tri, j) || vi32_push(&tri, k)) { rc = ORC_ENOMEM; goto done; }
+      }
+    }
+  int64_t nt = tri.n / 3;
+
+  /* spurious triangles: a cell with exactly three mutually adjacent
+   * neighbours j<k<l; the triangle (j,k,l) covers it and is removed */
+  removed = (char*)calloc((size_t)(nt + 1), 1);
+  if (!removed) { rc = ORC_ENOMEM; goto done; }
+  for (int32_t i = 0; i < n_s; ++i) {
+    if (dp[i + 1] - dp[i] != 3) continue;
+    int32_t j = dc[dp[i]], k = dc[dp[i] + 1], l = dc[dp[i] + 2];
+    if (!(csr_has(dp, dc, j, k) && csr_has(dp, dc, k, l) && csr_has(dp, dc, j, l))) continue;
+    for (int64_t t = 0; t < nt; ++t)
+      if (tri.a[3 * t] == j && tri.a[3 * t + 1] == k && tri.a[3 * t + 2] == l) removed[t] = 1;
+  }
+  {
+    int64_t m = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      if (removed[t]) { out->n_removed++; continue; }
+      tri.a[3 * m] = tri.a[3 * t];
+      tri.a[3 * m + 1] = tri.a[3 * t + 1];
+      tri.a[3 * m + 2] = tri.a[3 * t + 2];
+      ++m;
+    }
+    nt = m;
+  }
+
+  /* orientation.  Edge -> faces through sorted keys (edge key * nt + face). */
+  for (int64_t t = 0; t < nt; ++t)
+    for (int e = 0; e < 3; ++e) {
+      int32_t x = tri.a[3 * t + e], y = tri.a[3 * t + (e + 1) % 3];
+      int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+      if (vi64_push(&ek, (lo * NS + hi) * (nt + 1) + t)) { rc = ORC_ENOMEM; goto done; }
+    }
+  qsort(ek.a, (size_t)ek.n, sizeof(int64_t), cmp_i64);
+  /* for every (face, local edge) the face across it, or -1 */
+  eface = (int32_t*)malloc((size_t)(3 * nt + 1) * sizeof(int32_t));
+  if (!eface) { rc = ORC_ENOMEM; goto done; }
+  for (int64_t t = 0; t < 3 * nt; ++t) eface[t] = -1;
+  for (int64_t a = 0; a < ek.n;) {
+    int64_t b = a;
+    int64_t key = ek.a[a] / (nt + 1);
+    while (b < ek.n && ek.a[b] / (nt + 1) == key) ++b;
+    if (b - a > 2) out->n_nonmanifold++;
+    if (b - a == 2) {
+      int64_t f0 = ek.a[a] % (nt + 1), f1 = ek.a[a + 1] % (nt + 1);
+      int32_t lo = (int32_t)(key / NS), hi = (int32_t)(key % NS);
+      for (int e = 0; e < 3; ++e) {
+        int32_t x = tri.a[3 * f0 + e], y = tri.a[3 * f0 + (e + 1) % 3];
+        if ((x == lo && y == hi) || (x == hi && y == lo)) eface[3 * f0 + e] = (int32_t)f1;
+        x = tri.a[3 * f1 + e]; y = tri.a[3 * f1 + (e + 1) % 3];
+        if ((x == lo && y == hi) || (x == hi && y == lo)) eface[3 * f1 + e] = (int32_t)f0;
+      }
+    }
+    a = b;
+  }
+  /* primal vertex normals (area weighted) */
+  vn = (double*)calloc((size_t)3 * n_v, sizeof(double));
+  orient = (int32_t*)malloc((size_t)(3 * nt + 1) * sizeof(int32_t));
+  done_ = (char*)calloc((size_t)(nt + 1), 1);
+  fq = (int32_t*)malloc((size_t)(nt + 1) * sizeof(int32_t));
+  if (!vn || !orient || !done_ || !fq) { rc = ORC_ENOMEM; goto done; }
+  for (int32_t f = 0; f < n_f; ++f) {
+    const int32_t* fv = F + 3 * (int64_t)f;
+    double e1[3], e2[3], cr[3];
+    sub3(V + 3 * (int64_t)fv[1], V + 3 * (int64_t)fv[0], e1);
+    sub3(V + 3 * (int64_t)fv[2], V + 3 * (int64_t)fv[0], e2);
+    cross3(e1, e2, cr);
+    for (int k = 0; k < 3; ++k)
+      for (int d = 0; d < 3; ++d) vn[3 * (int64_t)fv[k] + d] += cr[d];
+  }
+  for (int64_t r = 0; r < nt; ++r) {
+    if (done_[r]) continue;
+    /* orient the component's lowest triangle along the summed normals */
+    int32_t* o = orient + 3 * r;
+    o[0] = tri.a[3 * r]; o[1] = tri.a[3 * r + 1]; o[2] = tri.a[3 * r + 2];
+    const double *x0 = V + 3 * (int64_t)seeds[o[0]], *x1 = V + 3 * (int64_t)seeds[o[1]],
+                 *x2 = V + 3 * (int64_t)seeds[o[2]];
+    double e1[3], e2[3], cr[3], ref[3];
+    sub3(x1, x0, e1);
+    sub3(x2, x0, e2);
+    cross3(e1, e2, cr);
+    for (int d = 0; d < 3; ++d)
+      ref[d] = vn[3 * (int64_t)seeds[o[0]] + d] + vn[3 * (int64_t)seeds[o[1]] + d] +
+               vn[3 * (int64_t)seeds[o[2]] + d];
+    if (dot3(cr, ref) < 0.0) { int32_t s = o[1]; o[1] = o[2]; o[2] = s; }
+    done_[r] = 1;
+    int64_t head = 0, tail = 0;
+    fq[tail++] = (int32_t)r;
+    while (head < tail) {
+      int32_t f = fq[head++];
+      const int32_t* of = orient + 3 * (int64_t)f;
+      for (int e = 0; e < 3; ++e) {
+        int32_t x = of[e], y = of[(e + 1) % 3];
+        /* the unoriented slot of the face across edge {x,y} */
+        int32_t g = -1;
+        for (int s = 0; s < 3; ++s) {
+          int32_t a = tri.a[3 * (int64_t)f + s], b = tri.a[3 * (int64_t)f + (s + 1) % 3];
+          if ((a == x && b == y) || (a == y && b == x)) g = eface[3 * (int64_t)f + s];
+        }
+        if (g < 0) continue;
+        /* g must traverse the shared edge as y -> x */
+        int32_t z = tri.a[3 * (int64_t)g] ^ tri.a[3 * (int64_t)g + 1] ^ tri.a[3 * (int64_t)g + 2] ^ x ^ y;
+        if (!done_[g]) {
+          orient[3 * (int64_t)g] = y;
+          orient[3 * (int64_t)g + 1] = x;
+          orient[3 * (int64_t)g + 2] = z;
+          done_[g] = 1;
+          fq[tail++] = g;
+        } else {
+          const int32_t* og = orient + 3 * (int64_t)g;
+          int ok = 0;
+          for (int s = 0; s < 3; ++s) ok |= (og[s] == y && og[(s + 1) % 3] == x);
+          if (!ok) out->n_conflict++;
+        }
+      }
+    }
+  }
+  /* each conflict is seen from both of its faces */
+  out->n_conflict /= 2;
+  out->n_tri = nt;
+  out->tri = orient;
+  orient = 0;
+  if (!out->tri) out->tri = (int32_t*)malloc(sizeof(int32_t));
+#undef THR
+done:
+  free(kv.a); free(kt.a); free(kd.a); free(bf.a); free(ek.a);
+  free(cand.a); free(cst.a); free(cmg.a); free(tri.a);
+  free(bptr); free(tptr); free(bcol); free(orient); free(fq); free(eface);
+  free(removed); free(done_); free(vn);
+  if (rc) orc_dual_free(out);
+  return rc;
+}

@@ -1,0 +1,247 @@
+"""Pins for the oracle's labels, Lloyd re-seeding and dual mesh (Section 5)."""
+import numpy as np
+import pytest
+
+from paper_1804_09152_amd import inputs as I
+
+
+def _csr(rows, n_cols=None):
+    ptr = np.zeros(len(rows) + 1, np.int64)
+    col, val = [], []
+    for i, r in enumerate(rows):
+        for c, v in sorted(r.items()):
+            col.append(c)
+            val.append(v)
+        ptr[i + 1] = len(col)
+    return ptr, np.array(col, np.int32), np.array(val, float)
+
+
+# ---- labels -----------------------------------------------------------------
+
+def test_labels_definition(orc):
+    rows = [{0: 0.5, 1: 0.5}, {2: 0.3, 3: 0.6, 4: 0.1}, {4: 1.0}, {1: 0.2, 4: 0.8}, {}]
+    lab, gap = orc.labels(_csr(rows), 4)  # column 4 is the base
+    assert list(lab) == [0, 3, -1, 1, -1]  # tie -> lower id; base never a label
+    assert np.allclose(gap[:2], [0.0, 0.3]) and gap[3] == pytest.approx(0.2)
+
+
+# ---- Lloyd ------------------------------------------------------------------
+
+def _ring(mesh, v):
+    nb = set()
+    for f in mesh.F:
+        if v in f:
+            nb.update(int(x) for x in f)
+    return nb
+
+
+def _cells_state(mesh, supports, n_s):
+    """rows: each vertex gets equal shares of the cells whose support holds it,
+    the base otherwise"""
+    rows = []
+    for v in range(mesh.n_v):
+        cs = [c for c in range(n_s) if v in supports[c]]
+        rows.append({c: 1.0 / len(cs) for c in cs} if cs else {n_s: 1.0})
+    return _csr(rows)
+
+
+def test_lloyd_symmetric_cell_moves_to_its_centre(orc):
+    # icosahedron vertex 3 has five-fold symmetric surroundings: the centroid
+    # of its ring lies on the axis through it, the line hits at the vertex
+    m = I.icosphere(2)
+    sup0 = _ring(m, 3)
+    sup1 = set(range(m.n_v)) - sup0
+    U = _cells_state(m, [sup0, sup1], 2)
+    seeds = np.array([min(sup0 - {3}), 0], np.int32)
+    new, st, mg = orc.lloyd(m.V, m.F, U, seeds)
+    assert new[0] == 3 and st[0] == 0
+
+
+def test_lloyd_miss_keeps_seed(orc):
+    # two caps around adjacent icosahedron vertices (63.4 degrees apart): the
+    # line through the centroid leaves between them and misses both
+    m = I.icosphere(3)
+    sup0 = _ring(m, 0) | _ring(m, 1)
+    U = _cells_state(m, [sup0], 1)
+    new, st, _ = orc.lloyd(m.V, m.F, U, np.array([0], np.int32))
+    assert st[0] == 1 and new[0] == 0
+
+
+def test_lloyd_collisions(orc):
+    m = I.icosphere(3)
+    ring = _ring(m, 3)
+    far = set(range(m.n_v)) - ring
+    # two cells want vertex 3: the lower id gets it, the other stays
+    U = _cells_state(m, [ring, ring, far], 3)
+    seeds = np.array([sorted(ring - {3})[0], sorted(ring - {3})[1], 0], np.int32)
+    new, st, _ = orc.lloyd(m.V, m.F, U, seeds)
+    assert new[0] == 3 and st[0] == 0
+    assert new[1] == seeds[1] and st[1] == 2
+    # a mover landing on the seed of a cell that misses stays where it is
+    caps = _ring(m, 0) | _ring(m, 1)
+    U = _cells_state(m, [ring, caps], 2)
+    seeds = np.array([sorted(ring - {3})[0], 3], np.int32)
+    new, st, _ = orc.lloyd(m.V, m.F, U, seeds)
+    assert st[1] == 1 and new[1] == 3
+    assert st[0] == 2 and new[0] == seeds[0]
+
+
+def test_lloyd_improves_area_balance(orc):
+    """Figure 7: Lloyd-like iterations even out the cell areas."""
+    m, seeds = I.config_c2(level=4, n_seeds=24)
+    L = orc.operator(m.V, m.F, 1)
+    p = orc.default_params()
+    # vertex areas: a third of each incident face
+    e1 = m.V[m.F[:, 1]] - m.V[m.F[:, 0]]
+    e2 = m.V[m.F[:, 2]] - m.V[m.F[:, 0]]
+    fa = 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1)
+    va = np.zeros(m.n_v)
+    for k in range(3):
+        np.add.at(va, m.F[:, k], fa / 3)
+    spread = []
+    for rnd in range(4):
+        U, _ = orc.run(L, orc.init(m.n_v, seeds), 24, p, 250)
+        lab, _ = orc.labels(U, 24)
+        area = np.bincount(lab[lab >= 0], weights=va[lab >= 0], minlength=24)
+        spread.append(area.std() / area.mean())
+        seeds, st, _ = orc.lloyd(m.V, m.F, U, seeds)
+        assert np.unique(seeds).size == 24
+    assert spread[-1] < 0.7 * spread[0]
+
+
+# ---- dual mesh ----------------------------------------------------------------
+
+def _lattice_torus(orc, nx=64, step=8, steps=120):
+    m = I.torus_grid(nx, nx)
+    L = orc.operator(m.V, m.F, 0)
+    seeds = np.array([x + nx * y for y in range(0, nx, step) for x in range(0, nx, step)], np.int32)
+    U, _ = orc.run(L, orc.init(m.n_v, seeds), seeds.size, orc.default_params(), steps)
+    return m, seeds, U
+
+
+def test_dual_mesh_regular_lattice(orc):
+    """Seeds on a sub-lattice of the (triangular-lattice) torus grid: the
+    dual is a regular triangulation of the torus."""
+    m, seeds, U = _lattice_torus(orc)
+    d = orc.dual_mesh(m.V, m.F, U, seeds)
+    k = seeds.size
+    deg = np.diff(d["A_d"][0])
+    assert (deg == 6).all()
+    T = d["tri"]
+    assert len(T) == 2 * k
+    edges = d["A_d"][1].size // 2
+    assert k - edges + len(T) == 0  # torus
+    # consistent orientation: every directed edge once, every edge twice
+    de = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+    key = de[:, 0].astype(np.int64) * k + de[:, 1]
+    assert np.unique(key).size == key.size
+    assert d["n_conflict"] == 0 and d["n_nonmanifold"] == 0
+
+
+def test_dual_mesh_sphere_vs_convex_hull(orc):
+    """Undisplaced sphere: the dual is close to the convex-hull Delaunay of
+    the seeds (Section 3.1, Figure 4 claims quasi-similarity)."""
+    from scipy.spatial import ConvexHull
+    m = I.icosphere(5)
+    k = 40
+    seeds = I.seeds_uniform(m.n_v, k, np.random.default_rng(0))
+    L = orc.operator(m.V, m.F, 1)
+    U, _ = orc.run(L, orc.init(m.n_v, seeds), k, orc.default_params(), 500)
+    d = orc.dual_mesh(m.V, m.F, U, seeds)
+    hull = set()
+    for s in ConvexHull(m.V[seeds]).simplices:
+        for a in range(3):
+            hull.add(tuple(sorted((int(s[a]), int(s[(a + 1) % 3])))))
+    ptr, col = d["A_d"]
+    ours = {(i, int(j)) for i in range(k) for j in col[ptr[i]:ptr[i + 1]] if i < j}
+    assert len(hull & ours) / len(hull | ours) >= 0.85
+    # A_v is a subset of A_t (Section 5.1)
+    for i in range(k):
+        av = set(d["A_v"][1][d["A_v"][0][i]:d["A_v"][0][i + 1]])
+        at = set(d["A_t"][1][d["A_t"][0][i]:d["A_t"][0][i + 1]])
+        assert av <= at
+    # triangles are 3-cliques and mostly face outwards
+    T = d["tri"]
+    adj = [set(col[ptr[i]:ptr[i + 1]]) for i in range(k)]
+    for a, b, c in T:
+        assert b in adj[a] and c in adj[a] and c in adj[b]
+    X = m.V[seeds]
+    n = np.cross(X[T[:, 1]] - X[T[:, 0]], X[T[:, 2]] - X[T[:, 0]])
+    assert (np.einsum("ij,ij->i", n, X[T].mean(1)) > 0).mean() > 0.9
+
+
+def _tet_case(phi_p, phi_q, extra=None):
+    """Regular tetrahedron, fields given per vertex for cells p=0, q=1 (and
+    optional extra cells); the base takes nothing (thresholds only)."""
+    V = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)
+    F = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]], np.int32)
+    cells = [phi_p, phi_q] + (extra or [])
+    n_s = len(cells)
+    rows = []
+    for v in range(4):
+        r = {c: cells[c][v] for c in range(n_s) if cells[c][v] > 0}
+        rows.append(r if r else {n_s: 1.0})
+    return V, F, _csr(rows), np.arange(n_s, dtype=np.int32), n_s
+
+
+def _segments_cross(fa, fb, tau=0.25):
+    """Independent check: supporting lines intersected by solving a 2x2
+    system, both parameters in [0, 1] (barycentric plane of one face)."""
+    def seg(f):
+        pts = []
+        for a, b in ((0, 1), (1, 2), (2, 0)):
+            if (f[a] >= tau) != (f[b] >= tau):
+                t = (tau - f[a]) / (f[b] - f[a])
+                w = np.zeros(3)
+                w[a], w[b] = 1 - t, t
+                pts.append(w[1:])
+        return pts if len(pts) == 2 else None
+    P, Q = seg(fa), seg(fb)
+    if P is None or Q is None:
+        return False
+    A = np.array([P[1] - P[0], Q[0] - Q[1]]).T
+    if abs(np.linalg.det(A)) < 1e-12:
+        return None  # parallel: not used by the randomized cases
+    s, t = np.linalg.solve(A, Q[0] - P[0])
+    return bool(0 <= s <= 1 and 0 <= t <= 1)
+
+
+def test_candidate_crossing_randomized(orc):
+    """Cells that share no vertex above tau but meet on faces: the verdict
+    on every candidate equals the independent segment test over the common
+    faces."""
+    rng = np.random.default_rng(11)
+    F = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]])
+    seen = {0: 0, 1: 0}
+    for trial in range(600):
+        pv = rng.uniform(0, 0.24, 4)
+        qv = rng.uniform(0, 0.24, 4)
+        a, b = rng.choice(4, 2, replace=False)
+        pv[a] = rng.uniform(0.3, 1.0)
+        qv[b] = rng.uniform(0.3, 1.0)
+        V, Fm, U, seeds, n_s = _tet_case(list(pv), list(qv))
+        d = orc.dual_mesh(V, Fm, U, seeds)
+        assert len(d["cand"]) == 1 and tuple(d["cand"][0]) == (0, 1)
+        verdicts = [_segments_cross(pv[f], qv[f]) for f in F]
+        if None in verdicts or d["cand_margin"][0] < 1e-9:
+            continue
+        expect = any(verdicts)
+        assert (d["cand_state"][0] == 1) == expect
+        seen[int(expect)] += 1
+    assert seen[0] > 10 and seen[1] > 10
+
+
+def test_manifold_rule(orc):
+    """A crossing candidate whose cells already share two neighbours is
+    dropped (Section 5.1, Figure 8c); without them it is kept."""
+    p = [0.9, 0.2, 0.2, 0.0]
+    q = [0.2, 0.9, 0.2, 0.0]
+    V, F, U, seeds, n_s = _tet_case(p, q)
+    d = orc.dual_mesh(V, F, U, seeds)
+    assert list(d["cand_state"]) == [1]
+    r = [0.3, 0.3, 0.0, 0.0]
+    s = [0.3, 0.3, 0.0, 0.1]
+    V, F, U, seeds, n_s = _tet_case(p, q, [r, s])
+    d = orc.dual_mesh(V, F, U, seeds)
+    i = [tuple(c) for c in d["cand"]].index((0, 1))
+    assert d["cand_state"][i] == 2
