@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the layered-field hot path on one MI355X.
+
+Workload (one bench "step" = one whole job): icosphere level 9 (2,621,442
+vertices, 5,242,880 triangles) radially displaced by 8 random real spherical
+harmonics (max amplitude 0.2), cotangent operator, 16,384 seeds; the fields
+are initialised from the seeds, advanced by 2,000 explicit Euler steps,
+labelled, re-seeded once (Lloyd) and turned into a dual mesh.  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line: field nnz-updates/s (sum over steps of the rows-of-
+interest sizes divided by wall time), the step kernel's roofline (algorithmic
+bytes per launch over its event-timed duration, against 8 TB/s), and the
+FP64 CPU oracle timed on a bounded sample of the same job.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "field nnz-updates/sec and % HBM peak per step; p50/p99 job latency batched"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for name in ("lf_step.hip", "lf_internal.h"):
+        with open(os.path.join(ROOT, "paper_1804_09152_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(alg_bytes_per_launch: float):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, or None when it was taken on other kernel sources."""
+    p = os.path.join(ROOT, "profiles", "k_step_c3_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_src_sha") != kernel_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(mesh, seeds, seconds: float, max_steps: int = 200):
+    import oracle
+    oracle.build()
+    log("cpu baseline: oracle operator")
+    L = oracle.operator(mesh.V, mesh.F, 1)
+    U = oracle.init(mesh.n_v, seeds)
+    P = oracle.default_params()
+    skel = 0
+    n = 0
+    t0 = time.perf_counter()
+    while n < max_steps:
+        U, info = oracle.step(L, U, seeds.size, P, want_info=True)
+        skel += int(info["skel"].sum())
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    log(f"cpu baseline: {n} steps in {dt:.1f} s")
+    return {"value": skel / dt, "unit": "nnz-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} Euler steps of the same job from its seeds, FP64 C oracle, "
+                      f"one thread, operator build excluded ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed jobs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
+    ap.add_argument("--euler-steps", type=int, default=2000)
+    ap.add_argument("--level", type=int, default=9)
+    ap.add_argument("--seeds", type=int, default=16384)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-post", action="store_true", help="skip Lloyd and dual mesh")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1804_09152_amd as lfb
+    from paper_1804_09152_amd import inputs as I
+
+    lfb.load()
+    log("generating the mesh")
+    mesh, seeds = I.config_c3(level=args.level, n_seeds=args.seeds)
+    dev = torch.device("cuda", 0)
+    ctx = lfb.Context(0)
+    log("operator build")
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, lfb.LF_OP_COTAN)
+    f = lfb.Fields(m, seeds)
+    labels = torch.empty(mesh.n_v, dtype=torch.int32, device=dev)
+    post = not args.no_post
+    have_post = True
+
+    def job():
+        nonlocal have_post
+        f.reset(seeds)
+        f.step(args.euler_steps)
+        lfb.lf_labels(f.h, labels)
+        if post and have_post:
+            try:
+                f.lloyd_reseed()
+                f.dual_mesh(0.25)
+            except lfb.LFError as e:
+                if e.status != 6:
+                    raise
+                have_post = False
+
+    for w in range(args.warmup):
+        log(f"warmup job {w}")
+        job()
+    torch.cuda.synchronize()
+    st0 = f.stats()
+    tin0, tout0 = f.traffic()
+    f.timing(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        log(f"timed job {k}")
+        job()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_total, launches = f.timing(0)
+    st1 = f.stats()
+    tin1, tout1 = f.traffic()
+    wall = t1 - t0
+    skel = st1["skeleton_total"] - st0["skeleton_total"]
+    n_v = mesh.n_v
+    nnz_off = lfb.lf_mesh_operator(m.h) - n_v
+    op_bytes = 4 * (n_v + 1) + 8 * nnz_off + 4 * n_v
+    alg_bytes = launches * (op_bytes + 2 * 4 * (n_v + 1)) + 8 * ((tin1 - tin0) + (tout1 - tout0))
+    per_launch_bytes = alg_bytes / max(launches, 1)
+    avg_ms = ms_total / max(launches, 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(per_launch_bytes)
+    out = {
+        "metric": METRIC,
+        "value": skel / wall,
+        "unit": "nnz-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"icosphere level {args.level} displaced by 8 random spherical harmonics, "
+                         f"cotangent operator, {args.seeds} seeds, {args.euler_steps} Euler steps"
+                         + (" + labels + Lloyd re-seed + dual mesh" if (post and have_post)
+                            else " + labels")),
+            "n_vertices": n_v,
+            "n_faces": mesh.n_f,
+            "n_seeds": int(seeds.size),
+            "euler_steps_per_job": args.euler_steps,
+            "step_kernel_us": avg_ms * 1e3,
+            "step_kernel_launches": launches,
+            "mean_nnz_per_vertex": (tout1 - tout0) / max(launches, 1) / n_v,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, seeds, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/* lf.h -- C ABI of the MI355X (gfx950) layered-field library.
+ *
+ * Implements the method of Zayer, Mlakar, Steinberger, Seidel, "Layered
+ * Fields for Natural Tessellations on Surfaces": a sparse field matrix with
+ * one layer per cell (plus a base layer) is evolved on a triangle mesh by
+ * explicit Euler steps (Algorithm 1, equations (11)-(13)); cells are read
+ * off as labels, re-seeded Lloyd-style (Section 5) and turned into a dual
+ * triangle mesh (Sections 5.1-5.2).
+ *
+ * Conventions
+ *  - Every function returns lf_status; nothing throws or longjmps across the
+ *    ABI.  On failure lf_last_error() returns a message (thread-local, owned
+ *    by the library, valid until the next call on the same thread).
+ *  - Field matrix U = Phi^T: CSR, one row per vertex, one column per layer;
+ *    columns 0..n_s-1 are the cells in seed order, column n_s is the base
+ *    layer.  Row pointers and column ids are int32, values float32, columns
+ *    ascending within a row, stored values > 0.
+ *  - "Host or device" buffers: arguments documented with `is_device_ptr`
+ *    take caller-owned memory; device pointers must stay valid until the
+ *    call returns (all calls synchronise with the context stream before
+ *    returning, except lf_step which is asynchronous unless it has to grow
+ *    storage).
+ *  - Handles are created and destroyed explicitly by their owner.  A context
+ *    serves one host thread at a time; calls on one context serialise on its
+ *    stream.
+ *  - All device state lives in the GPU's HBM and is allocated by the library.
+ */
+#ifndef LF_H
+#define LF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LF_OK = 0,
+  LF_EINVAL = 1,    /* invalid argument (ids out of range, duplicate seeds, ...) */
+  LF_ENOMEM = 2,    /* device or host allocation failed; state unchanged */
+  LF_EDEVICE = 3,   /* HIP runtime error */
+  LF_ECAPACITY = 4, /* storage could not be grown / a row exceeded the row limit */
+  LF_EBUSY = 5,
+  LF_ENOSYS = 6
+} lf_status;
+
+typedef enum { LF_OP_GRAPH = 0, LF_OP_COTAN = 1 } lf_operator;
+
+/* Constants of the update (Section 3.1; values of Section 7 where given).
+ * w: penalty between cells (0.2); a: gradient coefficient (0.04, a ratio of
+ * 5 to w); e: band interaction (1.0); mu: mobility (0.1); dt: Euler step
+ * (5.0); theta: entries below theta after normalisation are dropped (1e-3;
+ * 0 keeps every positive entry); tau: dual-mesh threshold (0.25).
+ * base_mode 0: the base layer couples to cells through the gradient term
+ * and an antisymmetric band term only; 1: the base is an ordinary layer.
+ * capacity_hint: initial field storage in entries (0 = 3 per vertex). */
+typedef struct {
+  double w, a, e, mu, dt, theta, tau;
+  int32_t base_mode;
+  int32_t pad_;
+  int64_t capacity_hint;
+} lf_params;
+
+typedef struct lf_ctx lf_ctx;
+typedef struct lf_mesh lf_mesh;
+typedef struct lf_fields lf_fields;
+
+const char* lf_last_error(void);
+void lf_params_default(lf_params* p);
+
+/* Context on one GPU.  hip_stream: a hipStream_t to run on (for example
+ * torch.cuda.current_stream().cuda_stream), or NULL for a library-owned
+ * stream. */
+lf_status lf_ctx_create(int32_t device, void* hip_stream, lf_ctx** out);
+lf_status lf_ctx_destroy(lf_ctx* ctx);
+
+/* Mesh and its operator (Section 3.2, "Laplacian computation"): the
+ * Laplacian is computed once on the GPU.  V: float64[n_v*3] host positions;
+ * F: int32[n_f*3] host triangles (copied in).  LF_EINVAL on ids out of
+ * range or a face repeating a vertex; LF_EINVAL for a zero-area face with
+ * the cotangent operator.  Graph: L_ij = 1 per edge; cotangent: L_ij =
+ * (cot alpha + cot beta)/2; both with L_ii = -sum_j L_ij. */
+lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* F,
+                         int32_t n_f, int32_t op, lf_mesh** out);
+lf_status lf_mesh_destroy(lf_mesh* mesh);
+/* Operator export (diagonal included, columns ascending), size query with
+ * NULL buffers: *nnz is always written.  rowptr int32[n_v+1], col int32[nnz],
+ * val float32[nnz]. */
+lf_status lf_mesh_operator(lf_mesh* mesh, int64_t* nnz, int32_t* rowptr, int32_t* col,
+                           float* val, int32_t is_device_ptr);
+
+/* Fields (Algorithm 1, first line; Initialization paragraph): seeds
+ * int32[n_s] host array of distinct vertex ids; a seed holds 1 in its own
+ * layer, every other vertex 1 in the base layer.  params may be NULL for the
+ * defaults. */
+lf_status lf_fields_create(lf_mesh* mesh, const int32_t* seeds, int32_t n_s,
+                           const lf_params* params, lf_fields** out);
+lf_status lf_fields_destroy(lf_fields* f);
+/* Re-initialise from new seeds (same count), as after a Lloyd re-seeding. */
+lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds);
+/* Current seeds, int32[n_s] host. */
+lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds);
+
+/* n_steps explicit Euler steps of Algorithm 1 (Jacobi form): field
+ * Laplacian L_t = Phi L^T (row form: L U), rows of interest, update with
+ * clamping to [0,1], column normalisation, then the theta prune.  Runs on the
+ * context stream; output storage grows on the device side (an overflowing
+ * step is detected on the GPU, storage grows by 20% or more and the step is
+ * replayed).  LF_ECAPACITY if a vertex touches more layers than the row
+ * limit (64) or storage cannot grow. */
+lf_status lf_step(lf_fields* f, int32_t n_steps);
+lf_status lf_sync(lf_fields* f);
+
+/* Export U.  Size query with NULL buffers (*nnz always written).  rowptr
+ * int32[n_v+1], col int32[nnz], val float32[nnz]; host or device. */
+lf_status lf_fields_export(lf_fields* f, int64_t* nnz, int32_t* rowptr, int32_t* col,
+                           float* val, int32_t is_device_ptr);
+/* Import U (teacher forcing, resume).  Must be canonical: rowptr monotone
+ * from 0, columns ascending in [0, n_s], values in (0, 1].  LF_EINVAL
+ * otherwise (checked on the GPU). */
+lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                           const float* val, int32_t is_device_ptr);
+
+/* Sharp labels (Figure 10, Section 7): per vertex, the cell layer with the
+ * largest value (lowest id on ties), -1 when the vertex holds no cell.
+ * labels int32[n_v], host or device. */
+lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_device_ptr);
+
+/* One Lloyd-like re-seeding (Section 5) from the current fields: per cell,
+ * area-weighted centroid of the barycentres of the faces having a vertex in
+ * the cell's support and the area-weighted mean normal; the line through
+ * the centroid along it is intersected with those faces; the closest hit
+ * wins (lower face id on ties) and the new seed is that face's vertex
+ * nearest the hit (lower id on ties); a miss keeps the seed.  Colliding
+ * seeds: the lowest cell id keeps the vertex, the others (and movers onto a
+ * staying seed) keep their old seed.  Geometry in float64.  Writes
+ * seeds_out int32[n_s] and status int32[n_s] (0 hit, 1 miss, 2 collision;
+ * may be NULL), host.  Does not re-initialise the fields. */
+lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status);
+
+/* Dual mesh (Sections 5.1-5.2) from the current fields with threshold tau:
+ * A_v = Phibar Phibar^T, A_t = (Phibar Mbar)(Phibar Mbar)^T, candidates
+ * A_t and not A_v confirmed by isoline crossings on their common faces,
+ * confirmed candidates whose cells share two or more A_v neighbours are
+ * dropped, triangles are the 3-cliques of the curated adjacency, spurious
+ * triangles over a cell of three mutually adjacent neighbours are removed,
+ * orientation is propagated across edges from each component's lowest
+ * triangle.  Size query with NULL buffers: n_tri and adj_nnz are always
+ * written.  tris int32[3*n_tri]; adj_rowptr int32[n_s+1], adj_col
+ * int32[adj_nnz]; host. */
+lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, int64_t* adj_nnz,
+                       int32_t* adj_rowptr, int32_t* adj_col);
+/* Intermediate matrices of the last lf_dual_mesh call, for inspection:
+ * which 0 = A_v, 1 = A_t; candidates as pairs with state 0 rejected, 1 kept,
+ * 2 dropped by the shared-neighbour rule.  Size query with NULL buffers. */
+lf_status lf_dual_matrix(lf_fields* f, int32_t which, int64_t* nnz, int32_t* rowptr,
+                         int32_t* col);
+lf_status lf_dual_candidates(lf_fields* f, int64_t* n_cand, int32_t* pairs, int32_t* state);
+
+/* Counters since creation or the last reset: nnz of U, sum over steps of the
+ * rows-of-interest sizes (|skeleton|), steps taken, zero-sum columns,
+ * storage growth events. */
+lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skeleton_total, int64_t* steps,
+                   int64_t* empty_columns, int64_t* grow_events);
+
+/* Entries read and written by the completed steps: the sums over steps of
+ * nnz(U_t) and nnz(U_{t+1}) (for the algorithmic byte count of a step:
+ * operator once, U_t in, U_{t+1} out). */
+lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out);
+
+/* Device time of the step kernels, measured with HIP events on the
+ * context stream around every step launch while enabled; total in ms and
+ * number of launches timed since the last enable. */
+lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,400 @@
+"""Python binding of liblf.so, the gfx950 layered-field library.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  The functions `lf_*` mirror the C ABI in include/lf.h one to
+one (same names, same arguments, a handle in place of an out-pointer);
+`Context`, `Mesh` and `Fields` are small owners of those handles.  PyTorch
+provides device memory (tensors passed by data_ptr) and streams.
+
+There is no fallback: if liblf.so is missing or fails to load, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["LFError", "load", "Context", "Mesh", "Fields", "default_params",
+           "LF_OP_GRAPH", "LF_OP_COTAN"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblf.so")
+LF_OP_GRAPH = 0
+LF_OP_COTAN = 1
+_STATUS = {0: "LF_OK", 1: "LF_EINVAL", 2: "LF_ENOMEM", 3: "LF_EDEVICE", 4: "LF_ECAPACITY",
+           5: "LF_EBUSY", 6: "LF_ENOSYS"}
+
+
+class LFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class lf_params(C.Structure):
+    _fields_ = [("w", C.c_double), ("a", C.c_double), ("e", C.c_double), ("mu", C.c_double),
+                ("dt", C.c_double), ("theta", C.c_double), ("tau", C.c_double),
+                ("base_mode", C.c_int32), ("pad_", C.c_int32), ("capacity_hint", C.c_int64)]
+
+
+EXPORTS = [
+    "lf_last_error", "lf_params_default", "lf_ctx_create", "lf_ctx_destroy", "lf_mesh_create",
+    "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
+    "lf_fields_reset", "lf_fields_seeds", "lf_step", "lf_sync", "lf_fields_export",
+    "lf_fields_import", "lf_labels", "lf_lloyd_reseed", "lf_dual_mesh", "lf_dual_matrix",
+    "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
+]
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load liblf.so (no build, no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise LFError(6, f"{p} is missing: build it with python -m paper_1804_09152_amd.build")
+    lib = C.CDLL(p)
+    V, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    PV = C.POINTER(C.c_void_p)
+    sig = {
+        "lf_last_error": (C.c_char_p, []),
+        "lf_params_default": (None, [C.POINTER(lf_params)]),
+        "lf_ctx_create": (C.c_int, [I32, V, PV]),
+        "lf_ctx_destroy": (C.c_int, [V]),
+        "lf_mesh_create": (C.c_int, [V, V, I32, V, I32, I32, PV]),
+        "lf_mesh_destroy": (C.c_int, [V]),
+        "lf_mesh_operator": (C.c_int, [V, V, V, V, V, I32]),
+        "lf_fields_create": (C.c_int, [V, V, I32, C.POINTER(lf_params), PV]),
+        "lf_fields_destroy": (C.c_int, [V]),
+        "lf_fields_reset": (C.c_int, [V, V]),
+        "lf_fields_seeds": (C.c_int, [V, V]),
+        "lf_step": (C.c_int, [V, I32]),
+        "lf_sync": (C.c_int, [V]),
+        "lf_fields_export": (C.c_int, [V, V, V, V, V, I32]),
+        "lf_fields_import": (C.c_int, [V, I64, V, V, V, I32]),
+        "lf_labels": (C.c_int, [V, V, I32]),
+        "lf_lloyd_reseed": (C.c_int, [V, V, V]),
+        "lf_dual_mesh": (C.c_int, [V, D, V, V, V, V, V]),
+        "lf_dual_matrix": (C.c_int, [V, I32, V, V, V]),
+        "lf_dual_candidates": (C.c_int, [V, V, V, V]),
+        "lf_stats": (C.c_int, [V, V, V, V, V, V]),
+        "lf_traffic": (C.c_int, [V, V, V]),
+        "lf_step_timing": (C.c_int, [V, I32, V, V]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LFError(rc, load().lf_last_error().decode())
+
+
+def _ptr(a):
+    """numpy array or torch tensor -> (address, is_device)"""
+    if a is None:
+        return None, 0
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data, 0
+    assert a.is_contiguous()
+    return a.data_ptr(), int(a.is_cuda)
+
+
+def _addr(x):
+    return C.byref(x)
+
+
+def default_params(**kw) -> lf_params:
+    p = lf_params()
+    load().lf_params_default(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+# ---- C ABI, one wrapper per entry point ------------------------------------------
+
+def lf_ctx_create(device: int = 0, stream=None):
+    h = C.c_void_p()
+    _check(load().lf_ctx_create(device, stream, C.byref(h)))
+    return h
+
+
+def lf_ctx_destroy(ctx):
+    _check(load().lf_ctx_destroy(ctx))
+
+
+def lf_mesh_create(ctx, V: np.ndarray, F: np.ndarray, op: int):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    h = C.c_void_p()
+    _check(load().lf_mesh_create(ctx, V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], op,
+                                 C.byref(h)))
+    return h
+
+
+def lf_mesh_destroy(mesh):
+    _check(load().lf_mesh_destroy(mesh))
+
+
+def lf_mesh_operator(mesh, rowptr=None, col=None, val=None):
+    nnz = C.c_int64()
+    pr, d = _ptr(rowptr)
+    pc, _ = _ptr(col)
+    pv, _ = _ptr(val)
+    _check(load().lf_mesh_operator(mesh, C.byref(nnz), pr, pc, pv, d))
+    return nnz.value
+
+
+def lf_fields_create(mesh, seeds, params: lf_params | None = None):
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    h = C.c_void_p()
+    _check(load().lf_fields_create(mesh, seeds.ctypes.data, seeds.size,
+                                   C.byref(params) if params is not None else None, C.byref(h)))
+    return h
+
+
+def lf_fields_destroy(f):
+    _check(load().lf_fields_destroy(f))
+
+
+def lf_fields_reset(f, seeds):
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    _check(load().lf_fields_reset(f, seeds.ctypes.data))
+
+
+def lf_fields_seeds(f, out: np.ndarray):
+    _check(load().lf_fields_seeds(f, out.ctypes.data))
+
+
+def lf_step(f, n_steps: int):
+    _check(load().lf_step(f, n_steps))
+
+
+def lf_sync(f):
+    _check(load().lf_sync(f))
+
+
+def lf_fields_export(f, rowptr=None, col=None, val=None):
+    nnz = C.c_int64()
+    pr, d = _ptr(rowptr)
+    pc, _ = _ptr(col)
+    pv, _ = _ptr(val)
+    _check(load().lf_fields_export(f, C.byref(nnz), pr, pc, pv, d))
+    return nnz.value
+
+
+def lf_fields_import(f, rowptr, col, val):
+    pr, d = _ptr(rowptr)
+    pc, _ = _ptr(col)
+    pv, _ = _ptr(val)
+    _check(load().lf_fields_import(f, int(col.shape[0]), pr, pc, pv, d))
+
+
+def lf_labels(f, out):
+    p, d = _ptr(out)
+    _check(load().lf_labels(f, p, d))
+
+
+def lf_lloyd_reseed(f, seeds_out: np.ndarray, status: np.ndarray | None = None):
+    _check(load().lf_lloyd_reseed(f, seeds_out.ctypes.data,
+                                  status.ctypes.data if status is not None else None))
+
+
+def lf_dual_mesh(f, tau: float, tris=None, adj_rowptr=None, adj_col=None):
+    n_tri = C.c_int64()
+    nnz = C.c_int64()
+    _check(load().lf_dual_mesh(f, tau, C.byref(n_tri), _ptr(tris)[0], C.byref(nnz),
+                               _ptr(adj_rowptr)[0], _ptr(adj_col)[0]))
+    return n_tri.value, nnz.value
+
+
+def lf_dual_matrix(f, which: int, rowptr=None, col=None):
+    nnz = C.c_int64()
+    _check(load().lf_dual_matrix(f, which, C.byref(nnz), _ptr(rowptr)[0], _ptr(col)[0]))
+    return nnz.value
+
+
+def lf_dual_candidates(f, pairs=None, state=None):
+    n = C.c_int64()
+    _check(load().lf_dual_candidates(f, C.byref(n), _ptr(pairs)[0], _ptr(state)[0]))
+    return n.value
+
+
+def lf_stats(f):
+    v = [C.c_int64() for _ in range(5)]
+    _check(load().lf_stats(f, *[C.byref(x) for x in v]))
+    return dict(zip(["nnz", "skeleton_total", "steps", "empty_columns", "grow_events"],
+                    [x.value for x in v]))
+
+
+def lf_traffic(f):
+    a, b = C.c_int64(), C.c_int64()
+    _check(load().lf_traffic(f, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def lf_step_timing(f, enable: int):
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(load().lf_step_timing(f, enable, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+# ---- owners ----------------------------------------------------------------------
+
+class Context:
+    """A library context on one GPU, running on a torch stream (default: the
+    current stream of `device`)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.torch_stream = stream
+        self.device = device
+        self.h = lf_ctx_create(device, C.c_void_p(stream.cuda_stream))
+
+    def close(self):
+        if self.h:
+            lf_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    def __init__(self, ctx: Context, V, F, op: int):
+        self.ctx = ctx
+        self.n_v = int(V.shape[0])
+        self.n_f = int(F.shape[0])
+        self.h = lf_mesh_create(ctx.h, V, F, op)
+
+    def operator(self):
+        """Operator with diagonal as host CSR (rowptr, col, val float32)."""
+        nnz = lf_mesh_operator(self.h)
+        rp = np.zeros(self.n_v + 1, np.int32)
+        col = np.zeros(nnz, np.int32)
+        val = np.zeros(nnz, np.float32)
+        lf_mesh_operator(self.h, rp, col, val)
+        return rp, col, val
+
+    def close(self):
+        if self.h:
+            lf_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fields:
+    def __init__(self, mesh: Mesh, seeds, params: lf_params | None = None):
+        self.mesh = mesh
+        self.n_s = int(np.asarray(seeds).size)
+        self.h = lf_fields_create(mesh.h, seeds, params)
+
+    def step(self, n: int = 1):
+        lf_step(self.h, n)
+
+    def reset(self, seeds):
+        lf_fields_reset(self.h, seeds)
+
+    def seeds(self):
+        out = np.zeros(self.n_s, np.int32)
+        lf_fields_seeds(self.h, out)
+        return out
+
+    def export(self):
+        """Host CSR (rowptr int32, col int32, val float32)."""
+        nnz = lf_fields_export(self.h)
+        rp = np.zeros(self.mesh.n_v + 1, np.int32)
+        col = np.zeros(nnz, np.int32)
+        val = np.zeros(nnz, np.float32)
+        lf_fields_export(self.h, rp, col, val)
+        return rp, col, val
+
+    def export_device(self):
+        import torch
+        nnz = lf_fields_export(self.h)
+        dev = torch.device("cuda", self.mesh.ctx.device)
+        rp = torch.empty(self.mesh.n_v + 1, dtype=torch.int32, device=dev)
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
+        val = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)[:nnz]
+        lf_fields_export(self.h, rp, col, val)
+        return rp, col, val
+
+    def load(self, rowptr, col, val):
+        lf_fields_import(self.h, np.ascontiguousarray(rowptr, np.int32) if isinstance(rowptr, np.ndarray) else rowptr,
+                         np.ascontiguousarray(col, np.int32) if isinstance(col, np.ndarray) else col,
+                         np.ascontiguousarray(val, np.float32) if isinstance(val, np.ndarray) else val)
+
+    def labels(self):
+        out = np.zeros(self.mesh.n_v, np.int32)
+        lf_labels(self.h, out)
+        return out
+
+    def lloyd_reseed(self):
+        seeds = np.zeros(self.n_s, np.int32)
+        status = np.zeros(self.n_s, np.int32)
+        lf_lloyd_reseed(self.h, seeds, status)
+        return seeds, status
+
+    def dual_mesh(self, tau: float = 0.25):
+        n_tri, nnz = lf_dual_mesh(self.h, tau)
+        tris = np.zeros((n_tri, 3), np.int32)
+        rp = np.zeros(self.n_s + 1, np.int32)
+        col = np.zeros(nnz, np.int32)
+        lf_dual_mesh(self.h, tau, tris, rp, col)
+        return tris, (rp, col)
+
+    def dual_matrix(self, which: int):
+        nnz = lf_dual_matrix(self.h, which)
+        rp = np.zeros(self.n_s + 1, np.int32)
+        col = np.zeros(nnz, np.int32)
+        lf_dual_matrix(self.h, which, rp, col)
+        return rp, col
+
+    def dual_candidates(self):
+        n = lf_dual_candidates(self.h)
+        pairs = np.zeros((n, 2), np.int32)
+        state = np.zeros(n, np.int32)
+        lf_dual_candidates(self.h, pairs, state)
+        return pairs, state
+
+    def stats(self):
+        return lf_stats(self.h)
+
+    def timing(self, enable: int = -1):
+        return lf_step_timing(self.h, enable)
+
+    def traffic(self):
+        return lf_traffic(self.h)
+
+    def close(self):
+        if self.h:
+            lf_fields_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

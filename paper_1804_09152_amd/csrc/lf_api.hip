@@ -1,0 +1,587 @@
+// C ABI of the layered-field library: contexts, meshes, fields, stepping
+// with device-side capacity checks, import / export, labels, statistics.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lf_internal.h"
+
+namespace lf {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+lf_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+  return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? LF_ENOMEM : LF_EDEVICE;
+}
+
+static lf_status fail(lf_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+// device buffer released at scope exit unless released
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
+  hipError_t alloc(int64_t n) { return dalloc(&p, n); }
+  T* release() {
+    T* q = p;
+    p = nullptr;
+    return q;
+  }
+};
+
+static StepArgs make_args(lf_fields* f, int parity) {
+  StepArgs a;
+  lf_mesh* m = f->mesh;
+  a.lptr = m->lptr;
+  a.lent = m->lent;
+  a.ldiag = m->ldiag;
+  a.uptr_in = f->uptr[parity];
+  a.uent_in = f->uent[parity];
+  a.uptr_out = f->uptr[1 - parity];
+  a.uent_out = f->uent[1 - parity];
+  a.n_v = m->n_v;
+  a.n_tiles = f->n_tiles;
+  a.cap = f->cap;
+  a.c.a = (float)f->P.a;
+  a.c.w = (float)f->P.w;
+  a.c.e = (float)f->P.e;
+  a.c.mu = (float)f->P.mu;
+  a.c.dt = (float)f->P.dt;
+  a.c.theta = (float)f->P.theta;
+  a.c.base_mode = f->P.base_mode;
+  a.c.n_s = f->n_s;
+  a.status = f->status[parity];
+  a.status_next = f->status[1 - parity];
+  a.ticket = f->tickets + parity;
+  a.ticket_next = f->tickets + (1 - parity);
+  a.flags = f->flags;
+  return a;
+}
+
+static lf_status clear_step_state(lf_fields* f) {
+  hipStream_t s = f->mesh->ctx->stream;
+  for (int k = 0; k < 2; ++k) LF_HIP(launch_fill_u64(f->status[k], f->n_tiles, 0ull, s));
+  LF_HIP(launch_fill_i32((int32_t*)f->tickets, 2, 0, s));
+  LF_HIP(launch_reset_flags(f->flags, s, false));
+  return LF_OK;
+}
+
+static lf_status current_nnz(lf_fields* f, int64_t* nnz) {
+  int32_t v = 0;
+  hipStream_t s = f->mesh->ctx->stream;
+  LF_HIP(hipMemcpyAsync(&v, f->uptr[f->cur] + f->mesh->n_v, sizeof(int32_t),
+                        hipMemcpyDeviceToHost, s));
+  LF_HIP(hipStreamSynchronize(s));
+  *nnz = v;
+  return LF_OK;
+}
+
+// grows both field buffers to at least `need` entries (plus 20%), keeping
+// the current state
+static lf_status grow(lf_fields* f, int64_t need) {
+  const int64_t lim = (1ll << 31) - 1;
+  int64_t ncap = std::max(need + need / 5, f->cap + f->cap / 5) + 1024;
+  if (need > lim) return fail(LF_ECAPACITY, "field storage would exceed 2^31 entries");
+  ncap = std::min(ncap, lim);
+  int64_t nnz = 0;
+  lf_status st = current_nnz(f, &nnz);
+  if (st) return st;
+  hipStream_t s = f->mesh->ctx->stream;
+  DevBuf<Ent> a, b;
+  LF_HIP(a.alloc(ncap));
+  LF_HIP(b.alloc(ncap));
+  if (nnz > 0)
+    LF_HIP(hipMemcpyAsync(a.p, f->uent[f->cur], sizeof(Ent) * nnz, hipMemcpyDeviceToDevice, s));
+  LF_HIP(hipStreamSynchronize(s));
+  hipFree(f->uent[0]);
+  hipFree(f->uent[1]);
+  f->uent[f->cur] = a.release();
+  f->uent[1 - f->cur] = b.release();
+  f->cap = ncap;
+  f->grow_events++;
+  return clear_step_state(f);
+}
+
+}  // namespace lf
+
+using namespace lf;
+
+extern "C" {
+
+const char* lf_last_error(void) { return g_err.c_str(); }
+
+void lf_params_default(lf_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->w = 0.2;
+  p->a = 0.04;
+  p->e = 1.0;
+  p->mu = 0.1;
+  p->dt = 5.0;
+  p->theta = 1e-3;
+  p->tau = 0.25;
+  p->base_mode = 0;
+  p->capacity_hint = 0;
+}
+
+lf_status lf_ctx_create(int32_t device, void* hip_stream, lf_ctx** out) {
+  if (!out) return fail(LF_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  LF_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(LF_EINVAL, "no such device");
+  LF_HIP(hipSetDevice(device));
+  lf_ctx* c = new lf_ctx();
+  c->device = device;
+  c->own_stream = hip_stream == nullptr;
+  if (c->own_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "hipStreamCreate");
+    }
+  } else {
+    c->stream = (hipStream_t)hip_stream;
+  }
+  *out = c;
+  return LF_OK;
+}
+
+lf_status lf_ctx_destroy(lf_ctx* c) {
+  if (!c) return LF_OK;
+  hipSetDevice(c->device);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+  return LF_OK;
+}
+
+lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* F, int32_t n_f,
+                         int32_t op, lf_mesh** out) {
+  if (!ctx || !V || !F || !out) return fail(LF_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n_v < 3 || n_v >= kMaxVerts || n_f < 1 || (int64_t)n_f > 4ll * n_v)
+    return fail(LF_EINVAL, "mesh size out of range (3 <= n_v < 2^25, 1 <= n_f <= 4 n_v)");
+  if (op != LF_OP_GRAPH && op != LF_OP_COTAN) return fail(LF_EINVAL, "unknown operator");
+  for (int64_t f = 0; f < n_f; ++f) {
+    const int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= n_v || b >= n_v || c >= n_v)
+      return fail(LF_EINVAL, "face " + std::to_string(f) + " has a vertex id out of range");
+    if (a == b || b == c || a == c)
+      return fail(LF_EINVAL, "face " + std::to_string(f) + " repeats a vertex");
+  }
+  LF_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  DevBuf<double> dV;
+  DevBuf<int32_t> dF;
+  LF_HIP(dV.alloc(3ll * n_v));
+  LF_HIP(dF.alloc(3ll * n_f));
+  LF_HIP(hipMemcpyAsync(dV.p, V, sizeof(double) * 3 * n_v, hipMemcpyHostToDevice, s));
+  LF_HIP(hipMemcpyAsync(dF.p, F, sizeof(int32_t) * 3 * n_f, hipMemcpyHostToDevice, s));
+  int32_t* lptr = nullptr;
+  Ent* lent = nullptr;
+  float* ldiag = nullptr;
+  int64_t nnz = 0;
+  int bad = 0;
+  LF_HIP(build_operator(dV.p, dF.p, n_v, n_f, op, &lptr, &lent, &ldiag, &nnz, &bad, s));
+  if (bad) return fail(LF_EINVAL, "zero-area face: cotangent weights undefined");
+  lf_mesh* m = new lf_mesh();
+  m->ctx = ctx;
+  m->n_v = n_v;
+  m->n_f = n_f;
+  m->op = op;
+  m->V = dV.release();
+  m->F = dF.release();
+  m->lptr = lptr;
+  m->lent = lent;
+  m->ldiag = ldiag;
+  m->nnz_off = nnz;
+  m->Vh.assign(V, V + 3ll * n_v);
+  m->Fh.assign(F, F + 3ll * n_f);
+  *out = m;
+  return LF_OK;
+}
+
+lf_status lf_mesh_destroy(lf_mesh* m) {
+  if (!m) return LF_OK;
+  hipSetDevice(m->ctx->device);
+  hipFree(m->V);
+  hipFree(m->F);
+  hipFree(m->lptr);
+  hipFree(m->lent);
+  hipFree(m->ldiag);
+  delete m;
+  return LF_OK;
+}
+
+lf_status lf_mesh_operator(lf_mesh* m, int64_t* nnz, int32_t* rowptr, int32_t* col, float* val,
+                           int32_t is_dev) {
+  if (!m || !nnz) return fail(LF_EINVAL, "NULL argument");
+  const int64_t total = m->nnz_off + m->n_v;
+  *nnz = total;
+  if (!rowptr && !col && !val) return LF_OK;
+  if (!rowptr || !col || !val) return fail(LF_EINVAL, "rowptr, col and val must all be given");
+  LF_HIP(hipSetDevice(m->ctx->device));
+  hipStream_t s = m->ctx->stream;
+  if (is_dev) {
+    LF_HIP(launch_operator_export(m->lptr, m->lent, m->ldiag, m->n_v, rowptr, col, val, s));
+    LF_HIP(hipStreamSynchronize(s));
+    return LF_OK;
+  }
+  DevBuf<int32_t> dp, dc;
+  DevBuf<float> dv;
+  LF_HIP(dp.alloc(m->n_v + 1));
+  LF_HIP(dc.alloc(total));
+  LF_HIP(dv.alloc(total));
+  LF_HIP(launch_operator_export(m->lptr, m->lent, m->ldiag, m->n_v, dp.p, dc.p, dv.p, s));
+  LF_HIP(hipMemcpyAsync(rowptr, dp.p, sizeof(int32_t) * (m->n_v + 1), hipMemcpyDeviceToHost, s));
+  LF_HIP(hipMemcpyAsync(col, dc.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
+  LF_HIP(hipMemcpyAsync(val, dv.p, sizeof(float) * total, hipMemcpyDeviceToHost, s));
+  LF_HIP(hipStreamSynchronize(s));
+  return LF_OK;
+}
+
+static lf_status check_seeds(const int32_t* seeds, int32_t n_s, int32_t n_v) {
+  if (n_s < 1 || n_s >= n_v) return fail(LF_EINVAL, "need 1 <= n_s < n_v seeds");
+  if (!seeds) return fail(LF_EINVAL, "seeds is NULL");
+  std::vector<char> used(n_v, 0);
+  for (int32_t k = 0; k < n_s; ++k) {
+    const int32_t v = seeds[k];
+    if (v < 0 || v >= n_v) return fail(LF_EINVAL, "seed " + std::to_string(k) + " out of range");
+    if (used[v]) return fail(LF_EINVAL, "seed vertex " + std::to_string(v) + " repeated");
+    used[v] = 1;
+  }
+  return LF_OK;
+}
+
+static lf_status init_fields(lf_fields* f) {
+  hipStream_t s = f->mesh->ctx->stream;
+  const int32_t n_v = f->mesh->n_v;
+  LF_HIP(hipMemcpyAsync(f->d_seeds, f->seeds.data(), sizeof(int32_t) * f->n_s,
+                        hipMemcpyHostToDevice, s));
+  LF_HIP(launch_fill_i32(f->owner, n_v, f->n_s, s));
+  LF_HIP(launch_scatter_owner(f->d_seeds, f->n_s, f->owner, s));
+  f->cur = 0;
+  LF_HIP(launch_init_fields(f->owner, n_v, f->uptr[0], f->uent[0], s));
+  lf_status st = clear_step_state(f);
+  if (st) return st;
+  LF_HIP(hipStreamSynchronize(s));
+  return LF_OK;
+}
+
+lf_status lf_fields_destroy(lf_fields* f) {
+  if (!f) return LF_OK;
+  hipSetDevice(f->mesh->ctx->device);
+  for (int k = 0; k < 2; ++k) {
+    hipFree(f->uptr[k]);
+    hipFree(f->uent[k]);
+    hipFree(f->status[k]);
+  }
+  hipFree(f->d_seeds);
+  hipFree(f->owner);
+  hipFree(f->tickets);
+  hipFree(f->flags);
+  if (f->flags_host) hipHostFree(f->flags_host);
+  for (auto e : f->ev0) hipEventDestroy(e);
+  for (auto e : f->ev1) hipEventDestroy(e);
+  dual_release(f);
+  delete f;
+  return LF_OK;
+}
+
+lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const lf_params* P,
+                           lf_fields** out) {
+  if (!m || !out) return fail(LF_EINVAL, "NULL argument");
+  *out = nullptr;
+  lf_status st = check_seeds(seeds, n_s, m->n_v);
+  if (st) return st;
+  lf_params prm;
+  if (P) prm = *P;
+  else lf_params_default(&prm);
+  if (!(prm.dt > 0) || !(prm.mu >= 0) || !(prm.theta >= 0 && prm.theta < 1) ||
+      (prm.base_mode != 0 && prm.base_mode != 1))
+    return fail(LF_EINVAL, "invalid parameters");
+  LF_HIP(hipSetDevice(m->ctx->device));
+  lf_fields* f = new lf_fields();
+  f->mesh = m;
+  f->n_s = n_s;
+  f->P = prm;
+  f->seeds.assign(seeds, seeds + n_s);
+  f->n_tiles = (m->n_v + kBlock - 1) / kBlock;
+  int64_t cap = prm.capacity_hint > 0 ? prm.capacity_hint : 3ll * m->n_v;
+  cap = std::max<int64_t>(cap, m->n_v);
+  f->cap = std::min<int64_t>(cap, (1ll << 31) - 1);
+  hipError_t e = hipSuccess;
+#define ALLOC(x, n)                          \
+  if (e == hipSuccess) e = dalloc(&(x), (n));
+  ALLOC(f->d_seeds, n_s);
+  ALLOC(f->owner, m->n_v);
+  for (int k = 0; k < 2; ++k) {
+    ALLOC(f->uptr[k], m->n_v + 1);
+    ALLOC(f->uent[k], f->cap);
+    ALLOC(f->status[k], f->n_tiles);
+  }
+  ALLOC(f->tickets, 2);
+  ALLOC(f->flags, 1);
+#undef ALLOC
+  if (e == hipSuccess) e = hipHostMalloc((void**)&f->flags_host, sizeof(StepFlags), 0);
+  if (e != hipSuccess) {
+    lf_fields_destroy(f);
+    return hip_fail(e, "allocating field state");
+  }
+  e = launch_reset_flags(f->flags, m->ctx->stream, true);
+  if (e != hipSuccess) {
+    lf_fields_destroy(f);
+    return hip_fail(e, "reset flags");
+  }
+  st = init_fields(f);
+  if (st) {
+    lf_fields_destroy(f);
+    return st;
+  }
+  *out = f;
+  return LF_OK;
+}
+
+lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds) {
+  if (!f) return fail(LF_EINVAL, "NULL argument");
+  lf_status st = check_seeds(seeds, f->n_s, f->mesh->n_v);
+  if (st) return st;
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  f->seeds.assign(seeds, seeds + f->n_s);
+  return init_fields(f);
+}
+
+lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds) {
+  if (!f || !seeds) return fail(LF_EINVAL, "NULL argument");
+  memcpy(seeds, f->seeds.data(), sizeof(int32_t) * f->n_s);
+  return LF_OK;
+}
+
+static hipEvent_t pool_event(std::vector<hipEvent_t>& pool, size_t k) {
+  while (pool.size() <= k) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool.push_back(e);
+  }
+  return pool[k];
+}
+
+lf_status lf_step(lf_fields* f, int32_t n) {
+  if (!f || n < 0) return fail(LF_EINVAL, "invalid argument");
+  if (n == 0) return LF_OK;
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  hipStream_t s = f->mesh->ctx->stream;
+  int64_t remaining = n;
+  int grows = 0;
+  while (remaining > 0) {
+    LF_HIP(launch_reset_flags(f->flags, s, false));
+    size_t used = 0;
+    for (int64_t k = 0; k < remaining; ++k) {
+      StepArgs a = make_args(f, (int)((f->cur + k) & 1));
+      hipEvent_t t0 = nullptr, t1 = nullptr;
+      if (f->timing) {
+        t0 = pool_event(f->ev0, used);
+        t1 = pool_event(f->ev1, used);
+        if (t0 && t1) ++used;
+      }
+      LF_HIP(launch_step(a, s, t0, t1));
+    }
+    LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipStreamSynchronize(s));
+    for (size_t k = 0; k < used; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, f->ev0[k], f->ev1[k]) == hipSuccess) {
+        f->timed_ms += ms;
+        f->timed_launches++;
+      }
+    }
+    const StepFlags fl = *f->flags_host;
+    const int64_t ok = (int64_t)fl.steps_ok;
+    f->cur = (int)((f->cur + ok) & 1);
+    f->steps += ok;
+    remaining -= ok;
+    if (fl.poisoned & 2u) {
+      clear_step_state(f);
+      return fail(LF_ECAPACITY, "a vertex touches more than 64 layers");
+    }
+    if (fl.poisoned & 4u) {
+      clear_step_state(f);
+      return fail(LF_EDEVICE, "step look-back did not complete");
+    }
+    if (fl.poisoned & 1u) {
+      if (++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
+      lf_status st = grow(f, (int64_t)fl.need);
+      if (st) return st;
+    } else if (remaining > 0) {
+      return fail(LF_EDEVICE, "steps reported complete but some are missing");
+    }
+  }
+  return LF_OK;
+}
+
+lf_status lf_sync(lf_fields* f) {
+  if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_HIP(hipStreamSynchronize(f->mesh->ctx->stream));
+  return LF_OK;
+}
+
+lf_status lf_fields_export(lf_fields* f, int64_t* nnz, int32_t* rowptr, int32_t* col, float* val,
+                           int32_t is_dev) {
+  if (!f || !nnz) return fail(LF_EINVAL, "NULL argument");
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  lf_status st = current_nnz(f, nnz);
+  if (st) return st;
+  if (!rowptr && !col && !val) return LF_OK;
+  if (!rowptr || !col || !val) return fail(LF_EINVAL, "rowptr, col and val must all be given");
+  hipStream_t s = f->mesh->ctx->stream;
+  const int32_t n_v = f->mesh->n_v;
+  if (is_dev) {
+    LF_HIP(hipMemcpyAsync(rowptr, f->uptr[f->cur], sizeof(int32_t) * (n_v + 1),
+                          hipMemcpyDeviceToDevice, s));
+    LF_HIP(launch_split(f->uent[f->cur], *nnz, col, val, s));
+  } else {
+    DevBuf<int32_t> dc;
+    DevBuf<float> dv;
+    LF_HIP(dc.alloc(*nnz));
+    LF_HIP(dv.alloc(*nnz));
+    LF_HIP(launch_split(f->uent[f->cur], *nnz, dc.p, dv.p, s));
+    LF_HIP(hipMemcpyAsync(rowptr, f->uptr[f->cur], sizeof(int32_t) * (n_v + 1),
+                          hipMemcpyDeviceToHost, s));
+    if (*nnz > 0) {
+      LF_HIP(hipMemcpyAsync(col, dc.p, sizeof(int32_t) * *nnz, hipMemcpyDeviceToHost, s));
+      LF_HIP(hipMemcpyAsync(val, dv.p, sizeof(float) * *nnz, hipMemcpyDeviceToHost, s));
+    }
+    LF_HIP(hipStreamSynchronize(s));
+    return LF_OK;
+  }
+  LF_HIP(hipStreamSynchronize(s));
+  return LF_OK;
+}
+
+lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                           const float* val, int32_t is_dev) {
+  if (!f || !rowptr || (nnz > 0 && (!col || !val)) || nnz < 0)
+    return fail(LF_EINVAL, "invalid argument");
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  hipStream_t s = f->mesh->ctx->stream;
+  const int32_t n_v = f->mesh->n_v;
+  if (nnz > f->cap) {
+    lf_status st = grow(f, nnz);
+    if (st) return st;
+  }
+  DevBuf<int32_t> dp, dc, bad;
+  DevBuf<float> dv;
+  const int32_t* p = rowptr;
+  const int32_t* c = col;
+  const float* v = val;
+  if (!is_dev) {
+    if (rowptr[n_v] != nnz || rowptr[0] != 0) return fail(LF_EINVAL, "rowptr does not match nnz");
+    for (int32_t i = 0; i < n_v; ++i)
+      if (rowptr[i + 1] < rowptr[i]) return fail(LF_EINVAL, "rowptr is not monotone");
+    LF_HIP(dp.alloc(n_v + 1));
+    LF_HIP(dc.alloc(nnz));
+    LF_HIP(dv.alloc(nnz));
+    LF_HIP(hipMemcpyAsync(dp.p, rowptr, sizeof(int32_t) * (n_v + 1), hipMemcpyHostToDevice, s));
+    if (nnz > 0) {
+      LF_HIP(hipMemcpyAsync(dc.p, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+      LF_HIP(hipMemcpyAsync(dv.p, val, sizeof(float) * nnz, hipMemcpyHostToDevice, s));
+    }
+    p = dp.p;
+    c = dc.p;
+    v = dv.p;
+  } else {
+    int32_t last = -1;
+    LF_HIP(hipMemcpyAsync(&last, rowptr + n_v, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipStreamSynchronize(s));
+    if (last != nnz) return fail(LF_EINVAL, "rowptr does not match nnz");
+  }
+  LF_HIP(bad.alloc(1));
+  LF_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+  const int tgt = 1 - f->cur;
+  LF_HIP(launch_join_check(c, v, p, n_v, f->n_s + 1, nnz, f->uent[tgt], bad.p, s));
+  LF_HIP(hipMemcpyAsync(f->uptr[tgt], p, sizeof(int32_t) * (n_v + 1), hipMemcpyDeviceToDevice, s));
+  int32_t hb = 0;
+  LF_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LF_HIP(hipStreamSynchronize(s));
+  if (hb) return fail(LF_EINVAL, "imported fields are not canonical (code " + std::to_string(hb) + ")");
+  f->cur = tgt;
+  lf_status st = clear_step_state(f);
+  if (st) return st;
+  LF_HIP(hipStreamSynchronize(s));
+  return LF_OK;
+}
+
+lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_dev) {
+  if (!f || !labels) return fail(LF_EINVAL, "NULL argument");
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  hipStream_t s = f->mesh->ctx->stream;
+  const int32_t n_v = f->mesh->n_v;
+  if (is_dev) {
+    LF_HIP(launch_labels(f->uptr[f->cur], f->uent[f->cur], n_v, f->n_s, labels, s));
+  } else {
+    DevBuf<int32_t> d;
+    LF_HIP(d.alloc(n_v));
+    LF_HIP(launch_labels(f->uptr[f->cur], f->uent[f->cur], n_v, f->n_s, d.p, s));
+    LF_HIP(hipMemcpyAsync(labels, d.p, sizeof(int32_t) * n_v, hipMemcpyDeviceToHost, s));
+    LF_HIP(hipStreamSynchronize(s));
+    return LF_OK;
+  }
+  LF_HIP(hipStreamSynchronize(s));
+  return LF_OK;
+}
+
+lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skel, int64_t* steps, int64_t* empty,
+                   int64_t* grows) {
+  if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  hipStream_t s = f->mesh->ctx->stream;
+  LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
+  LF_HIP(hipStreamSynchronize(s));
+  if (nnz_u) {
+    lf_status st = current_nnz(f, nnz_u);
+    if (st) return st;
+  }
+  if (skel) *skel = (int64_t)f->flags_host->skel;
+  if (steps) *steps = f->steps;
+  if (empty) *empty = (int64_t)f->flags_host->events;
+  if (grows) *grows = f->grow_events;
+  return LF_OK;
+}
+
+lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out) {
+  if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  hipStream_t s = f->mesh->ctx->stream;
+  LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
+  LF_HIP(hipStreamSynchronize(s));
+  if (entries_in) *entries_in = (int64_t)f->flags_host->in_total;
+  if (entries_out) *entries_out = (int64_t)f->flags_host->out_total;
+  return LF_OK;
+}
+
+lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t* launches) {
+  if (!f) return fail(LF_EINVAL, "NULL argument");
+  if (total_ms) *total_ms = f->timed_ms;
+  if (launches) *launches = f->timed_launches;
+  if (enable >= 0) {
+    if (enable && !f->timing) {
+      f->timed_ms = 0.0;
+      f->timed_launches = 0;
+    }
+    f->timing = enable != 0;
+  }
+  return LF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,385 @@
+// Setup-time kernels: mesh operator, field initialisation, scans, import /
+// export of the field matrix, labels.
+#include "lf_internal.h"
+
+namespace lf {
+
+namespace {
+
+constexpr int kT = 256;
+
+inline unsigned blocks_for(int64_t n, int per = kT) {
+  int64_t b = (n + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ---- fills -----------------------------------------------------------------
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---- initialisation (Algorithm 1, first line) --------------------------------
+
+__global__ void k_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owner) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_s) owner[seeds[k]] = k;
+}
+
+// owner[v] = seed index of v, or n_s (the base layer) for unseeded vertices
+__global__ void k_init_fields(const int32_t* owner, int32_t n_v, int32_t* uptr, Ent* uent) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_v) {
+    uptr[i] = i;
+    uent[i] = Ent{owner[i], 1.0f};
+  }
+  if (i == 0) uptr[n_v] = n_v;
+}
+
+// ---- exclusive scan -------------------------------------------------------------
+// three passes: per-block sums, one block scanning the block sums, per-block
+// scan with its offset.  Blocks cover kScanItems elements.
+
+constexpr int kScanPer = 4;
+constexpr int kScanItems = kT * kScanPer;
+
+__device__ __forceinline__ long long block_incl_scan(long long v, long long* sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  if (lane == 63) sh[wid] = v;
+  __syncthreads();
+  long long off = 0;
+  for (int w = 0; w < wid; ++w) off += sh[w];
+  __syncthreads();
+  return v + off;
+}
+
+__global__ __launch_bounds__(kT) void k_scan_sums(const int32_t* in, int64_t n, long long* sums) {
+  __shared__ long long sh[kT / 64];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanItems;
+  long long v = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int64_t j = b0 + (int64_t)threadIdx.x * kScanPer + k;
+    if (j < n) v += in[j];
+  }
+  const long long incl = block_incl_scan(v, sh);
+  if (threadIdx.x == kT - 1) sums[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(kT) void k_scan_sums_scan(long long* sums, int64_t nb) {
+  __shared__ long long sh[kT / 64];
+  __shared__ long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nb; c0 += kT) {
+    const int64_t j = c0 + threadIdx.x;
+    const long long v = j < nb ? sums[j] : 0;
+    const long long incl = block_incl_scan(v, sh);
+    const long long base = carry;
+    if (j < nb) sums[j] = base + incl - v;  // exclusive
+    __syncthreads();
+    if (threadIdx.x == kT - 1) carry = base + incl;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_scan_apply(const int32_t* in, int64_t n,
+                                                  const long long* offs, int32_t* out) {
+  __shared__ long long sh[kT / 64];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanItems;
+  int32_t vals[kScanPer];
+  long long v = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int64_t j = b0 + (int64_t)threadIdx.x * kScanPer + k;
+    vals[k] = j < n ? in[j] : 0;
+    v += vals[k];
+  }
+  const long long incl = block_incl_scan(v, sh);
+  long long run = offs[blockIdx.x] + incl - v;
+  for (int k = 0; k < kScanPer; ++k) {
+    const int64_t j = b0 + (int64_t)threadIdx.x * kScanPer + k;
+    if (j < n) out[j] = (int32_t)run;
+    run += vals[k];
+    if (j == n - 1) out[n] = (int32_t)run;
+  }
+}
+
+// ---- operator (Section 3.2, Laplacian computation) ------------------------------
+
+struct HalfEdge {
+  int32_t col;
+  int32_t face;
+  double w;
+};
+
+__global__ void k_face_count(const int32_t* F, int32_t n_f, int32_t* cnt) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n_f) return;
+  for (int k = 0; k < 3; ++k) atomicAdd(&cnt[F[3 * (int64_t)f + k]], 2);
+}
+
+// for every corner o of a face, the opposite edge (p, q) gets the corner's
+// half cotangent (cotangent operator) or 1 (graph operator), both ways
+__global__ void k_face_fill(const double* V, const int32_t* F, int32_t n_f, int op,
+                            int32_t* cursor, HalfEdge* he, int32_t* bad) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n_f) return;
+  const int32_t* c = F + 3 * (int64_t)f;
+  for (int k = 0; k < 3; ++k) {
+    const int32_t o = c[k], p = c[(k + 1) % 3], q = c[(k + 2) % 3];
+    double w = 1.0;
+    if (op == 1) {
+      const double ux = V[3 * (int64_t)p] - V[3 * (int64_t)o];
+      const double uy = V[3 * (int64_t)p + 1] - V[3 * (int64_t)o + 1];
+      const double uz = V[3 * (int64_t)p + 2] - V[3 * (int64_t)o + 2];
+      const double vx = V[3 * (int64_t)q] - V[3 * (int64_t)o];
+      const double vy = V[3 * (int64_t)q + 1] - V[3 * (int64_t)o + 1];
+      const double vz = V[3 * (int64_t)q + 2] - V[3 * (int64_t)o + 2];
+      const double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+      const double s = sqrt(cx * cx + cy * cy + cz * cz);
+      if (s == 0.0) { atomicOr(bad, 1); return; }
+      w = 0.5 * (ux * vx + uy * vy + uz * vz) / s;
+    }
+    int32_t a = atomicAdd(&cursor[p], 1);
+    he[a] = HalfEdge{q, f, w};
+    a = atomicAdd(&cursor[q], 1);
+    he[a] = HalfEdge{p, f, w};
+  }
+}
+
+// per row: order the half-edges by (neighbour, face) so that the sum of the
+// contributions of one edge has a fixed order, merge, and take the diagonal
+// as minus the sum of the row (float64, in neighbour order)
+__global__ void k_row_merge(const int32_t* tptr, HalfEdge* he, int32_t n_v, int op,
+                            int32_t* ucnt, float* ldiag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  const int32_t a = tptr[i], b = tptr[i + 1];
+  for (int32_t x = a + 1; x < b; ++x) {
+    const HalfEdge h = he[x];
+    int32_t y = x - 1;
+    while (y >= a && (he[y].col > h.col || (he[y].col == h.col && he[y].face > h.face))) {
+      he[y + 1] = he[y];
+      --y;
+    }
+    he[y + 1] = h;
+  }
+  int32_t m = 0;
+  double diag = 0.0;
+  for (int32_t x = a; x < b;) {
+    int32_t y = x;
+    double s = 0.0;
+    while (y < b && he[y].col == he[x].col) { s += he[y].w; ++y; }
+    if (op == 0) s = 1.0;
+    he[a + m] = HalfEdge{he[x].col, 0, s};
+    diag -= s;
+    ++m;
+    x = y;
+  }
+  ucnt[i] = m;
+  ldiag[i] = (float)diag;
+}
+
+__global__ void k_row_emit(const int32_t* tptr, const HalfEdge* he, const int32_t* lptr,
+                           int32_t n_v, Ent* lent) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  const int32_t a = tptr[i], o = lptr[i], m = lptr[i + 1] - lptr[i];
+  for (int32_t k = 0; k < m; ++k) lent[o + k] = Ent{he[a + k].col, (float)he[a + k].w};
+}
+
+// operator with the diagonal in its sorted place
+__global__ void k_operator_export(const int32_t* lptr, const Ent* lent, const float* ldiag,
+                                  int32_t n_v, int32_t* rowptr, int32_t* col, float* val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  int32_t o = lptr[i] + i;
+  rowptr[i] = o;
+  if (i == n_v - 1) rowptr[n_v] = lptr[n_v] + n_v;
+  if (!col) return;
+  bool placed = false;
+  for (int32_t q = lptr[i]; q < lptr[i + 1]; ++q) {
+    if (!placed && lent[q].col > i) {
+      col[o] = i; val[o] = ldiag[i]; ++o; placed = true;
+    }
+    col[o] = lent[q].col; val[o] = lent[q].val; ++o;
+  }
+  if (!placed) { col[o] = i; val[o] = ldiag[i]; }
+}
+
+// ---- field import / export --------------------------------------------------------
+
+__global__ void k_split(const Ent* e, int64_t n, int32_t* col, float* val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) { col[i] = e[i].col; val[i] = e[i].val; }
+}
+
+// checks a caller's CSR for canonical form while packing it; bad != 0 on error
+__global__ void k_join_check(const int32_t* col, const float* val, const int32_t* ptr,
+                             int32_t n_v, int32_t n_r, int64_t nnz, Ent* out, int32_t* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  const int32_t a = ptr[i], b = ptr[i + 1];
+  if (i == 0 && a != 0) atomicOr(bad, 1);
+  if (a < 0 || b < a || (int64_t)b > nnz) { atomicOr(bad, 2); return; }
+  int32_t last = -1;
+  for (int32_t p = a; p < b; ++p) {
+    const int32_t c = col[p];
+    const float v = val[p];
+    if (c <= last || c >= n_r) atomicOr(bad, 4);
+    if (!(v > 0.f && v <= 1.f)) atomicOr(bad, 8);
+    last = c;
+    out[p] = Ent{c, v};
+  }
+}
+
+// ---- labels (sharp visualisation, Figure 10) -------------------------------------
+
+__global__ void k_labels(const int32_t* uptr, const Ent* uent, int32_t n_v, int32_t n_s,
+                         int32_t* labels) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  int32_t best = -1;
+  float bv = 0.f;
+  for (int32_t p = uptr[i]; p < uptr[i + 1]; ++p) {
+    const Ent e = uent[p];
+    if (e.col >= n_s) continue;  // the base layer is no cell
+    if (best < 0 || e.val > bv) { best = e.col; bv = e.val; }
+  }
+  labels[i] = best;
+}
+
+}  // namespace
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n)), dim3(kT), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n)), dim3(kT), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owner,
+                                hipStream_t s) {
+  if (n_s <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_owner, dim3(blocks_for(n_s)), dim3(kT), 0, s, seeds, n_s, owner);
+  return hipGetLastError();
+}
+hipError_t launch_init_fields(const int32_t* owner, int32_t n_v, int32_t* uptr, Ent* uent,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_init_fields, dim3(blocks_for(n_v)), dim3(kT), 0, s, owner, n_v, uptr, uent);
+  return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanItems - 1) / kScanItems + 1; }
+
+hipError_t exclusive_scan(const int32_t* in, int32_t* out, int64_t n, long long* tmp,
+                          hipStream_t s) {
+  if (n <= 0) return hipMemsetAsync(out, 0, sizeof(int32_t), s);
+  const int64_t nb = (n + kScanItems - 1) / kScanItems;
+  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kT), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_sums_scan, dim3(1), dim3(kT), 0, s, tmp, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kT), 0, s, in, n, tmp, out);
+  return hipGetLastError();
+}
+
+hipError_t build_operator(const double* V, const int32_t* F, int32_t n_v, int32_t n_f, int op,
+                          int32_t** lptr_out, Ent** lent_out, float** ldiag_out,
+                          int64_t* nnz_off, int* bad_face, hipStream_t s) {
+  hipError_t e;
+  int32_t *cnt = nullptr, *tptr = nullptr, *cursor = nullptr, *ucnt = nullptr, *lptr = nullptr,
+          *bad = nullptr;
+  long long* tmp = nullptr;
+  HalfEdge* he = nullptr;
+  Ent* lent = nullptr;
+  float* ldiag = nullptr;
+  int32_t total = 0, h_bad = 0;
+  *bad_face = 0;
+#define TRY(x)                   \
+  do {                           \
+    e = (x);                     \
+    if (e != hipSuccess) goto fail; \
+  } while (0)
+  TRY(dalloc(&cnt, n_v));
+  TRY(dalloc(&tptr, n_v + 1));
+  TRY(dalloc(&cursor, n_v + 1));
+  TRY(dalloc(&ucnt, n_v));
+  TRY(dalloc(&lptr, n_v + 1));
+  TRY(dalloc(&bad, 1));
+  TRY(dalloc(&tmp, scan_tmp_elems(n_v)));
+  TRY(dalloc(&ldiag, n_v));
+  TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * n_v, s));
+  TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_face_count, dim3(blocks_for(n_f)), dim3(kT), 0, s, F, n_f, cnt);
+  TRY(hipGetLastError());
+  TRY(exclusive_scan(cnt, tptr, n_v, tmp, s));
+  TRY(hipMemcpyAsync(cursor, tptr, sizeof(int32_t) * (n_v + 1), hipMemcpyDeviceToDevice, s));
+  TRY(hipMemcpyAsync(&total, tptr + n_v, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TRY(hipStreamSynchronize(s));
+  TRY(dalloc(&he, total));
+  hipLaunchKernelGGL(k_face_fill, dim3(blocks_for(n_f)), dim3(kT), 0, s, V, F, n_f, op, cursor,
+                     he, bad);
+  TRY(hipGetLastError());
+  TRY(hipMemcpyAsync(&h_bad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TRY(hipStreamSynchronize(s));
+  if (h_bad) { *bad_face = 1; e = hipSuccess; goto fail; }
+  hipLaunchKernelGGL(k_row_merge, dim3(blocks_for(n_v)), dim3(kT), 0, s, tptr, he, n_v, op, ucnt,
+                     ldiag);
+  TRY(hipGetLastError());
+  TRY(exclusive_scan(ucnt, lptr, n_v, tmp, s));
+  TRY(hipMemcpyAsync(&total, lptr + n_v, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TRY(hipStreamSynchronize(s));
+  TRY(dalloc(&lent, total));
+  hipLaunchKernelGGL(k_row_emit, dim3(blocks_for(n_v)), dim3(kT), 0, s, tptr, he, lptr, n_v, lent);
+  TRY(hipGetLastError());
+  TRY(hipStreamSynchronize(s));
+  hipFree(cnt); hipFree(tptr); hipFree(cursor); hipFree(ucnt); hipFree(bad); hipFree(tmp);
+  hipFree(he);
+  *lptr_out = lptr;
+  *lent_out = lent;
+  *ldiag_out = ldiag;
+  *nnz_off = total;
+  return hipSuccess;
+fail:
+  hipFree(cnt); hipFree(tptr); hipFree(cursor); hipFree(ucnt); hipFree(bad); hipFree(tmp);
+  hipFree(he); hipFree(lptr); hipFree(lent); hipFree(ldiag);
+  return e;
+#undef TRY
+}
+
+hipError_t launch_split(const Ent* e, int64_t n, int32_t* col, float* val, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split, dim3(blocks_for(n)), dim3(kT), 0, s, e, n, col, val);
+  return hipGetLastError();
+}
+hipError_t launch_join_check(const int32_t* col, const float* val, const int32_t* ptr,
+                             int32_t n_v, int32_t n_r, int64_t nnz, Ent* out, int32_t* bad,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_join_check, dim3(blocks_for(n_v)), dim3(kT), 0, s, col, val, ptr, n_v, n_r,
+                     nnz, out, bad);
+  return hipGetLastError();
+}
+hipError_t launch_operator_export(const int32_t* lptr, const Ent* lent, const float* ldiag,
+                                  int32_t n_v, int32_t* rowptr, int32_t* col, float* val,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_operator_export, dim3(blocks_for(n_v)), dim3(kT), 0, s, lptr, lent, ldiag,
+                     n_v, rowptr, col, val);
+  return hipGetLastError();
+}
+hipError_t launch_labels(const int32_t* uptr, const Ent* uent, int32_t n_v, int32_t n_s,
+                         int32_t* labels, hipStream_t s) {
+  hipLaunchKernelGGL(k_labels, dim3(blocks_for(n_v)), dim3(kT), 0, s, uptr, uent, n_v, n_s, labels);
+  return hipGetLastError();
+}
+
+}  // namespace lf

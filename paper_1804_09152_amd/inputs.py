@@ -251,40 +251,38 @@ def serving_jobs(count: int, seed: int = 0, levels=(5, 6, 7, 8, 9)):
 
 
 def synthetic_state(mesh: Mesh, seeds: np.ndarray, rng: np.random.Generator,
-                    band: float = 0.35, base_frac: float = 0.3, n_extra: int = 2):
+                    band: float = 0.35, base_frac: float = 0.3, k: int = 3):
     """A plausible mid-run field matrix U (n_v x (n_s+1), CSR, rows = vertices,
     last column = base layer) for one-step comparisons.
 
     Built only from Euclidean nearest-seed assignment: each vertex takes its
-    nearest seed's column with value 1; vertices on a boundary between two
-    assignments get a two- or three-way soft mixture; a random fraction of
-    cells is still "growing" (their outer rows share weight with the base).
-    Values are positive and every row sums to 1.  Returns (rowptr, col, val).
+    nearest seed's layer with weight 1; up to k-1 further seeds whose distance
+    is within (1 + band) of the nearest get a weight in [0.2, 0.9] (bands and
+    junctions); in a random fraction of the cells (still "growing") half the
+    vertices also keep some base layer.  Rows are normalised to sum 1,
+    columns ascending.  Returns (rowptr int64, col int32, val float64).
     """
     from scipy.spatial import cKDTree
     n_v = mesh.n_v
     n_s = int(seeds.size)
-    tree = cKDTree(mesh.V[seeds])
-    k = min(3, n_s)
-    dist, idx = tree.query(mesh.V, k=k)
-    if k == 1:
-        dist = dist[:, None]
-        idx = idx[:, None]
-    rows = []
+    k = max(1, min(k, n_s))
+    dist, idx = cKDTree(mesh.V[seeds]).query(mesh.V, k=k)
+    dist = np.asarray(dist, dtype=np.float64).reshape(n_v, k)
+    idx = np.asarray(idx, dtype=np.int64).reshape(n_v, k)
+    w = rng.uniform(0.2, 0.9, size=(n_v, k))
+    w[:, 0] = 1.0
+    keep = np.ones((n_v, k), dtype=bool)
+    keep[:, 1:] = (dist[:, 1:] - dist[:, :1]) < band * np.maximum(dist[:, :1], 1e-12)
     growing = rng.random(n_s) < base_frac
-    for i in range(n_v):
-        d0 = dist[i, 0]
-        entries = {int(idx[i, 0]): 1.0}
-        for t in range(1, k):
-            if dist[i, t] - d0 < band * max(d0, 1e-12) and len(entries) <= n_extra:
-                entries[int(idx[i, t])] = float(rng.uniform(0.2, 0.9))
-        c0 = int(idx[i, 0])
-        if growing[c0] and dist[i, 0] > 0 and rng.random() < 0.5:
-            entries[n_s] = float(rng.uniform(0.05, 0.9))
-        s = sum(entries.values())
-        rows.append(sorted((c, v / s) for c, v in entries.items()))
-    rowptr = np.zeros(n_v + 1, dtype=np.int32)
-    rowptr[1:] = np.cumsum([len(r) for r in rows])
-    col = np.fromiter((c for r in rows for c, _ in r), dtype=np.int32, count=int(rowptr[-1]))
-    val = np.fromiter((v for r in rows for _, v in r), dtype=np.float64, count=int(rowptr[-1]))
-    return rowptr, col, val
+    has_base = growing[idx[:, 0]] & (dist[:, 0] > 0) & (rng.random(n_v) < 0.5)
+    bw = rng.uniform(0.05, 0.9, size=n_v)
+    cols = np.concatenate([np.where(keep, idx, n_s + 1), np.where(has_base, n_s, n_s + 1)[:, None]], 1)
+    vals = np.concatenate([np.where(keep, w, 0.0), np.where(has_base, bw, 0.0)[:, None]], 1)
+    order = np.argsort(cols, axis=1, kind="stable")
+    cols = np.take_along_axis(cols, order, 1)
+    vals = np.take_along_axis(vals, order, 1)
+    vals /= vals.sum(1, keepdims=True)
+    valid = cols <= n_s
+    rowptr = np.zeros(n_v + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(valid.sum(1))
+    return rowptr, cols[valid].astype(np.int32), vals[valid]

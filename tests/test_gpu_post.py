@@ -1,0 +1,159 @@
+"""GPU parity of Lloyd re-seeding and dual-mesh extraction against the FP64
+oracle, both fed the same float32 field values."""
+import numpy as np
+import pytest
+
+from paper_1804_09152_amd import inputs as I
+from tests.gpu_common import f32, gpu_load, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_09152_amd as lfb
+    lfb.load()
+    ctx = lfb.Context(0)
+    yield lfb, ctx
+    ctx.close()
+
+
+def _converged(orc, mesh, seeds, op, steps):
+    L = orc.operator(mesh.V, mesh.F, op)
+    U, _ = orc.run(L, orc.init(mesh.n_v, seeds), seeds.size, orc.default_params(), steps)
+    return f32(U)
+
+
+CASES = {
+    "lattice_torus64": lambda orc: _lattice(orc),
+    "ico5_jit_64": lambda orc: _ico(orc, 5, 64, 2, 300),
+    "ico4_jit_48": lambda orc: _ico(orc, 4, 48, 1, 250),
+}
+
+
+def _lattice(orc):
+    nx = 64
+    mesh = I.torus_grid(nx, nx)
+    seeds = np.array([x + nx * y for y in range(0, nx, 8) for x in range(0, nx, 8)], np.int32)
+    return mesh, seeds, 0, _converged(orc, mesh, seeds, 0, 120)
+
+
+def _ico(orc, level, k, seed, steps):
+    mesh, seeds = I.config_c2(level=level, n_seeds=k, seed=seed)
+    return mesh, seeds, 1, _converged(orc, mesh, seeds, 1, steps)
+
+
+def _fields(lfb, ctx, mesh, seeds, op, U):
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, op)
+    f = lfb.Fields(m, seeds)
+    gpu_load(f, U)
+    return m, f
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_lloyd_parity(lf, orc, name):
+    lfb, ctx = lf
+    mesh, seeds, op, U = CASES[name](orc)
+    m, f = _fields(lfb, ctx, mesh, seeds, op, U)
+    say("lloyd", name)
+    new_g, st_g = f.lloyd_reseed()
+    new_o, st_o, mg = orc.lloyd(mesh.V, mesh.F, U, seeds)
+    clear = mg > 1e-9
+    assert clear.mean() > 0.9
+    assert np.array_equal(new_g[clear], new_o[clear]), np.nonzero((new_g != new_o) & clear)[0]
+    assert np.array_equal(st_g[clear], st_o[clear])
+    assert np.unique(new_g).size == seeds.size
+
+
+def _ring(mesh, v):
+    return {int(x) for fc in mesh.F if v in fc for x in fc}
+
+
+def _state(mesh, supports, n_s):
+    rows = []
+    for v in range(mesh.n_v):
+        cs = [c for c in range(n_s) if v in supports[c]]
+        rows.append({c: 1.0 / len(cs) for c in cs} if cs else {n_s: 1.0})
+    ptr = np.zeros(mesh.n_v + 1, np.int64)
+    col, val = [], []
+    for i, r in enumerate(rows):
+        for c in sorted(r):
+            col.append(c)
+            val.append(r[c])
+        ptr[i + 1] = len(col)
+    return f32((ptr, np.array(col, np.int32), np.array(val)))
+
+
+def test_lloyd_pins_on_gpu(lf):
+    """The oracle's hand-built Lloyd cases, run through the GPU."""
+    lfb, ctx = lf
+    m3 = I.icosphere(3)
+    ring = _ring(m3, 3)
+    far = set(range(m3.n_v)) - ring
+    caps = _ring(m3, 0) | _ring(m3, 1)
+    say("lloyd pins")
+    # symmetric cell moves to its centre; a second cell wanting it stays
+    seeds = np.array([sorted(ring - {3})[0], sorted(ring - {3})[1], 0], np.int32)
+    _, f = _fields(lfb, ctx, m3, seeds, 1, _state(m3, [ring, ring, far], 3))
+    new, st = f.lloyd_reseed()
+    assert new[0] == 3 and st[0] == 0 and new[1] == seeds[1] and st[1] == 2
+    # a miss keeps the seed; a mover onto it stays
+    seeds = np.array([sorted(ring - {3})[0], 3], np.int32)
+    _, f = _fields(lfb, ctx, m3, seeds, 1, _state(m3, [ring, caps], 2))
+    new, st = f.lloyd_reseed()
+    assert st[1] == 1 and new[1] == 3 and st[0] == 2 and new[0] == seeds[0]
+
+
+def _csr_pairs(rp, col):
+    return {(i, int(j)) for i in range(len(rp) - 1) for j in col[rp[i]:rp[i + 1]]}
+
+
+def _cyc(t):
+    k = int(np.argmin(t))
+    return tuple(int(x) for x in np.roll(t, -k))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dual_mesh_parity(lf, orc, name):
+    lfb, ctx = lf
+    mesh, seeds, op, U = CASES[name](orc)
+    m, f = _fields(lfb, ctx, mesh, seeds, op, U)
+    say("dual", name)
+    tris, (rp, col) = f.dual_mesh(0.25)
+    d = orc.dual_mesh(mesh.V, mesh.F, U, seeds, 0.25)
+    # A_v and A_t: exact (thresholds on identical float32 values)
+    assert _csr_pairs(*f.dual_matrix(0)) == _csr_pairs(*d["A_v"])
+    assert _csr_pairs(*f.dual_matrix(1)) == _csr_pairs(*d["A_t"])
+    pairs, state = f.dual_candidates()
+    assert np.array_equal(pairs, d["cand"])
+    clear = d["cand_margin"] > 1e-12
+    assert np.array_equal(state[clear], d["cand_state"][clear])
+    if clear.all():
+        assert _csr_pairs(rp, col) == _csr_pairs(*d["A_d"])
+        assert {tuple(sorted(t)) for t in tris} == {tuple(sorted(t)) for t in d["tri"]}
+        if d["n_conflict"] == 0 and d["n_nonmanifold"] == 0:
+            assert {_cyc(t) for t in tris} == {_cyc(t) for t in d["tri"]}
+
+
+def test_full_size_c3_post(lf, orc):
+    """Lloyd and dual mesh at the benchmark's size, on a synthetic state."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c3()
+    U = f32(I.synthetic_state(mesh, seeds, np.random.default_rng(0), k=3))
+    m, f = _fields(lfb, ctx, mesh, seeds, 1, U)
+    say("c3 lloyd")
+    new_g, st_g = f.lloyd_reseed()
+    new_o, st_o, mg = orc.lloyd(mesh.V, mesh.F, U, seeds)
+    clear = mg > 1e-9
+    assert np.array_equal(new_g[clear], new_o[clear])
+    say("c3 dual")
+    tris, (rp, col) = f.dual_mesh(0.25)
+    d = orc.dual_mesh(mesh.V, mesh.F, U, seeds, 0.25)
+    assert _csr_pairs(*f.dual_matrix(0)) == _csr_pairs(*d["A_v"])
+    pairs, state = f.dual_candidates()
+    assert np.array_equal(pairs, d["cand"])
+    clear = d["cand_margin"] > 1e-12
+    assert np.array_equal(state[clear], d["cand_state"][clear])

@@ -1,0 +1,294 @@
+"""GPU parity of the operator, initialisation, time step and labels against the
+FP64 oracle, through the C ABI (liblf.so)."""
+import numpy as np
+import pytest
+
+from paper_1804_09152_amd import inputs as I
+from tests.gpu_common import as_oracle, check_step, f32, gpu_load, row_compare, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_09152_amd as lfb
+    lfb.load()
+    ctx = lfb.Context(0)
+    yield lfb, ctx
+    ctx.close()
+
+
+def _params(lfb, P):
+    return lfb.default_params(w=P["w"], a=P["a"], e=P["e"], mu=P["mu"], dt=P["dt"],
+                              theta=P["theta"], base_mode=P.get("base_mode", 0))
+
+
+MESHES = {
+    "c1_torus64_graph": (lambda: I.config_c1(), 0),
+    "ico4_jit_cotan": (lambda: I.config_c2(level=4, n_seeds=48, seed=1), 1),
+    "ico5_jit_cotan": (lambda: I.config_c2(level=5, n_seeds=64, seed=2), 1),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_operator_parity(lf, orc, name):
+    lfb, ctx = lf
+    (mesh, seeds), op = MESHES[name][0](), MESHES[name][1]
+    say("operator", name)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, op)
+    rp, col, val = m.operator()
+    Lp, Lc, Lv = orc.operator(mesh.V, mesh.F, op)
+    assert np.array_equal(rp, Lp) and np.array_equal(col, Lc)
+    assert np.all(np.abs(val - Lv) <= 1e-6 * np.maximum(1.0, np.abs(Lv)))
+
+
+def test_init_parity(lf, orc):
+    lfb, ctx = lf
+    mesh, seeds = I.config_c1()
+    say("init c1")
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, seeds)
+    G = f.export()
+    O = orc.init(mesh.n_v, seeds)
+    assert np.array_equal(G[0], O[0]) and np.array_equal(G[1], O[1]) and np.array_equal(G[2], O[2])
+
+
+TF_CASES = [
+    ("c1_torus64_graph", {}, [0, 1, 2, 5, 10, 20, 40, 80, 150]),
+    ("ico5_jit_cotan", {}, [0, 1, 3, 10, 30, 60, 120, 200]),
+    ("ico4_jit_cotan", {"theta": 0.0}, [0, 1, 2, 5, 10, 20, 40, 80]),
+    ("ico4_jit_cotan", {"base_mode": 1}, [0, 1, 2, 5, 10, 20]),
+]
+
+
+@pytest.mark.parametrize("name,over,ts", TF_CASES)
+def test_step_teacher_forced(lf, orc, name, over, ts):
+    """The oracle's state at step t (rounded to float32) goes into the GPU; one
+    GPU step is compared with one oracle step from the same input."""
+    lfb, ctx = lf
+    (mesh, seeds), op = MESHES[name][0](), MESHES[name][1]
+    P = orc.default_params(**over)
+    L = orc.operator(mesh.V, mesh.F, op)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, op)
+    f = lfb.Fields(m, seeds, _params(lfb, P))
+    k = seeds.size
+    U = orc.init(mesh.n_v, seeds)
+    t = 0
+    for target in ts:
+        while t < target:
+            U = orc.step(L, U, k, P)
+            t += 1
+        Uf = f32(U)
+        say("teacher-forced", name, over, "t", t)
+        gpu_load(f, Uf)
+        s0 = f.stats()["skeleton_total"]
+        f.step(1)
+        G = as_oracle(f.export())
+        O, info = orc.step(L, Uf, k, P, want_info=True)
+        r = check_step(G, O, info["margin"], what=f"{name} t={t}")
+        if r["guarded"] == 0:
+            assert f.stats()["skeleton_total"] - s0 == int(info["skel"].sum())
+
+
+def test_free_running_c1(lf, orc):
+    """200 float32 GPU steps against 200 float64 oracle steps (theta = 1e-3):
+    identical patterns and labels, fields within 1e-5."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c1()
+    P = orc.default_params()
+    L = orc.operator(mesh.V, mesh.F, 0)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, seeds)
+    U = orc.init(mesh.n_v, seeds)
+    skel = 0
+    for chunk in range(10):
+        say("free-running c1 chunk", chunk)
+        f.step(20)
+        for _ in range(20):
+            U, info = orc.step(L, U, 32, P, want_info=True)
+            skel += int(info["skel"].sum())
+        G = as_oracle(f.export())
+        pat, diff = row_compare(G, U)
+        assert pat.all(), f"pattern differs at step {20 * (chunk + 1)} on {(~pat).sum()} rows"
+        assert diff.max() <= 1e-5
+    lab_g = f.labels()
+    lab_o, gap = orc.labels(U, 32)
+    clear = gap > 1e-5
+    assert np.array_equal(lab_g[clear], lab_o[clear])
+    st = f.stats()
+    assert st["steps"] == 200 and st["skeleton_total"] == skel and st["empty_columns"] == 0
+
+
+def test_labels_parity_on_shared_state(lf, orc):
+    """Labels of the same float32 state: an argmax on identical numbers."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c2(level=5, n_seeds=64, seed=2)
+    U = f32(I.synthetic_state(mesh, seeds, np.random.default_rng(3), k=3))
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    f = lfb.Fields(m, seeds)
+    say("labels ico5")
+    gpu_load(f, U)
+    lab_o, _ = orc.labels(U, seeds.size)
+    assert np.array_equal(f.labels(), lab_o)
+
+
+def test_full_size_c3_one_step(lf, orc):
+    """The roofline workload at full size (icosphere level 9, 2,621,442
+    vertices, 16,384 cells) in the benchmark's launch configuration: one step
+    from a synthetic mid-run state, every row against the oracle."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c3()
+    say("c3 operator")
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    L = orc.operator(mesh.V, mesh.F, 1)
+    rp, col, val = m.operator()
+    assert np.array_equal(rp, L[0]) and np.array_equal(col, L[1])
+    assert np.all(np.abs(val - L[2]) <= 1e-6 * np.maximum(1.0, np.abs(L[2])))
+    U = f32(I.synthetic_state(mesh, seeds, np.random.default_rng(0), k=3))
+    f = lfb.Fields(m, seeds)
+    say("c3 step")
+    gpu_load(f, U)
+    f.step(1)
+    G = as_oracle(f.export())
+    O, info = orc.step(L, U, seeds.size, orc.default_params(), want_info=True)
+    r = check_step(G, O, info["margin"], what="c3")
+    say("c3", r)
+    # from seeds too: 5 free steps, teacher-forced comparison of the last
+    f.reset(seeds)
+    f.step(4)
+    G4 = as_oracle(f.export())
+    U4 = orc.init(mesh.n_v, seeds)
+    for _ in range(4):
+        U4 = orc.step(L, U4, seeds.size, orc.default_params())
+    pat, diff = row_compare(G4, U4)
+    assert pat.all() and diff.max() <= 1e-5
+
+
+def test_capacity_growth_replays_exactly(lf, orc):
+    lfb, ctx = lf
+    mesh, seeds = I.config_c1()
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    say("capacity growth")
+    a = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=mesh.n_v))
+    b = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=8 * mesh.n_v))
+    a.step(100)
+    b.step(100)
+    A, B = a.export(), b.export()
+    assert a.stats()["grow_events"] > 0 and b.stats()["grow_events"] == 0
+    for x, y in zip(A, B):
+        assert np.array_equal(x, y)
+    assert a.stats()["skeleton_total"] == b.stats()["skeleton_total"]
+
+
+def test_wide_rows(lf, orc):
+    """A vertex whose neighbourhood holds 13 layers takes the 64-slot path."""
+    lfb, ctx = lf
+    nx = 16
+    mesh = I.torus_grid(nx, nx)
+    L = orc.operator(mesh.V, mesh.F, 0)
+    nb = [int(c) for c in L[1][L[0][0]:L[0][1]] if c != 0]
+    n_s = 14
+    rows = [{n_s: 1.0} for _ in range(mesh.n_v)]
+    rows[0] = {0: 1.0}
+    for j, u in enumerate(nb):
+        rows[u] = {1 + 2 * j: 0.5, 2 + 2 * j: 0.5}
+    ptr = np.zeros(mesh.n_v + 1, np.int64)
+    col, val = [], []
+    for i, r in enumerate(rows):
+        for c in sorted(r):
+            col.append(c)
+            val.append(r[c])
+        ptr[i + 1] = len(col)
+    U = (ptr, np.array(col, np.int32), np.array(val))
+    seeds = np.arange(n_s, dtype=np.int32) + 100
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, seeds)
+    say("wide rows")
+    for t in range(3):
+        gpu_load(f, f32(U))
+        f.step(1)
+        G = as_oracle(f.export())
+        O, info = orc.step(L, f32(U), n_s, orc.default_params(), want_info=True)
+        assert np.diff(O[0])[0] > 8 or t > 0
+        check_step(G, O, info["margin"], what=f"wide t={t}", max_guarded_frac=0.05)
+        U = O
+
+
+def test_determinism(lf):
+    lfb, ctx = lf
+    mesh, seeds = I.config_c2(level=5, n_seeds=64, seed=2)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    say("determinism")
+    out = []
+    for _ in range(2):
+        f = lfb.Fields(m, seeds)
+        f.step(150)
+        out.append(f.export())
+        f.close()
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
+
+
+def test_constant_field(lf):
+    lfb, ctx = lf
+    mesh = I.jitter(I.icosphere(4), np.random.default_rng(1))
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    seeds = np.array([0, 1, 2], np.int32)
+    f = lfb.Fields(m, seeds)
+    n = mesh.n_v
+    ptr = np.arange(n + 1, dtype=np.int32) * 3
+    col = np.tile(np.array([0, 2, 3], np.int32), n)
+    val = np.tile(np.array([0.3, 0.5, 0.2], np.float32), n)
+    say("constant field")
+    f.load(ptr, col, val)
+    f.step(3)
+    P, C, V = f.export()
+    assert np.all(np.diff(P) == np.diff(P)[0])
+    k = np.diff(P)[0]
+    assert np.abs(V.reshape(n, k) - V.reshape(n, k)[0]).max() < 2e-6
+
+
+def test_single_seed_and_many_seeds(lf, orc):
+    lfb, ctx = lf
+    for nx, k, steps in [(32, 1, 150), (8, 63, 30)]:
+        mesh = I.torus_grid(nx, nx)
+        seeds = I.seeds_uniform(mesh.n_v, k, np.random.default_rng(k))
+        L = orc.operator(mesh.V, mesh.F, 0)
+        m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+        f = lfb.Fields(m, seeds)
+        say("seeds", nx, k)
+        f.step(steps)
+        U, _ = orc.run(L, orc.init(mesh.n_v, seeds), k, orc.default_params(), steps)
+        pat, diff = row_compare(as_oracle(f.export()), U)
+        assert pat.all() and diff.max() <= 1e-5
+
+
+def test_invalid_inputs(lf):
+    lfb, ctx = lf
+    mesh, seeds = I.config_c1()
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    say("invalid inputs")
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        lfb.Fields(m, np.array([1, 2, 1], np.int32))
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        lfb.Fields(m, np.array([1, mesh.n_v], np.int32))
+    bad = mesh.F.copy()
+    bad[3, 2] = bad[3, 0]
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        lfb.Mesh(ctx, mesh.V, bad, 0)
+    f = lfb.Fields(m, seeds)
+    f.step(3)
+    before = f.export()
+    P, C, V = [x.copy() for x in before]
+    if P[1] - P[0] >= 2:
+        C[0], C[1] = C[1], C[0]
+    else:
+        V[0] = 2.0  # out of range value
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        f.load(P, C, V)
+    after = f.export()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
