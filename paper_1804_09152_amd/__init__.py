@@ -11,6 +11,7 @@ raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 
@@ -48,6 +49,17 @@ EXPORTS = [
 ]
 
 _lib = None
+_exiting = False
+
+
+def _at_exit():
+    # handles still alive at interpreter exit are left to the process
+    # teardown: the HIP runtime may already be shutting down
+    global _exiting
+    _exiting = True
+
+
+atexit.register(_at_exit)
 
 
 def load(path: str | None = None):
@@ -271,6 +283,8 @@ class Context:
             self.h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -299,6 +313,8 @@ class Mesh:
             self.h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -394,6 +410,8 @@ class Fields:
             self.h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:

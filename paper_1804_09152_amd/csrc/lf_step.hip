@@ -196,31 +196,73 @@ __device__ __forceinline__ bool add_regs(RowBuf<kRowRegs>& r, int& cnt, int c, f
   return true;
 }
 
+constexpr int kNbPre = 8;  // neighbours whose rows are prefetched
+
 // Gathers row i: its own layers (lam starts at L_ii * phi) and then, in the
-// operator's column order, every neighbour row scaled by L(i,u).
+// operator's column order, every neighbour row scaled by L(i,u).  The loads
+// are issued in four independent rounds (row bounds; operator row; the
+// neighbours' row bounds; the first two entries of the own row and of every
+// neighbour row) so that a thread keeps about twenty loads in flight
+// instead of walking a chain of dependent ones.  The accumulation order is
+// fixed: own row, then neighbour by neighbour, each row in layer order.
 __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int i,
                                             const StepArgs& A) {
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   cnt = 0;
-  const float dg = A.ldiag[i];
   const int p0 = A.uptr_in[i], p1 = A.uptr_in[i + 1];
+  const int q0 = A.lptr[i], q1 = A.lptr[i + 1];
+  const float dg = A.ldiag[i];
+  int nu[kNbPre];
+  float nw[kNbPre];
+#pragma unroll
+  for (int k = 0; k < kNbPre; ++k) {
+    const bool ok = q0 + k < q1;
+    const Ent le = ok ? A.lent[q0 + k] : Ent{-1, 0.f};
+    nu[k] = le.col;
+    nw[k] = le.val;
+  }
+  int na[kNbPre], nb[kNbPre];
+#pragma unroll
+  for (int k = 0; k < kNbPre; ++k) {
+    na[k] = nu[k] >= 0 ? A.uptr_in[nu[k]] : 0;
+    nb[k] = nu[k] >= 0 ? A.uptr_in[nu[k] + 1] : 0;
+  }
+  const Ent o0 = p0 < p1 ? A.uent_in[p0] : Ent{-1, 0.f};
+  const Ent o1 = p0 + 1 < p1 ? A.uent_in[p0 + 1] : Ent{-1, 0.f};
+  Ent e0[kNbPre], e1[kNbPre];
+#pragma unroll
+  for (int k = 0; k < kNbPre; ++k) {
+    e0[k] = na[k] < nb[k] ? A.uent_in[na[k]] : Ent{-1, 0.f};
+    e1[k] = na[k] + 1 < nb[k] ? A.uent_in[na[k] + 1] : Ent{-1, 0.f};
+  }
   if (p1 - p0 > kRowRegs) return false;
-  for (int p = p0; p < p1; ++p) {
+  if (p0 < p1) { put_regs(r, 0, o0.col, o0.val, dg * o0.val); cnt = 1; }
+  if (p0 + 1 < p1) { put_regs(r, 1, o1.col, o1.val, dg * o1.val); cnt = 2; }
+  for (int p = p0 + 2; p < p1; ++p) {
     const Ent e = A.uent_in[p];
     put_regs(r, cnt, e.col, e.val, dg * e.val);
     ++cnt;
   }
-  const int q0 = A.lptr[i], q1 = A.lptr[i + 1];
-  for (int q = q0; q < q1; ++q) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < kNbPre; ++k) {
+    if (na[k] < nb[k]) ok = ok && add_regs(r, cnt, e0[k].col, nw[k], e0[k].val);
+    if (na[k] + 1 < nb[k]) ok = ok && add_regs(r, cnt, e1[k].col, nw[k], e1[k].val);
+    for (int p = na[k] + 2; p < nb[k]; ++p) {
+      const Ent e = A.uent_in[p];
+      ok = ok && add_regs(r, cnt, e.col, nw[k], e.val);
+    }
+  }
+  for (int q = q0 + kNbPre; q < q1; ++q) {  // vertices of degree above kNbPre
     const Ent le = A.lent[q];
     const int a0 = A.uptr_in[le.col], a1 = A.uptr_in[le.col + 1];
     for (int p = a0; p < a1; ++p) {
       const Ent e = A.uent_in[p];
-      if (!add_regs(r, cnt, e.col, le.val, e.val)) return false;
+      ok = ok && add_regs(r, cnt, e.col, le.val, e.val);
     }
   }
-  return true;
+  return ok;
 }
 
 // ---- wide path (rows touching more than kRowRegs layers) ----------------------

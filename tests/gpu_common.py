@@ -56,7 +56,7 @@ def row_compare(G, O):
     return pat, diff
 
 
-def check_step(G, O, margin, guard=1e-5, tol=1e-5, max_guarded_frac=1e-3, what=""):
+def check_step(G, O, margin, guard=1e-5, tol=1e-5, max_guarded_frac=1e-2, what=""):
     """Bit-exact patterns and values within tol on every row whose oracle
     decisions are all further than `guard` from their thresholds."""
     pat, diff = row_compare(G, O)
