@@ -70,6 +70,9 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise LFError(6, f"{p} is missing: build it with python -m paper_1804_09152_amd.build")
+    # torch ships its own HIP runtime; importing it first makes liblf.so bind
+    # to that same runtime instead of loading a second one
+    import torch  # noqa: F401
     lib = C.CDLL(p)
     V, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     PV = C.POINTER(C.c_void_p)

@@ -65,6 +65,11 @@ static StepArgs make_args(lf_fields* f, int parity) {
   a.status_next = f->status[1 - parity];
   a.ticket = f->tickets + parity;
   a.ticket_next = f->tickets + (1 - parity);
+  a.wide = f->wide;
+  a.wide_cap = f->wide_cap;
+  a.pad_ = 0;
+  a.wide_ctr = f->tickets + 2 + parity;
+  a.wide_ctr_next = f->tickets + 2 + (1 - parity);
   a.flags = f->flags;
   return a;
 }
@@ -72,8 +77,22 @@ static StepArgs make_args(lf_fields* f, int parity) {
 static lf_status clear_step_state(lf_fields* f) {
   hipStream_t s = f->mesh->ctx->stream;
   for (int k = 0; k < 2; ++k) LF_HIP(launch_fill_u64(f->status[k], f->n_tiles, 0ull, s));
-  LF_HIP(launch_fill_i32((int32_t*)f->tickets, 2, 0, s));
-  LF_HIP(launch_reset_flags(f->flags, s, false));
+  LF_HIP(launch_fill_i32((int32_t*)f->tickets, 4, 0, s));
+  LF_HIP(launch_reset_flags(f->flags, nullptr, 0, s));
+  return LF_OK;
+}
+
+// four times more workspace rows for vertices touching many layers
+static lf_status grow_wide(lf_fields* f) {
+  const int64_t c = 4ll * f->wide_cap;
+  if (c > (1ll << 24)) return fail(LF_ECAPACITY, "wide-row workspace would exceed 2^24 rows");
+  WideRow* p = nullptr;
+  LF_HIP(dalloc(&p, c));
+  LF_HIP(hipStreamSynchronize(f->mesh->ctx->stream));
+  hipFree(f->wide);
+  f->wide = p;
+  f->wide_cap = (int32_t)c;
+  f->grow_events++;
   return LF_OK;
 }
 
@@ -290,6 +309,8 @@ lf_status lf_fields_destroy(lf_fields* f) {
   hipFree(f->d_seeds);
   hipFree(f->owner);
   hipFree(f->tickets);
+  hipFree(f->wide);
+  hipFree(f->stats);
   hipFree(f->flags);
   if (f->flags_host) hipHostFree(f->flags_host);
   for (auto e : f->ev0) hipEventDestroy(e);
@@ -331,7 +352,9 @@ lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const 
     ALLOC(f->uent[k], f->cap);
     ALLOC(f->status[k], f->n_tiles);
   }
-  ALLOC(f->tickets, 2);
+  ALLOC(f->tickets, 4);
+  f->wide_cap = 1024;
+  ALLOC(f->wide, f->wide_cap);
   ALLOC(f->flags, 1);
 #undef ALLOC
   if (e == hipSuccess) e = hipHostMalloc((void**)&f->flags_host, sizeof(StepFlags), 0);
@@ -339,7 +362,7 @@ lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const 
     lf_fields_destroy(f);
     return hip_fail(e, "allocating field state");
   }
-  e = launch_reset_flags(f->flags, m->ctx->stream, true);
+  e = launch_reset_flags(f->flags, nullptr, 0, m->ctx->stream);
   if (e != hipSuccess) {
     lf_fields_destroy(f);
     return hip_fail(e, "reset flags");
@@ -385,10 +408,20 @@ lf_status lf_step(lf_fields* f, int32_t n) {
   int64_t remaining = n;
   int grows = 0;
   while (remaining > 0) {
-    LF_HIP(launch_reset_flags(f->flags, s, false));
+    if (remaining > f->stats_cap) {
+      const int64_t c = std::max<int64_t>(remaining, 2 * f->stats_cap);
+      StepStats* p = nullptr;
+      LF_HIP(dalloc(&p, c));
+      hipFree(f->stats);
+      f->stats = p;
+      f->stats_cap = c;
+    }
+    LF_HIP(launch_reset_flags(f->flags, f->stats, (int)remaining, s));
     size_t used = 0;
     for (int64_t k = 0; k < remaining; ++k) {
       StepArgs a = make_args(f, (int)((f->cur + k) & 1));
+      a.stats = f->stats + k;
+      a.step_idx = (uint32_t)k;
       hipEvent_t t0 = nullptr, t1 = nullptr;
       if (f->timing) {
         t0 = pool_event(f->ev0, used);
@@ -397,7 +430,10 @@ lf_status lf_step(lf_fields* f, int32_t n) {
       }
       LF_HIP(launch_step(a, s, t0, t1));
     }
+    f->stats_host.resize((size_t)remaining);
     LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipMemcpyAsync(f->stats_host.data(), f->stats, sizeof(StepStats) * remaining,
+                          hipMemcpyDeviceToHost, s));
     LF_HIP(hipStreamSynchronize(s));
     for (size_t k = 0; k < used; ++k) {
       float ms = 0.f;
@@ -407,10 +443,19 @@ lf_status lf_step(lf_fields* f, int32_t n) {
       }
     }
     const StepFlags fl = *f->flags_host;
-    const int64_t ok = (int64_t)fl.steps_ok;
+    // steps before the first failed one are complete; the later ones did nothing
+    const int64_t ok = fl.poisoned ? std::min<int64_t>(fl.fail_step, remaining) : remaining;
+    for (int64_t k = 0; k < ok; ++k) {
+      const StepStats& t = f->stats_host[(size_t)k];
+      f->skel_total += t.skel;
+      f->out_total += t.out;
+      f->in_total += t.in;
+      f->events_total += t.events;
+    }
     f->cur = (int)((f->cur + ok) & 1);
     f->steps += ok;
     remaining -= ok;
+    if (!fl.poisoned) break;
     if (fl.poisoned & 2u) {
       clear_step_state(f);
       return fail(LF_ECAPACITY, "a vertex touches more than 64 layers");
@@ -419,13 +464,17 @@ lf_status lf_step(lf_fields* f, int32_t n) {
       clear_step_state(f);
       return fail(LF_EDEVICE, "step look-back did not complete");
     }
+    if (++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
+    if (fl.poisoned & 8u) {
+      lf_status st = grow_wide(f);
+      if (st) return st;
+    }
     if (fl.poisoned & 1u) {
-      if (++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
       lf_status st = grow(f, (int64_t)fl.need);
       if (st) return st;
-    } else if (remaining > 0) {
-      return fail(LF_EDEVICE, "steps reported complete but some are missing");
     }
+    lf_status st = clear_step_state(f);
+    if (st) return st;
   }
   return LF_OK;
 }
@@ -545,28 +594,21 @@ lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skel, int64_t* steps, 
                    int64_t* grows) {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
-  hipStream_t s = f->mesh->ctx->stream;
-  LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
-  LF_HIP(hipStreamSynchronize(s));
   if (nnz_u) {
     lf_status st = current_nnz(f, nnz_u);
     if (st) return st;
   }
-  if (skel) *skel = (int64_t)f->flags_host->skel;
+  if (skel) *skel = (int64_t)f->skel_total;
   if (steps) *steps = f->steps;
-  if (empty) *empty = (int64_t)f->flags_host->events;
+  if (empty) *empty = (int64_t)f->events_total;
   if (grows) *grows = f->grow_events;
   return LF_OK;
 }
 
 lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out) {
   if (!f) return fail(LF_EINVAL, "NULL argument");
-  LF_HIP(hipSetDevice(f->mesh->ctx->device));
-  hipStream_t s = f->mesh->ctx->stream;
-  LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
-  LF_HIP(hipStreamSynchronize(s));
-  if (entries_in) *entries_in = (int64_t)f->flags_host->in_total;
-  if (entries_out) *entries_out = (int64_t)f->flags_host->out_total;
+  if (entries_in) *entries_in = (int64_t)f->in_total;
+  if (entries_out) *entries_out = (int64_t)f->out_total;
   return LF_OK;
 }
 

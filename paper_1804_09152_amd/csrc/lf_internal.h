@@ -24,21 +24,35 @@ constexpr int kMaxVerts = 1 << 25;
 // Device-side step status.  Written by the step kernels, read by the host
 // once per lf_step call.
 struct StepFlags {
-  unsigned int poisoned;        // bit 0 capacity, bit 1 row limit, bit 2 look-back timeout
-  unsigned int pad;
-  unsigned long long need;      // entries needed by the failing step
-  unsigned long long steps_ok;  // steps completed in this call
-  unsigned long long nnz;       // entries written by the last completed step
-  unsigned long long skel;      // sum of |rows of interest| over completed steps
-  unsigned long long events;    // columns whose normalisation sum was zero
-  unsigned long long out_total; // sum of nnz(U_{t+1}) over completed steps
-  unsigned long long in_total;  // sum of nnz(U_t) over completed steps
+  unsigned int poisoned;   // bit 0 capacity, bit 1 row limit, bit 2 look-back timeout,
+                           // bit 3 wide-row workspace exhausted
+  unsigned int fail_step;  // index (within the call) of the first failed step
+  unsigned long long need; // entries needed by a step that overflowed
+};
+
+// Per-step counters, written for step k of an lf_step call at stats[k]: the
+// host adds up those of the steps that completed.
+struct StepStats {
+  unsigned long long skel;    // sum of |rows of interest|
+  unsigned long long out;     // nnz(U_{t+1})
+  unsigned long long in;      // nnz(U_t)
+  unsigned long long events;  // columns whose normalisation sum was zero
 };
 
 struct StepConsts {
   float a, w, e, mu, dt, theta;
   int32_t base_mode;
   int32_t n_s;
+};
+
+// Workspace of one row touching more than kRowRegs layers (global memory, so
+// that the step kernel itself needs no private memory).
+struct WideRow {
+  int32_t col[kRowWide];
+  float phi[kRowWide];
+  float lam[kRowWide];
+  float out[kRowWide];
+  int32_t cnt, n_keep, pad0, pad1;
 };
 
 struct StepArgs {
@@ -57,7 +71,15 @@ struct StepArgs {
   unsigned long long* status_next;  // cleared here for the next step
   unsigned int* ticket;
   unsigned int* ticket_next;
+  WideRow* wide;                   // workspace slots for wide rows
+  int32_t wide_cap;
+  int32_t pad_;
+  unsigned int* wide_ctr;          // slots taken in this step
+  unsigned int* wide_ctr_next;     // cleared here for the next step
   StepFlags* flags;
+  StepStats* stats;                // this step's counters
+  uint32_t step_idx;               // index of this step within the call
+  uint32_t pad2_;
 };
 
 // error handling -----------------------------------------------------------
@@ -71,7 +93,8 @@ lf_status hip_fail(hipError_t e, const char* what);
 
 // launchers (each defined next to its kernels) ------------------------------
 hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
-hipError_t launch_reset_flags(StepFlags* f, hipStream_t s, bool all);
+// clears the failure flags and the first n per-step counters
+hipError_t launch_reset_flags(StepFlags* f, StepStats* st, int n, hipStream_t s);
 hipError_t launch_init_fields(const int32_t* owner, int32_t n_v, int32_t* uptr, Ent* uent,
                               hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -145,12 +168,18 @@ struct lf_fields {
   int64_t cap;
   int cur;
   unsigned long long* status[2];
-  unsigned int* tickets;       // 2 counters
+  unsigned int* tickets;       // 4 counters: tile tickets and wide-row slots, per parity
+  lf::WideRow* wide;
+  int32_t wide_cap;
   lf::StepFlags* flags;
   lf::StepFlags* flags_host;   // pinned
+  lf::StepStats* stats;        // per-step counters of one call
+  int64_t stats_cap;
+  std::vector<lf::StepStats> stats_host;
   int32_t n_tiles;
-  // stats
+  // totals over completed steps
   long long steps, grow_events;
+  unsigned long long skel_total, out_total, in_total, events_total;
   // timing
   bool timing;
   std::vector<hipEvent_t> ev0, ev1;

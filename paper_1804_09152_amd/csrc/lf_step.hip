@@ -20,7 +20,8 @@
 // Design: one thread per vertex row, 256 rows per tile.  The row's union of
 // layers (its own row and the rows of its mesh neighbours, typically 1-4
 // layers) is accumulated in registers (8 slots); a row with more layers
-// takes a slower path with 64 slots in private memory.  Nothing but U and
+// takes a slower path with 64 slots in a global-memory workspace row (the
+// kernel uses no private memory).  Nothing but U and
 // the operator is read, nothing but the next U is written: the field
 // Laplacian and the rows of interest never leave the chip.  The output is
 // compacted in the same pass: a block-wide scan of the per-row counts and a
@@ -68,9 +69,9 @@ struct MaskT<kRowRegs> {
 // Closed-form update of one row's active layers.  Slots s < cnt hold the
 // row's union of layers (col, phi = U(i,col), lam = field Laplacian).
 // out[s] receives the normalised kept value or -1.
-template <int K, bool UNROLL>
-__device__ __forceinline__ void row_update(RowBuf<K>& r, int cnt, const StepConsts& c,
-                                           int& n_keep, int& n_skel, int& ev) {
+template <int K, bool UNROLL, class B>
+__device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, int& n_keep,
+                                           int& n_skel, int& ev) {
   using M = typename MaskT<K>::type;
   M act = 0;
   int n = 0, nC = 0;
@@ -268,11 +269,10 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int i
 // ---- wide path (rows touching more than kRowRegs layers) ----------------------
 
 // Same arithmetic in the same order as the register path, with kRowWide
-// slots in private memory.  Returns the number of kept entries; writes them
-// to dst in ascending layer order when dst is given.
-__device__ __noinline__ int wide_row(int i, const StepArgs* A, Ent* dst, int* n_skel, int* ev,
+// slots in a global-memory workspace row.  Returns the number of kept
+// entries (0 and *ovf set when the row touches more than kRowWide layers).
+__device__ __forceinline__ int wide_row(int i, const StepArgs* A, WideRow* r, int* n_skel, int* ev,
                                      int* ovf) {
-  RowBuf<kRowWide> r;
   int cnt = 0;
   *n_skel = 0;
   *ev = 0;
@@ -280,9 +280,9 @@ __device__ __noinline__ int wide_row(int i, const StepArgs* A, Ent* dst, int* n_
   for (int p = A->uptr_in[i]; p < A->uptr_in[i + 1]; ++p) {
     if (cnt == kRowWide) { *ovf = 1; return 0; }
     const Ent e = A->uent_in[p];
-    r.col[cnt] = e.col;
-    r.phi[cnt] = e.val;
-    r.lam[cnt] = dg * e.val;
+    r->col[cnt] = e.col;
+    r->phi[cnt] = e.val;
+    r->lam[cnt] = dg * e.val;
     ++cnt;
   }
   for (int q = A->lptr[i]; q < A->lptr[i + 1]; ++q) {
@@ -290,32 +290,42 @@ __device__ __noinline__ int wide_row(int i, const StepArgs* A, Ent* dst, int* n_
     for (int p = A->uptr_in[le.col]; p < A->uptr_in[le.col + 1]; ++p) {
       const Ent e = A->uent_in[p];
       int s = 0;
-      while (s < cnt && r.col[s] != e.col) ++s;
+      while (s < cnt && r->col[s] != e.col) ++s;
       if (s < cnt) {
-        r.lam[s] = fmaf(le.val, e.val, r.lam[s]);
+        r->lam[s] = fmaf(le.val, e.val, r->lam[s]);
       } else {
         if (cnt == kRowWide) { *ovf = 1; return 0; }
-        r.col[cnt] = e.col;
-        r.phi[cnt] = 0.f;
-        r.lam[cnt] = le.val * e.val;
+        r->col[cnt] = e.col;
+        r->phi[cnt] = 0.f;
+        r->lam[cnt] = le.val * e.val;
         ++cnt;
       }
     }
   }
-  for (int s = cnt; s < kRowWide; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
+  for (int s = cnt; s < kRowWide; ++s) { r->col[s] = -1; r->phi[s] = 0.f; r->lam[s] = 0.f; }
   int n_keep = 0;
-  row_update<kRowWide, false>(r, cnt, A->c, n_keep, *n_skel, *ev);
-  if (dst) {
-    int last = -1;
-    for (int k = 0; k < n_keep; ++k) {
-      int best = -1;
-      for (int s = 0; s < cnt; ++s)
-        if (r.out[s] > 0.f && r.col[s] > last && (best < 0 || r.col[s] < r.col[best])) best = s;
-      dst[k] = Ent{r.col[best], r.out[best]};
-      last = r.col[best];
-    }
-  }
+  row_update<kRowWide, false>(*r, cnt, A->c, n_keep, *n_skel, *ev);
+  r->cnt = cnt;
+  r->n_keep = n_keep;
   return n_keep;
+}
+
+// kept entries of a wide row, in ascending layer order
+__device__ __forceinline__ void wide_write(const WideRow* r, Ent* dst) {
+  int last = -1;
+  for (int k = 0; k < r->n_keep; ++k) {
+    int best = -1;
+    for (int s = 0; s < r->cnt; ++s)
+      if (r->out[s] > 0.f && r->col[s] > last && (best < 0 || r->col[s] < r->col[best])) best = s;
+    dst[k] = Ent{r->col[best], r->out[best]};
+    last = r->col[best];
+  }
+}
+
+// marks this step (and so every later one of the call) as not done
+__device__ __forceinline__ void step_failed(const StepArgs& A, unsigned bit) {
+  atomicOr(&A.flags->poisoned, bit);
+  atomicMin(&A.flags->fail_step, A.step_idx);
 }
 
 __device__ __forceinline__ int wave_incl_scan(int x) {
@@ -343,22 +353,33 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   if (tile < 0) return;  // an earlier step overflowed: nothing to do
   if (tid == 0) {
     A.status_next[tile] = 0ull;
-    if (tile == 0) *A.ticket_next = 0u;
+    if (tile == 0) {
+      *A.ticket_next = 0u;
+      *A.wide_ctr_next = 0u;
+    }
   }
   const int i = tile * kBlock + tid;
 
   RowBuf<kRowRegs> r;
   int cnt = 0, n_keep = 0, n_skel = 0, ev = 0, rowovf = 0;
-  bool wide = false;
+  int wide = -1;  // workspace slot of a wide row
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) r.out[s] = -1.f;
   if (i < A.n_v) {
-    wide = !gather_regs(r, cnt, i, A);
-    if (!wide) row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);
-    else n_keep = wide_row(i, &A, nullptr, &n_skel, &ev, &rowovf);
+    if (gather_regs(r, cnt, i, A)) {
+      row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);
+    } else {
+      const unsigned slot = atomicAdd(A.wide_ctr, 1u);
+      if (slot < (unsigned)A.wide_cap) {
+        wide = (int)slot;
+        n_keep = wide_row(i, &A, A.wide + slot, &n_skel, &ev, &rowovf);
+        if (rowovf) step_failed(A, 2u);
+      } else {
+        step_failed(A, 8u);  // the step is replayed with more slots
+      }
+    }
   }
-  if (ev) atomicAdd(&A.flags->events, 1ull);
-  if (rowovf) atomicOr(&A.flags->poisoned, 2u);
+  if (ev) atomicAdd(&A.stats->events, 1ull);
 
   // block scan of (kept entries, rows-of-interest size), packed 16/16
   const int x = n_keep | (n_skel << 16);
@@ -375,32 +396,45 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   }
   incl += woff;
 
-  // decoupled look-back over tiles
-  if (tid == 0) {
+  // decoupled look-back over tiles, one wavefront reading 64 predecessors
+  // per probe: lane k looks at tile (tile - 1 - k - 64 m)
+  if (tid < 64) {
     const unsigned long long agg =
         ((unsigned long long)(tot >> 16) << 31) | (unsigned long long)(tot & 0xffff);
     unsigned long long excl = 0;
     if (tile == 0) {
-      st_status(&A.status[0], kFlagPre | agg);
+      if (lane == 0) st_status(&A.status[0], kFlagPre | agg);
     } else {
-      st_status(&A.status[tile], kFlagAgg | agg);
-      int j = tile - 1;
+      if (lane == 0) st_status(&A.status[tile], kFlagAgg | agg);
+      int j0 = tile - 1;
       unsigned spins = 0;
+      bool timed_out = false;
       for (;;) {
-        const unsigned long long v = ld_status(&A.status[j]);
-        const unsigned long long fl = v >> 62;
-        if (fl == 0) {
-          if (++spins > kSpinLimit) { atomicOr(&A.flags->poisoned, 4u); break; }
+        const int j = j0 - lane;
+        unsigned long long v;
+        for (;;) {
+          // before tile 0 there is nothing: read as a prefix of zero
+          v = j >= 0 ? ld_status(&A.status[j]) : kFlagPre;
+          if (!__any((v >> 62) == 0)) break;
+          if (++spins > kSpinLimit) { timed_out = true; break; }
           __builtin_amdgcn_s_sleep(1);
-          continue;
         }
-        excl += v & kNoFlag;
-        if (fl == 2 || j == 0) break;
-        --j;
+        if (timed_out) {
+          if (lane == 0) step_failed(A, 4u);
+          break;
+        }
+        const unsigned long long pre = __ballot((v >> 62) == 2);
+        const int first = pre ? __ffsll((unsigned long long)pre) - 1 : 64;
+        unsigned long long c = lane <= first ? (v & kNoFlag) : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        excl += c;
+        if (pre) break;
+        j0 -= 64;
       }
-      st_status(&A.status[tile], kFlagPre | (excl + agg));
+      if (lane == 0) st_status(&A.status[tile], kFlagPre | (excl + agg));
     }
-    s_excl = excl;
+    if (lane == 0) s_excl = excl;
   }
   __syncthreads();
   const unsigned long long ex = s_excl;
@@ -412,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     A.uptr_out[i + 1] = (int)(base + n_keep);
     if (base + n_keep <= A.cap) {
       Ent* dst = A.uent_out + base;
-      if (!wide) {
+      if (wide < 0) {
 #pragma unroll
         for (int s = 0; s < kRowRegs; ++s) {
           if (r.out[s] > 0.f) {
@@ -424,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
           }
         }
       } else if (!rowovf) {
-        wide_row(i, &A, dst, &n_skel, &ev, &rowovf);
+        wide_write(A.wide + wide, dst);
       }
     }
   }
@@ -433,31 +467,23 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     const long long total = ex_count + (tot & 0xffff);
     const long long skel = ex_skel + (tot >> 16);
     if (total > A.cap) {
-      atomicOr(&A.flags->poisoned, 1u);
       atomicMax(&A.flags->need, (unsigned long long)total);
-    } else {
-      atomicAdd(&A.flags->steps_ok, 1ull);
-      atomicAdd(&A.flags->skel, (unsigned long long)skel);
-      atomicAdd(&A.flags->out_total, (unsigned long long)total);
-      atomicAdd(&A.flags->in_total, (unsigned long long)A.uptr_in[A.n_v]);
-      A.flags->nnz = (unsigned long long)total;
+      step_failed(A, 1u);
     }
+    A.stats->skel = (unsigned long long)skel;
+    A.stats->out = (unsigned long long)total;
+    A.stats->in = (unsigned long long)A.uptr_in[A.n_v];
   }
 }
 
-__global__ void k_reset_flags(StepFlags* f, int all) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_reset_flags(StepFlags* f, StepStats* st, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) {
     f->poisoned = 0;
+    f->fail_step = 0xffffffffu;
     f->need = 0;
-    f->steps_ok = 0;
-    if (all) {
-      f->nnz = 0;
-      f->skel = 0;
-      f->events = 0;
-      f->out_total = 0;
-      f->in_total = 0;
-    }
   }
+  if (st && k < n) st[k] = StepStats{0, 0, 0, 0};
 }
 
 }  // namespace
@@ -471,8 +497,9 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent
   return hipGetLastError();
 }
 
-hipError_t launch_reset_flags(StepFlags* f, hipStream_t s, bool all) {
-  hipLaunchKernelGGL(k_reset_flags, dim3(1), dim3(64), 0, s, f, all ? 1 : 0);
+hipError_t launch_reset_flags(StepFlags* f, StepStats* st, int n, hipStream_t s) {
+  const int nb = n > 0 ? (n + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_reset_flags, dim3(nb), dim3(256), 0, s, f, st, n);
   return hipGetLastError();
 }
 

@@ -223,6 +223,34 @@ def test_wide_rows(lf, orc):
         U = O
 
 
+def test_wide_workspace_growth(lf, orc):
+    """Thousands of vertices touching more than 8 layers: the wide-row
+    workspace (1024 rows at first) runs out, grows and the step is replayed."""
+    lfb, ctx = lf
+    mesh = I.torus_grid(64, 64)
+    n_s = 40
+    rng = np.random.default_rng(5)
+    D = np.zeros((mesh.n_v, n_s + 1))
+    for i in range(mesh.n_v):
+        c = rng.choice(n_s + 1, 3, replace=False)
+        D[i, c] = rng.uniform(0.1, 1.0, 3)
+    D /= D.sum(1, keepdims=True)
+    ptr = np.zeros(mesh.n_v + 1, np.int64)
+    ptr[1:] = np.cumsum((D > 0).sum(1))
+    col = np.nonzero(D > 0)[1].astype(np.int32)
+    U = f32((ptr, col, D[D > 0]))
+    L = orc.operator(mesh.V, mesh.F, 0)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, I.seeds_uniform(mesh.n_v, n_s, rng))
+    say("wide workspace growth")
+    gpu_load(f, U)
+    g0 = f.stats()["grow_events"]
+    f.step(1)
+    assert f.stats()["grow_events"] > g0
+    O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
+    check_step(as_oracle(f.export()), O, info["margin"], max_guarded_frac=0.05, what="wide growth")
+
+
 def test_determinism(lf):
     lfb, ctx = lf
     mesh, seeds = I.config_c2(level=5, n_seeds=64, seed=2)
