@@ -49,6 +49,10 @@ __device__ __forceinline__ void st_status(unsigned long long* p, unsigned long l
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// square root of a field value in [0, 1]: the hardware instruction (within
+// one unit in the last place), not the correctly rounded library sequence
+__device__ __forceinline__ float root(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 template <int K>
 struct RowBuf {
   int col[K];
@@ -77,7 +81,12 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
   int n = 0, nC = 0;
   bool hb = false;
   float sqb = 0.f, T = 0.f, PC = 0.f, RC = 0.f, Pall = 0.f, Rall = 0.f;
-#define LF_SLOTS _Pragma("unroll") for (int s = 0; s < K; ++s)
+// unrolled: stop at the wavefront's largest slot count (slots at and above
+// cnt keep out = -1, set by the caller); runtime loop for the wide path
+#define LF_SLOTS                                  \
+  _Pragma("unroll") for (int s = 0; s < K; ++s)   \
+    if (!__any(s < cnt)) break;                   \
+    else
 #define LF_SLOTS_RT _Pragma("unroll 1") for (int s = 0; s < K; ++s)
   if constexpr (UNROLL) {
     LF_SLOTS {
@@ -88,7 +97,7 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
           act |= (M)1 << s;
           ++n;
           T += r.lam[s];
-          const float sq = sqrtf(ph);
+          const float sq = root(ph);
           Pall += ph;
           Rall += sq;
           if (r.col[s] == c.n_s) { hb = true; sqb = sq; }
@@ -105,7 +114,7 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
           act |= (M)1 << s;
           ++n;
           T += r.lam[s];
-          const float sq = sqrtf(ph);
+          const float sq = root(ph);
           Pall += ph;
           Rall += sq;
           if (r.col[s] == c.n_s) { hb = true; sqb = sq; }
@@ -128,7 +137,7 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
   float V = 0.f;
   auto upd = [&](int s) {
     const float ph = r.phi[s], la = r.lam[s];
-    const float sq = sqrtf(ph);
+    const float sq = root(ph);
     const bool base = r.col[s] == c.n_s;
     float Q, G;
     if (c.base_mode == 0) {
@@ -160,8 +169,10 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
     return;
   }
   int k = 0;
+  // one division per row; a single active layer normalises to exactly 1
+  const float inv = 1.f / V;
   auto fin = [&](int s) {
-    const float o = r.out[s] / V;
+    const float o = n == 1 ? 1.f : r.out[s] * inv;
     const bool keep = o > 0.f && o >= c.theta;
     r.out[s] = keep ? o : -1.f;
     k += keep ? 1 : 0;
@@ -178,23 +189,45 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
 
 // ---- register path --------------------------------------------------------
 
+// The slot loops below stop at the wavefront's largest slot count (a uniform
+// branch), and are otherwise straight-line selects: no early exits, so the
+// register arrays stay in place instead of being copied per control path.
+#define LF_FOR_USED_SLOTS(bound)                   \
+  _Pragma("unroll") for (int s = 0; s < kRowRegs; ++s) \
+    if (!__any(s < (bound))) break;                 \
+    else
+
 __device__ __forceinline__ void put_regs(RowBuf<kRowRegs>& r, int slot, int c, float ph, float la) {
 #pragma unroll
-  for (int s = 0; s < kRowRegs; ++s)
-    if (s == slot) { r.col[s] = c; r.phi[s] = ph; r.lam[s] = la; }
+  for (int s = 0; s < kRowRegs; ++s) {
+    const bool m = s == slot;
+    r.col[s] = m ? c : r.col[s];
+    r.phi[s] = m ? ph : r.phi[s];
+    r.lam[s] = m ? la : r.lam[s];
+  }
 }
 
-// add w*x into layer c; false when the row needs more than kRowRegs slots
-__device__ __forceinline__ bool add_regs(RowBuf<kRowRegs>& r, int& cnt, int c, float w, float x) {
+// adds w*x into layer c (a new slot when c is not held yet); ovf when the
+// row needs more than kRowRegs slots
+__device__ __forceinline__ void add_regs(RowBuf<kRowRegs>& r, int& cnt, bool& ovf, int c, float w,
+                                         float x) {
   bool found = false;
-#pragma unroll
-  for (int s = 0; s < kRowRegs; ++s)
-    if (r.col[s] == c) { r.lam[s] = fmaf(w, x, r.lam[s]); found = true; }
-  if (found) return true;
-  if (cnt == kRowRegs) return false;
-  put_regs(r, cnt, c, 0.f, w * x);
-  ++cnt;
-  return true;
+  LF_FOR_USED_SLOTS(cnt) {
+    const bool m = r.col[s] == c;
+    r.lam[s] = m ? fmaf(w, x, r.lam[s]) : r.lam[s];
+    found = found || m;
+  }
+  if (!found) {
+    const bool ins = cnt < kRowRegs;
+    const float wx = w * x;
+    LF_FOR_USED_SLOTS(cnt + 1) {
+      const bool m = ins && s == cnt;
+      r.col[s] = m ? c : r.col[s];
+      r.lam[s] = m ? wx : r.lam[s];
+    }
+    ovf = ovf || !ins;
+    cnt += ins ? 1 : 0;
+  }
 }
 
 constexpr int kNbPre = 8;  // neighbours whose rows are prefetched
@@ -231,28 +264,34 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int i
   }
   const Ent o0 = p0 < p1 ? A.uent_in[p0] : Ent{-1, 0.f};
   const Ent o1 = p0 + 1 < p1 ? A.uent_in[p0 + 1] : Ent{-1, 0.f};
-  Ent e0[kNbPre], e1[kNbPre];
+  const Ent o2 = p0 + 2 < p1 ? A.uent_in[p0 + 2] : Ent{-1, 0.f};
+  Ent e0[kNbPre], e1[kNbPre], e2[kNbPre];
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k) {
     e0[k] = na[k] < nb[k] ? A.uent_in[na[k]] : Ent{-1, 0.f};
     e1[k] = na[k] + 1 < nb[k] ? A.uent_in[na[k] + 1] : Ent{-1, 0.f};
+    e2[k] = na[k] + 2 < nb[k] ? A.uent_in[na[k] + 2] : Ent{-1, 0.f};
   }
   if (p1 - p0 > kRowRegs) return false;
-  if (p0 < p1) { put_regs(r, 0, o0.col, o0.val, dg * o0.val); cnt = 1; }
-  if (p0 + 1 < p1) { put_regs(r, 1, o1.col, o1.val, dg * o1.val); cnt = 2; }
-  for (int p = p0 + 2; p < p1; ++p) {
+  // own row: slots 0, 1, 2 in layer order (lam starts at L_ii * phi)
+  if (p0 < p1) { r.col[0] = o0.col; r.phi[0] = o0.val; r.lam[0] = dg * o0.val; }
+  if (p0 + 1 < p1) { r.col[1] = o1.col; r.phi[1] = o1.val; r.lam[1] = dg * o1.val; }
+  if (p0 + 2 < p1) { r.col[2] = o2.col; r.phi[2] = o2.val; r.lam[2] = dg * o2.val; }
+  cnt = min(p1 - p0, 3);
+  for (int p = p0 + 3; p < p1; ++p) {
     const Ent e = A.uent_in[p];
     put_regs(r, cnt, e.col, e.val, dg * e.val);
     ++cnt;
   }
-  bool ok = true;
+  bool ovf = false;
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k) {
-    if (na[k] < nb[k]) ok = ok && add_regs(r, cnt, e0[k].col, nw[k], e0[k].val);
-    if (na[k] + 1 < nb[k]) ok = ok && add_regs(r, cnt, e1[k].col, nw[k], e1[k].val);
-    for (int p = na[k] + 2; p < nb[k]; ++p) {
+    if (na[k] < nb[k]) add_regs(r, cnt, ovf, e0[k].col, nw[k], e0[k].val);
+    if (na[k] + 1 < nb[k]) add_regs(r, cnt, ovf, e1[k].col, nw[k], e1[k].val);
+    if (na[k] + 2 < nb[k]) add_regs(r, cnt, ovf, e2[k].col, nw[k], e2[k].val);
+    for (int p = na[k] + 3; p < nb[k]; ++p) {
       const Ent e = A.uent_in[p];
-      ok = ok && add_regs(r, cnt, e.col, nw[k], e.val);
+      add_regs(r, cnt, ovf, e.col, nw[k], e.val);
     }
   }
   for (int q = q0 + kNbPre; q < q1; ++q) {  // vertices of degree above kNbPre
@@ -260,10 +299,10 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int i
     const int a0 = A.uptr_in[le.col], a1 = A.uptr_in[le.col + 1];
     for (int p = a0; p < a1; ++p) {
       const Ent e = A.uent_in[p];
-      ok = ok && add_regs(r, cnt, e.col, le.val, e.val);
+      add_regs(r, cnt, ovf, e.col, le.val, e.val);
     }
   }
-  return ok;
+  return !ovf;
 }
 
 // ---- wide path (rows touching more than kRowRegs layers) ----------------------
@@ -449,11 +488,14 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
       if (wide < 0) {
 #pragma unroll
         for (int s = 0; s < kRowRegs; ++s) {
+          if (!__any(s < cnt)) break;
           if (r.out[s] > 0.f) {
             int rank = 0;
 #pragma unroll
-            for (int t = 0; t < kRowRegs; ++t)
+            for (int t = 0; t < kRowRegs; ++t) {
+              if (!__any(t < cnt)) break;
               rank += (r.out[t] > 0.f && r.col[t] < r.col[s]) ? 1 : 0;
+            }
             dst[rank] = Ent{r.col[s], r.out[s]};
           }
         }
