@@ -11,7 +11,17 @@ resident in HBM before the timed region.
 Prints one JSON line: field nnz-updates/s (sum over steps of the rows-of-
 interest sizes divided by wall time), the step kernel's roofline (algorithmic
 bytes per launch over its event-timed duration, against 8 TB/s), and the
-FP64 CPU oracle timed on a bounded sample of the same job.
+FP64 CPU oracle timed on a bounded sample of the same job.  Two more
+objects in the same line:
+
+* "batch": 256 torus grids of uneven size (vertex counts log-uniform in
+  [1e3, 1e5], seed counts log-uniform in [8, 512]), graph operator, 500 steps
+  + labels each, advanced as one batch and, on the same GPU, one mesh at a
+  time; nnz-updates/s of both.
+* "serving": a Poisson stream of tessellation jobs on jittered icospheres of
+  levels 5-9 (64 * 4^(level-5) seeds, cotangent operator, 1,000 steps + 3
+  Lloyd rounds + labels + dual mesh each) through the continuous-batching
+  server; p50/p99 latency from arrival to results in host memory, jobs/s.
 """
 from __future__ import annotations
 
@@ -76,6 +86,127 @@ def cpu_baseline(mesh, seeds, seconds: float, max_steps: int = 200):
                       f"one thread, operator build excluded ({dt:.1f} s)"}
 
 
+def run_batch(lfb, I, n_meshes: int, steps: int):
+    import numpy as np
+    import torch
+    items = I.batch_tori(n_meshes)
+    nv = [m.n_v for m, _ in items]
+    log(f"batch: {n_meshes} meshes, {sum(nv)} vertices, {sum(s.size for _, s in items)} seeds")
+    ctx = lfb.Context(0)
+    dev = torch.device("cuda", 0)
+    B = lfb.Batch(ctx, [(m.V, m.F) for m, _ in items], lfb.LF_OP_GRAPH, [s for _, s in items])
+    lab = torch.empty(sum(nv), dtype=torch.int32, device=dev)
+    # warm-up pass grows the storage to its working size, then the timed pass
+    for rep in range(2):
+        B.reset()
+        sk0 = B.stats()["skeleton_total"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.step(steps)
+        lfb.lf_labels(B.fh, lab)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        sk_b = B.stats()["skeleton_total"] - sk0
+    B.close()
+    log(f"batch: {t_b * 1e3:.1f} ms batched")
+    solo = []
+    for m, s in items:
+        M = lfb.Mesh(ctx, m.V, m.F, lfb.LF_OP_GRAPH)
+        solo.append((M, lfb.Fields(M, s),
+                     torch.empty(m.n_v, dtype=torch.int32, device=dev)))
+    for rep in range(2):
+        sk0 = sum(f.stats()["skeleton_total"] for _, f, _ in solo)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _, f, lab1 in solo:
+            f.reset(f.seeds())
+            f.step(steps)
+            lfb.lf_labels(f.h, lab1)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        sk_s = sum(f.stats()["skeleton_total"] for _, f, _ in solo) - sk0
+    log(f"batch: {t_s * 1e3:.1f} ms one mesh at a time")
+    for M, f, _ in solo:
+        f.close()
+        M.close()
+    return {
+        "workload": (f"{n_meshes} torus grids, vertices log-uniform [1e3,1e5], seeds log-uniform "
+                     f"[8,512], graph operator, {steps} steps + labels each"),
+        "n_vertices": int(sum(nv)),
+        "n_seeds": int(sum(s.size for _, s in items)),
+        "batched_nnz_updates_per_s": sk_b / t_b,
+        "batched_ms": t_b * 1e3,
+        "one_at_a_time_nnz_updates_per_s": sk_s / t_s,
+        "one_at_a_time_ms": t_s * 1e3,
+        "speedup": t_s / t_b,
+        "identical_work": bool(sk_b == sk_s),
+    }
+
+
+def run_serving(lfb, I, n_jobs: int, qps: float, steps: int, rounds: int, max_active: int,
+                budget_gib: float):
+    import numpy as np
+    jobs = I.serving_jobs(n_jobs, seed=0)
+    base = {}
+    inputs = []
+    for j in jobs:
+        lv = j["level"]
+        if lv not in base:
+            base[lv] = I.icosphere(lv)
+        rng = np.random.default_rng(j["seed"])
+        m = I.jitter(base[lv], rng)
+        inputs.append((m, I.seeds_uniform(m.n_v, j["n_seeds"], rng)))
+    arrivals = np.cumsum(np.random.default_rng(1).exponential(1.0 / qps, n_jobs))
+    log(f"serving: {n_jobs} jobs, levels {[j['level'] for j in jobs]}, {qps} jobs/s")
+    S = lfb.Server(0, int(budget_gib * (1 << 30)), max_active, 64)
+    # one small job first: loads the kernels and warms the allocator
+    wm, ws = inputs[0]
+    w = S.submit(wm.V, wm.F, ws, 50, 1, True, lfb.LF_OP_COTAN)
+    S.run()
+    S.release(w)
+    ids = [None] * n_jobs
+    t0 = time.perf_counter()
+    nxt = 0
+    done = 0
+    while done < n_jobs:
+        now = time.perf_counter() - t0
+        while nxt < n_jobs and arrivals[nxt] <= now:
+            m, s = inputs[nxt]
+            ids[nxt] = S.submit(m.V, m.F, s, steps, rounds, True, lfb.LF_OP_COTAN)
+            nxt += 1
+        q, a, d = S.poll()
+        done = d - 1
+        if q == 0 and a == 0 and nxt < n_jobs:
+            time.sleep(max(0.0, min(1e-3, arrivals[nxt] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    lat, qms, nsteps = [], [], 0
+    for i in ids:
+        r = S.result(i)
+        lat.append(r["latency_ms"])
+        qms.append(r["queue_ms"])
+        nsteps += r["steps"]
+        S.release(i)
+    peak = S.memory()[1]
+    S.close()
+    lat = np.array(lat)
+    log(f"serving: p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms")
+    return {
+        "workload": (f"Poisson arrivals at {qps} jobs/s of {n_jobs} jobs, jittered icospheres "
+                     f"levels 5-9, 64*4^(level-5) seeds, cotangent operator, {steps} steps + "
+                     f"{rounds} Lloyd rounds + labels + dual mesh each"),
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "mean_queue_ms": float(np.mean(qms)),
+        "jobs_per_s": n_jobs / wall,
+        "offered_jobs_per_s": qps,
+        "wall_s": wall,
+        "euler_steps": int(nsteps),
+        "max_active": max_active,
+        "hbm_budget_gib": budget_gib,
+        "peak_admitted_gib": peak / (1 << 30),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +218,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-post", action="store_true", help="skip Lloyd and dual mesh")
+    ap.add_argument("--batch-meshes", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--serve-jobs", type=int, default=24)
+    ap.add_argument("--serve-qps", type=float, default=2.0)
+    ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--serve-rounds", type=int, default=3)
+    ap.add_argument("--serve-active", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB ten times (calibrates "
                          "the HBM byte counters) and exit")
@@ -200,6 +341,13 @@ def main():
             "traffic": traffic,
         },
     }
+    f.close()
+    m.close()
+    if not args.no_batch:
+        out["batch"] = run_batch(lfb, I, args.batch_meshes, args.batch_steps)
+    if not args.no_serve:
+        out["serving"] = run_serving(lfb, I, args.serve_jobs, args.serve_qps, args.serve_steps,
+                                     args.serve_rounds, args.serve_active, args.serve_budget_gib)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, seeds, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -172,6 +172,75 @@ lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out);
  * number of launches timed since the last enable. */
 lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t* launches);
 
+/* ---- batches: many independent meshes advanced by the same launches ------
+ * A batch is the disjoint union of its meshes: mesh m's vertices follow
+ * those of meshes 0..m-1, its cells take layers off_m .. off_m + n_s[m] - 1
+ * (off_m = sum of the earlier n_s), and all meshes share one base layer
+ * above every cell.  Every row then computes exactly what it computes in a
+ * solo run of its mesh (same operands, same order of operations), so each
+ * mesh's fields are bit-identical to a solo run, while one step kernel per
+ * time step covers the whole batch.  All meshes use one operator type and
+ * one parameter set.  Inputs are host arrays, copied in. */
+typedef struct lf_batch lf_batch;
+lf_status lf_batch_create(lf_ctx* ctx, int32_t n_meshes, const double* const* V,
+                          const int32_t* n_v, const int32_t* const* F, const int32_t* n_f,
+                          int32_t op, const int32_t* const* seeds, const int32_t* n_s,
+                          const lf_params* params, lf_batch** out);
+lf_status lf_batch_destroy(lf_batch* b);
+/* The batch's field object: step it with lf_step, time it with
+ * lf_step_timing, read counters with lf_stats. */
+lf_status lf_batch_fields(lf_batch* b, lf_fields** f);
+/* Fields of one mesh in its own numbering (vertex ids from 0, cells 0..n_s-1,
+ * base n_s), size query with NULL buffers as for lf_fields_export; host. */
+lf_status lf_batch_export(lf_batch* b, int32_t mesh, int64_t* nnz, int32_t* rowptr,
+                          int32_t* col, float* val);
+/* Labels of one mesh in its own numbering (-1 where no cell), host. */
+lf_status lf_batch_labels(lf_batch* b, int32_t mesh, int32_t* labels);
+
+/* ---- serving: a continuous-batching job loop -------------------------------
+ * Jobs (a mesh, seeds and a recipe) are queued on submission and admitted
+ * while the HBM they will hold fits the budget and an active slot is free;
+ * each active job runs on a stream of its own, so the work of all active
+ * jobs overlaps on the GPU; a job's fields stay resident from admission to
+ * completion, and its memory is released as soon as it finishes, which lets
+ * queued jobs in.  A job runs `steps` Euler steps, then `lloyd_rounds` times
+ * (re-seed, re-initialise, `steps` steps), then labels and optionally the
+ * dual mesh.  Each job computes exactly what it computes alone.  The caller
+ * drives the loop with lf_server_poll (non-blocking apart from short waits
+ * at job phase boundaries). */
+typedef struct lf_server lf_server;
+typedef struct {
+  const double* V;     /* float64[n_v*3] */
+  const int32_t* F;    /* int32[n_f*3] */
+  const int32_t* seeds;/* int32[n_s] */
+  int32_t n_v, n_f, n_s, op;
+  int32_t steps, lloyd_rounds, dual_mesh, pad_;
+  lf_params params;
+} lf_job;
+/* hbm_budget: bytes the active jobs may hold (estimated per job from its
+ * size); max_active: concurrent jobs; chunk: steps issued per job per poll. */
+lf_status lf_server_create(int32_t device, int64_t hbm_budget, int32_t max_active, int32_t chunk,
+                           lf_server** out);
+lf_status lf_server_destroy(lf_server* s);
+/* Copies the job's inputs and queues it; *id identifies it.  LF_ENOMEM when
+ * the job alone exceeds the budget. */
+lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id);
+/* Admits, issues and books work; returns the queue, active and finished
+ * counts. */
+lf_status lf_server_poll(lf_server* s, int32_t* n_queued, int32_t* n_active, int32_t* n_done);
+/* Result of a finished job (LF_EBUSY while it runs): seeds int32[n_s] (final
+ * seeds), labels int32[n_v] (may be NULL), n_tri and tris int32[3*n_tri]
+ * (size query with tris NULL; 0 without dual mesh), latency_ms from
+ * submission to completion, queue_ms spent waiting for admission, steps run.
+ * Host buffers. */
+lf_status lf_server_result(lf_server* s, int64_t id, int32_t* seeds, int32_t* labels,
+                           int64_t* n_tri, int32_t* tris, double* latency_ms, double* queue_ms,
+                           int64_t* steps);
+/* Frees a finished job's results. */
+lf_status lf_server_release(lf_server* s, int64_t id);
+/* Bytes currently held by active jobs (estimate) and the peak so far. */
+lf_status lf_server_memory(lf_server* s, int64_t* in_use, int64_t* peak);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ import os
 
 import numpy as np
 
-__all__ = ["LFError", "load", "Context", "Mesh", "Fields", "default_params",
+__all__ = ["LFError", "load", "Context", "Mesh", "Batch", "Fields", "Server", "default_params",
            "LF_OP_GRAPH", "LF_OP_COTAN"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,12 +40,22 @@ class lf_params(C.Structure):
                 ("base_mode", C.c_int32), ("pad_", C.c_int32), ("capacity_hint", C.c_int64)]
 
 
+class lf_job(C.Structure):
+    _fields_ = [("V", C.c_void_p), ("F", C.c_void_p), ("seeds", C.c_void_p),
+                ("n_v", C.c_int32), ("n_f", C.c_int32), ("n_s", C.c_int32), ("op", C.c_int32),
+                ("steps", C.c_int32), ("lloyd_rounds", C.c_int32), ("dual_mesh", C.c_int32),
+                ("pad_", C.c_int32), ("params", lf_params)]
+
+
 EXPORTS = [
     "lf_last_error", "lf_params_default", "lf_ctx_create", "lf_ctx_destroy", "lf_mesh_create",
     "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
     "lf_fields_reset", "lf_fields_seeds", "lf_step", "lf_sync", "lf_fields_export",
     "lf_fields_import", "lf_labels", "lf_lloyd_reseed", "lf_dual_mesh", "lf_dual_matrix",
     "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
+    "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
+    "lf_server_create", "lf_server_destroy", "lf_server_submit", "lf_server_poll",
+    "lf_server_result", "lf_server_release", "lf_server_memory",
 ]
 
 _lib = None
@@ -100,6 +110,18 @@ def load(path: str | None = None):
         "lf_stats": (C.c_int, [V, V, V, V, V, V]),
         "lf_traffic": (C.c_int, [V, V, V]),
         "lf_step_timing": (C.c_int, [V, I32, V, V]),
+        "lf_batch_create": (C.c_int, [V, I32, V, V, V, V, I32, V, V, C.POINTER(lf_params), PV]),
+        "lf_batch_destroy": (C.c_int, [V]),
+        "lf_batch_fields": (C.c_int, [V, PV]),
+        "lf_batch_export": (C.c_int, [V, I32, V, V, V, V]),
+        "lf_batch_labels": (C.c_int, [V, I32, V]),
+        "lf_server_create": (C.c_int, [I32, I64, I32, I32, PV]),
+        "lf_server_destroy": (C.c_int, [V]),
+        "lf_server_submit": (C.c_int, [V, C.POINTER(lf_job), V]),
+        "lf_server_poll": (C.c_int, [V, V, V, V]),
+        "lf_server_result": (C.c_int, [V, I64, V, V, V, V, V, V, V]),
+        "lf_server_release": (C.c_int, [V, I64]),
+        "lf_server_memory": (C.c_int, [V, V, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -266,6 +288,86 @@ def lf_step_timing(f, enable: int):
     return ms.value, n.value
 
 
+def lf_batch_create(ctx, meshes, op: int, seeds, params: lf_params | None = None):
+    """meshes: list of (V float64 (n,3), F int32 (m,3)); seeds: list of int32."""
+    n = len(meshes)
+    Vs = [np.ascontiguousarray(V, np.float64) for V, _ in meshes]
+    Fs = [np.ascontiguousarray(F, np.int32) for _, F in meshes]
+    Ss = [np.ascontiguousarray(s, np.int32) for s in seeds]
+    Vp = (C.c_void_p * n)(*[v.ctypes.data for v in Vs])
+    Fp = (C.c_void_p * n)(*[f.ctypes.data for f in Fs])
+    Sp = (C.c_void_p * n)(*[s.ctypes.data for s in Ss])
+    nv = np.array([v.shape[0] for v in Vs], np.int32)
+    nf = np.array([f.shape[0] for f in Fs], np.int32)
+    ns = np.array([s.size for s in Ss], np.int32)
+    h = C.c_void_p()
+    _check(load().lf_batch_create(ctx, n, Vp, nv.ctypes.data, Fp, nf.ctypes.data, op, Sp,
+                                  ns.ctypes.data,
+                                  C.byref(params) if params is not None else None, C.byref(h)))
+    return h
+
+
+def lf_batch_destroy(b):
+    _check(load().lf_batch_destroy(b))
+
+
+def lf_batch_fields(b):
+    h = C.c_void_p()
+    _check(load().lf_batch_fields(b, C.byref(h)))
+    return h
+
+
+def lf_batch_export(b, mesh: int, rowptr=None, col=None, val=None):
+    nnz = C.c_int64()
+    _check(load().lf_batch_export(b, mesh, C.byref(nnz), _ptr(rowptr)[0], _ptr(col)[0],
+                                  _ptr(val)[0]))
+    return nnz.value
+
+
+def lf_batch_labels(b, mesh: int, out: np.ndarray):
+    _check(load().lf_batch_labels(b, mesh, out.ctypes.data))
+
+
+def lf_server_create(device: int, hbm_budget: int, max_active: int, chunk: int):
+    h = C.c_void_p()
+    _check(load().lf_server_create(device, hbm_budget, max_active, chunk, C.byref(h)))
+    return h
+
+
+def lf_server_destroy(s):
+    _check(load().lf_server_destroy(s))
+
+
+def lf_server_submit(s, job: lf_job):
+    i = C.c_int64()
+    _check(load().lf_server_submit(s, C.byref(job), C.byref(i)))
+    return i.value
+
+
+def lf_server_poll(s):
+    q, a, d = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().lf_server_poll(s, C.byref(q), C.byref(a), C.byref(d)))
+    return q.value, a.value, d.value
+
+
+def lf_server_result(s, job_id: int, seeds=None, labels=None, tris=None):
+    """Returns (n_tri, latency_ms, queue_ms, steps)."""
+    nt, lat, qu, st = C.c_int64(), C.c_double(), C.c_double(), C.c_int64()
+    _check(load().lf_server_result(s, job_id, _ptr(seeds)[0], _ptr(labels)[0], C.byref(nt),
+                                   _ptr(tris)[0], C.byref(lat), C.byref(qu), C.byref(st)))
+    return nt.value, lat.value, qu.value, st.value
+
+
+def lf_server_release(s, job_id: int):
+    _check(load().lf_server_release(s, job_id))
+
+
+def lf_server_memory(s):
+    a, b = C.c_int64(), C.c_int64()
+    _check(load().lf_server_memory(s, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
 # ---- owners ----------------------------------------------------------------------
 
 class Context:
@@ -313,6 +415,125 @@ class Mesh:
     def close(self):
         if self.h:
             lf_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _exiting:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent meshes stepped together; results per mesh in its own
+    numbering."""
+
+    def __init__(self, ctx: Context, meshes, op: int, seeds, params: lf_params | None = None):
+        self.ctx = ctx
+        self.n_v = [int(V.shape[0]) for V, _ in meshes]
+        self.n_s = [int(np.asarray(s).size) for s in seeds]
+        self.h = lf_batch_create(ctx.h, meshes, op, seeds, params)
+        self.fh = lf_batch_fields(self.h)
+
+    def step(self, n: int = 1):
+        lf_step(self.fh, n)
+
+    def reset(self):
+        """Back to the initial fields of every mesh (seeds kept)."""
+        s = np.zeros(sum(self.n_s), np.int32)
+        lf_fields_seeds(self.fh, s)
+        lf_fields_reset(self.fh, s)
+
+    def export(self, m: int):
+        nnz = lf_batch_export(self.h, m)
+        rp = np.zeros(self.n_v[m] + 1, np.int32)
+        col = np.zeros(nnz, np.int32)
+        val = np.zeros(nnz, np.float32)
+        lf_batch_export(self.h, m, rp, col, val)
+        return rp, col, val
+
+    def labels(self, m: int):
+        out = np.zeros(self.n_v[m], np.int32)
+        lf_batch_labels(self.h, m, out)
+        return out
+
+    def stats(self):
+        return lf_stats(self.fh)
+
+    def timing(self, enable: int = -1):
+        return lf_step_timing(self.fh, enable)
+
+    def close(self):
+        if self.h:
+            lf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _exiting:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching job loop on one GPU (see lf_server_* in lf.h)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_active: int = 8,
+                 chunk: int = 64):
+        self.h = lf_server_create(device, hbm_budget, max_active, chunk)
+        self.shape = {}
+
+    def submit(self, V, F, seeds, steps: int, lloyd_rounds: int = 0, dual_mesh: bool = False,
+               op: int = LF_OP_GRAPH, params: lf_params | None = None) -> int:
+        V = np.ascontiguousarray(V, np.float64)
+        F = np.ascontiguousarray(F, np.int32)
+        S = np.ascontiguousarray(seeds, np.int32)
+        j = lf_job()
+        j.V, j.F, j.seeds = V.ctypes.data, F.ctypes.data, S.ctypes.data
+        j.n_v, j.n_f, j.n_s, j.op = V.shape[0], F.shape[0], S.size, op
+        j.steps, j.lloyd_rounds, j.dual_mesh = steps, lloyd_rounds, int(bool(dual_mesh))
+        j.params = params if params is not None else default_params()
+        i = lf_server_submit(self.h, j)
+        self.shape[i] = (V.shape[0], S.size)
+        return i
+
+    def poll(self):
+        return lf_server_poll(self.h)
+
+    def run(self, sleep_s: float = 0.0):
+        """Polls until every submitted job has finished."""
+        import time
+        while True:
+            q, a, _ = self.poll()
+            if q == 0 and a == 0:
+                return
+            if sleep_s:
+                time.sleep(sleep_s)
+
+    def result(self, job_id: int):
+        """dict(seeds, labels, tris, latency_ms, queue_ms, steps)."""
+        n_v, n_s = self.shape[job_id]
+        nt, _, _, _ = lf_server_result(self.h, job_id)
+        seeds = np.zeros(n_s, np.int32)
+        labels = np.zeros(n_v, np.int32)
+        tris = np.zeros((nt, 3), np.int32)
+        nt, lat, qu, st = lf_server_result(self.h, job_id, seeds, labels, tris)
+        return dict(seeds=seeds, labels=labels, tris=tris, latency_ms=lat, queue_ms=qu, steps=st)
+
+    def release(self, job_id: int):
+        lf_server_release(self.h, job_id)
+        self.shape.pop(job_id, None)
+
+    def memory(self):
+        return lf_server_memory(self.h)
+
+    def close(self):
+        if self.h:
+            lf_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

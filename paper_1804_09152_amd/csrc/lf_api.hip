@@ -313,6 +313,8 @@ lf_status lf_fields_destroy(lf_fields* f) {
   hipFree(f->stats);
   hipFree(f->flags);
   if (f->flags_host) hipHostFree(f->flags_host);
+  if (f->stats_pinned) hipHostFree(f->stats_pinned);
+  if (f->done_ev) hipEventDestroy(f->done_ev);
   for (auto e : f->ev0) hipEventDestroy(e);
   for (auto e : f->ev1) hipEventDestroy(e);
   dual_release(f);
@@ -400,83 +402,126 @@ static hipEvent_t pool_event(std::vector<hipEvent_t>& pool, size_t k) {
   return pool[k];
 }
 
+}  // extern "C"
+
+namespace lf {
+
+// Enqueues n steps on the context stream, then asynchronous copies of the
+// failure flags and per-step counters and an event; does not wait.
+lf_status step_issue(lf_fields* f, int64_t n) {
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  hipStream_t s = f->mesh->ctx->stream;
+  if (n > f->stats_cap) {
+    const int64_t c = std::max<int64_t>(n, 2 * f->stats_cap);
+    StepStats* p = nullptr;
+    LF_HIP(dalloc(&p, c));
+    LF_HIP(hipStreamSynchronize(s));
+    (void)hipFree(f->stats);
+    f->stats = p;
+    f->stats_cap = c;
+  }
+  if (n > f->stats_pinned_cap) {
+    const int64_t c = std::max<int64_t>(n, 2 * f->stats_pinned_cap);
+    StepStats* p = nullptr;
+    LF_HIP(hipHostMalloc((void**)&p, sizeof(StepStats) * c, 0));
+    LF_HIP(hipStreamSynchronize(s));
+    if (f->stats_pinned) (void)hipHostFree(f->stats_pinned);
+    f->stats_pinned = p;
+    f->stats_pinned_cap = c;
+  }
+  if (!f->done_ev) LF_HIP(hipEventCreateWithFlags(&f->done_ev, hipEventDisableTiming));
+  LF_HIP(launch_reset_flags(f->flags, f->stats, (int)n, s));
+  size_t used = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    StepArgs a = make_args(f, (int)((f->cur + k) & 1));
+    a.stats = f->stats + k;
+    a.step_idx = (uint32_t)k;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (f->timing) {
+      t0 = pool_event(f->ev0, used);
+      t1 = pool_event(f->ev1, used);
+      if (t0 && t1) ++used;
+    }
+    LF_HIP(launch_step(a, s, t0, t1));
+  }
+  LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
+  LF_HIP(hipMemcpyAsync(f->stats_pinned, f->stats, sizeof(StepStats) * n, hipMemcpyDeviceToHost, s));
+  LF_HIP(hipEventRecord(f->done_ev, s));
+  f->pending = n;
+  f->ev_issued = used;
+  return LF_OK;
+}
+
+bool step_ready(lf_fields* f) {
+  return f->pending == 0 || hipEventQuery(f->done_ev) == hipSuccess;
+}
+
+// Waits for the issued steps and books the completed ones.  *remaining is
+// the number of issued steps that did not complete (storage was grown: issue
+// them again).
+lf_status step_complete(lf_fields* f, int64_t* remaining) {
+  *remaining = 0;
+  if (f->pending == 0) return LF_OK;
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  LF_HIP(hipEventSynchronize(f->done_ev));
+  for (size_t k = 0; k < f->ev_issued; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, f->ev0[k], f->ev1[k]) == hipSuccess) {
+      f->timed_ms += ms;
+      f->timed_launches++;
+    }
+  }
+  const int64_t n = f->pending;
+  f->pending = 0;
+  const StepFlags fl = *f->flags_host;
+  // steps before the first failed one are complete; the later ones did nothing
+  const int64_t ok = fl.poisoned ? std::min<int64_t>(fl.fail_step, n) : n;
+  for (int64_t k = 0; k < ok; ++k) {
+    const StepStats& t = f->stats_pinned[k];
+    f->skel_total += t.skel;
+    f->out_total += t.out;
+    f->in_total += t.in;
+    f->events_total += t.events;
+  }
+  f->cur = (int)((f->cur + ok) & 1);
+  f->steps += ok;
+  *remaining = n - ok;
+  if (!fl.poisoned) return LF_OK;
+  if (fl.poisoned & 2u) {
+    clear_step_state(f);
+    return fail(LF_ECAPACITY, "a vertex touches more than 64 layers");
+  }
+  if (fl.poisoned & 4u) {
+    clear_step_state(f);
+    return fail(LF_EDEVICE, "step look-back did not complete");
+  }
+  if (fl.poisoned & 8u) {
+    lf_status st = grow_wide(f);
+    if (st) return st;
+  }
+  if (fl.poisoned & 1u) {
+    lf_status st = grow(f, (int64_t)fl.need);
+    if (st) return st;
+  }
+  return clear_step_state(f);
+}
+
+}  // namespace lf
+
+extern "C" {
+
 lf_status lf_step(lf_fields* f, int32_t n) {
   if (!f || n < 0) return fail(LF_EINVAL, "invalid argument");
   if (n == 0) return LF_OK;
-  LF_HIP(hipSetDevice(f->mesh->ctx->device));
-  hipStream_t s = f->mesh->ctx->stream;
   int64_t remaining = n;
-  int grows = 0;
-  while (remaining > 0) {
-    if (remaining > f->stats_cap) {
-      const int64_t c = std::max<int64_t>(remaining, 2 * f->stats_cap);
-      StepStats* p = nullptr;
-      LF_HIP(dalloc(&p, c));
-      hipFree(f->stats);
-      f->stats = p;
-      f->stats_cap = c;
-    }
-    LF_HIP(launch_reset_flags(f->flags, f->stats, (int)remaining, s));
-    size_t used = 0;
-    for (int64_t k = 0; k < remaining; ++k) {
-      StepArgs a = make_args(f, (int)((f->cur + k) & 1));
-      a.stats = f->stats + k;
-      a.step_idx = (uint32_t)k;
-      hipEvent_t t0 = nullptr, t1 = nullptr;
-      if (f->timing) {
-        t0 = pool_event(f->ev0, used);
-        t1 = pool_event(f->ev1, used);
-        if (t0 && t1) ++used;
-      }
-      LF_HIP(launch_step(a, s, t0, t1));
-    }
-    f->stats_host.resize((size_t)remaining);
-    LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
-    LF_HIP(hipMemcpyAsync(f->stats_host.data(), f->stats, sizeof(StepStats) * remaining,
-                          hipMemcpyDeviceToHost, s));
-    LF_HIP(hipStreamSynchronize(s));
-    for (size_t k = 0; k < used; ++k) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, f->ev0[k], f->ev1[k]) == hipSuccess) {
-        f->timed_ms += ms;
-        f->timed_launches++;
-      }
-    }
-    const StepFlags fl = *f->flags_host;
-    // steps before the first failed one are complete; the later ones did nothing
-    const int64_t ok = fl.poisoned ? std::min<int64_t>(fl.fail_step, remaining) : remaining;
-    for (int64_t k = 0; k < ok; ++k) {
-      const StepStats& t = f->stats_host[(size_t)k];
-      f->skel_total += t.skel;
-      f->out_total += t.out;
-      f->in_total += t.in;
-      f->events_total += t.events;
-    }
-    f->cur = (int)((f->cur + ok) & 1);
-    f->steps += ok;
-    remaining -= ok;
-    if (!fl.poisoned) break;
-    if (fl.poisoned & 2u) {
-      clear_step_state(f);
-      return fail(LF_ECAPACITY, "a vertex touches more than 64 layers");
-    }
-    if (fl.poisoned & 4u) {
-      clear_step_state(f);
-      return fail(LF_EDEVICE, "step look-back did not complete");
-    }
-    if (++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
-    if (fl.poisoned & 8u) {
-      lf_status st = grow_wide(f);
-      if (st) return st;
-    }
-    if (fl.poisoned & 1u) {
-      lf_status st = grow(f, (int64_t)fl.need);
-      if (st) return st;
-    }
-    lf_status st = clear_step_state(f);
+  for (int grows = 0;; ++grows) {
+    if (grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
+    lf_status st = step_issue(f, remaining);
     if (st) return st;
+    st = step_complete(f, &remaining);
+    if (st) return st;
+    if (remaining == 0) return LF_OK;
   }
-  return LF_OK;
 }
 
 lf_status lf_sync(lf_fields* f) {

@@ -125,6 +125,12 @@ hipError_t launch_labels(const int32_t* uptr, const Ent* uent, int32_t n_v, int3
 // releases the dual-mesh state of a field object
 void dual_release(lf_fields* f);
 
+// asynchronous stepping: issue n steps; poll; book them (remaining > 0 when
+// storage had to grow and those steps must be issued again)
+lf_status step_issue(lf_fields* f, int64_t n);
+bool step_ready(lf_fields* f);
+lf_status step_complete(lf_fields* f, int64_t* remaining);
+
 // device allocation helpers
 template <class T>
 hipError_t dalloc(T** p, int64_t n) {
@@ -175,7 +181,11 @@ struct lf_fields {
   lf::StepFlags* flags_host;   // pinned
   lf::StepStats* stats;        // per-step counters of one call
   int64_t stats_cap;
-  std::vector<lf::StepStats> stats_host;
+  lf::StepStats* stats_pinned; // their host copy
+  int64_t stats_pinned_cap;
+  int64_t pending;             // steps issued and not yet booked
+  hipEvent_t done_ev;          // recorded after the copies of an issued chunk
+  size_t ev_issued;            // timing events used by the issued chunk
   int32_t n_tiles;
   // totals over completed steps
   long long steps, grow_events;

@@ -49,3 +49,34 @@ def test_binding_fails_loudly_without_library(tmp_path):
             lfb.load(str(tmp_path / "nope.so"))
     finally:
         lfb._lib = saved
+
+
+def test_server_host_logic_without_gpu():
+    """Queueing, budget check and result states touch no GPU until a poll."""
+    import numpy as np
+    import paper_1804_09152_amd as lfb
+    from paper_1804_09152_amd import inputs as I
+    if not os.path.exists(lfb.LIB_PATH):
+        pytest.skip("liblf.so not built")
+    mesh = I.torus_grid(16, 16)
+    seeds = np.array([0, 40, 200], np.int32)
+    with pytest.raises(lfb.LFError) as e:
+        lfb.Server(0, 0, 1, 1)
+    assert e.value.status == 1
+    S = lfb.Server(0, 3 << 20, 2, 8)
+    i = S.submit(mesh.V, mesh.F, seeds, steps=10)
+    big = I.torus_grid(200, 200)
+    with pytest.raises(lfb.LFError) as e:
+        S.submit(big.V, big.F, seeds, steps=10)
+    assert e.value.status == 2  # alone above the budget
+    with pytest.raises(lfb.LFError) as e:
+        lfb.lf_server_result(S.h, i)
+    assert e.value.status == 5  # queued, not finished
+    with pytest.raises(lfb.LFError) as e:
+        lfb.lf_server_release(S.h, i)
+    assert e.value.status == 5
+    with pytest.raises(lfb.LFError) as e:
+        lfb.lf_server_result(S.h, 12345)
+    assert e.value.status == 1
+    assert S.memory() == (0, 0)
+    S.close()  # queued jobs are dropped
