@@ -18,8 +18,7 @@
  *  - "Host or device" buffers: arguments documented with `is_device_ptr`
  *    take caller-owned memory; device pointers must stay valid until the
  *    call returns (all calls synchronise with the context stream before
- *    returning, except lf_step which is asynchronous unless it has to grow
- *    storage).
+ *    returning).
  *  - Handles are created and destroyed explicitly by their owner.  A context
  *    serves one host thread at a time; calls on one context serialise on its
  *    stream.
@@ -52,7 +51,10 @@ typedef enum { LF_OP_GRAPH = 0, LF_OP_COTAN = 1 } lf_operator;
  * 0 keeps every positive entry); tau: dual-mesh threshold (0.25).
  * base_mode 0: the base layer couples to cells through the gradient term
  * and an antisymmetric band term only; 1: the base is an ordinary layer.
- * capacity_hint: initial field storage in entries (0 = 3 per vertex). */
+ * capacity_hint: initial size, in entries, of the overflow area that holds
+ * the rows with more than four entries (the library keeps the fields as
+ * fixed-width rows of four entries; 0 = max(4096, n_v / 16)); it grows on
+ * demand. */
 typedef struct {
   double w, a, e, mu, dt, theta, tau;
   int32_t base_mode;
@@ -103,10 +105,11 @@ lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds);
 /* n_steps explicit Euler steps of Algorithm 1 (Jacobi form): field
  * Laplacian L_t = Phi L^T (row form: L U), rows of interest, update with
  * clamping to [0,1], column normalisation, then the theta prune.  Runs on the
- * context stream; output storage grows on the device side (an overflowing
- * step is detected on the GPU, storage grows by 20% or more and the step is
- * replayed).  LF_ECAPACITY if a vertex touches more layers than the row
- * limit (64) or storage cannot grow. */
+ * context stream and waits for it; a step whose rows overflow the overflow
+ * area is detected on the GPU, the area grows by 20% or more and the step is
+ * replayed, so results never depend on capacities.  LF_ECAPACITY if a
+ * vertex touches more layers than the row limit (64) or storage cannot
+ * grow. */
 lf_status lf_step(lf_fields* f, int32_t n_steps);
 lf_status lf_sync(lf_fields* f);
 

@@ -43,16 +43,18 @@ struct DevBuf {
 static StepArgs make_args(lf_fields* f, int parity) {
   StepArgs a;
   lf_mesh* m = f->mesh;
-  a.lptr = m->lptr;
-  a.lent = m->lent;
+  a.slices = m->slices;
+  a.lell = m->lell;
   a.ldiag = m->ldiag;
-  a.uptr_in = f->uptr[parity];
-  a.uent_in = f->uent[parity];
-  a.uptr_out = f->uptr[1 - parity];
-  a.uent_out = f->uent[1 - parity];
+  a.u_in = f->ell[parity];
+  a.u_out = f->ell[1 - parity];
+  a.ovf_in = f->ovf[parity];
+  a.ovf_out = f->ovf[1 - parity];
+  a.ovf_cap = f->ovf_cap;
+  a.ovf_ctr = f->counters + (1 - parity);
+  a.ovf_ctr_next = f->counters + parity;
   a.n_v = m->n_v;
-  a.n_tiles = f->n_tiles;
-  a.cap = f->cap;
+  a.n_slices = m->n_slices;
   a.c.a = (float)f->P.a;
   a.c.w = (float)f->P.w;
   a.c.e = (float)f->P.e;
@@ -61,23 +63,21 @@ static StepArgs make_args(lf_fields* f, int parity) {
   a.c.theta = (float)f->P.theta;
   a.c.base_mode = f->P.base_mode;
   a.c.n_s = f->n_s;
-  a.status = f->status[parity];
-  a.status_next = f->status[1 - parity];
-  a.ticket = f->tickets + parity;
-  a.ticket_next = f->tickets + (1 - parity);
   a.wide = f->wide;
   a.wide_cap = f->wide_cap;
   a.pad_ = 0;
-  a.wide_ctr = f->tickets + 2 + parity;
-  a.wide_ctr_next = f->tickets + 2 + (1 - parity);
+  a.wide_ctr = f->counters + 2 + (1 - parity);
+  a.wide_ctr_next = f->counters + 2 + parity;
   a.flags = f->flags;
+  a.parts = nullptr;
+  a.step_idx = 0;
+  a.pad2_ = 0;
   return a;
 }
 
 static lf_status clear_step_state(lf_fields* f) {
   hipStream_t s = f->mesh->ctx->stream;
-  for (int k = 0; k < 2; ++k) LF_HIP(launch_fill_u64(f->status[k], f->n_tiles, 0ull, s));
-  LF_HIP(launch_fill_i32((int32_t*)f->tickets, 4, 0, s));
+  LF_HIP(launch_fill_i32((int32_t*)f->counters, 4, 0, s));
   LF_HIP(launch_reset_flags(f->flags, nullptr, 0, s));
   return LF_OK;
 }
@@ -89,47 +89,61 @@ static lf_status grow_wide(lf_fields* f) {
   WideRow* p = nullptr;
   LF_HIP(dalloc(&p, c));
   LF_HIP(hipStreamSynchronize(f->mesh->ctx->stream));
-  hipFree(f->wide);
+  (void)hipFree(f->wide);
   f->wide = p;
   f->wide_cap = (int32_t)c;
   f->grow_events++;
   return LF_OK;
 }
 
-static lf_status current_nnz(lf_fields* f, int64_t* nnz) {
-  int32_t v = 0;
-  hipStream_t s = f->mesh->ctx->stream;
-  LF_HIP(hipMemcpyAsync(&v, f->uptr[f->cur] + f->mesh->n_v, sizeof(int32_t),
-                        hipMemcpyDeviceToHost, s));
-  LF_HIP(hipStreamSynchronize(s));
-  *nnz = v;
-  return LF_OK;
-}
-
-// grows both field buffers to at least `need` entries (plus 20%), keeping
-// the current state
+// grows both overflow areas to at least `need` entries (plus 20%), keeping
+// the current one's contents
 static lf_status grow(lf_fields* f, int64_t need) {
   const int64_t lim = (1ll << 31) - 1;
-  int64_t ncap = std::max(need + need / 5, f->cap + f->cap / 5) + 1024;
-  if (need > lim) return fail(LF_ECAPACITY, "field storage would exceed 2^31 entries");
+  if (need > lim) return fail(LF_ECAPACITY, "overflow area would exceed 2^31 entries");
+  int64_t ncap = std::max(need + need / 5, f->ovf_cap + f->ovf_cap / 5) + 1024;
   ncap = std::min(ncap, lim);
-  int64_t nnz = 0;
-  lf_status st = current_nnz(f, &nnz);
-  if (st) return st;
   hipStream_t s = f->mesh->ctx->stream;
   DevBuf<Ent> a, b;
   LF_HIP(a.alloc(ncap));
   LF_HIP(b.alloc(ncap));
-  if (nnz > 0)
-    LF_HIP(hipMemcpyAsync(a.p, f->uent[f->cur], sizeof(Ent) * nnz, hipMemcpyDeviceToDevice, s));
+  LF_HIP(hipMemcpyAsync(a.p, f->ovf[f->cur], sizeof(Ent) * f->ovf_cap, hipMemcpyDeviceToDevice, s));
   LF_HIP(hipStreamSynchronize(s));
-  hipFree(f->uent[0]);
-  hipFree(f->uent[1]);
-  f->uent[f->cur] = a.release();
-  f->uent[1 - f->cur] = b.release();
-  f->cap = ncap;
+  (void)hipFree(f->ovf[0]);
+  (void)hipFree(f->ovf[1]);
+  f->ovf[f->cur] = a.release();
+  f->ovf[1 - f->cur] = b.release();
+  f->ovf_cap = ncap;
   f->grow_events++;
   return clear_step_state(f);
+}
+
+// CSR buffer for at least n entries (contents not kept)
+static lf_status reserve_csr(lf_fields* f, int64_t n) {
+  if (n <= f->csr_cap && f->uent) return LF_OK;
+  const int64_t c = std::max<int64_t>(n + n / 5, f->mesh->n_v) + 1024;
+  Ent* p = nullptr;
+  LF_HIP(dalloc(&p, c));
+  LF_HIP(hipStreamSynchronize(f->mesh->ctx->stream));
+  (void)hipFree(f->uent);
+  f->uent = p;
+  f->csr_cap = c;
+  return LF_OK;
+}
+
+lf_status fields_csr(lf_fields* f, const int32_t** uptr, const Ent** uent) {
+  if (!f->csr_valid) {
+    hipStream_t s = f->mesh->ctx->stream;
+    const int32_t n_v = f->mesh->n_v;
+    lf_status st = reserve_csr(f, f->nnz);
+    if (st) return st;
+    LF_HIP(ell_to_csr_ptr(f->ell[f->cur], n_v, f->owner, f->uptr, f->scan_tmp, s));
+    LF_HIP(ell_to_csr_fill(f->ell[f->cur], f->ovf[f->cur], n_v, f->uptr, f->uent, s));
+    f->csr_valid = true;
+  }
+  *uptr = f->uptr;
+  *uent = f->uent;
+  return LF_OK;
 }
 
 }  // namespace lf
@@ -213,7 +227,22 @@ lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_
   int64_t nnz = 0;
   int bad = 0;
   LF_HIP(build_operator(dV.p, dF.p, n_v, n_f, op, &lptr, &lent, &ldiag, &nnz, &bad, s));
-  if (bad) return fail(LF_EINVAL, "zero-area face: cotangent weights undefined");
+  if (bad) {
+    (void)hipFree(lptr);
+    (void)hipFree(lent);
+    (void)hipFree(ldiag);
+    return fail(LF_EINVAL, "zero-area face: cotangent weights undefined");
+  }
+  Slice* slices = nullptr;
+  Ent* lell = nullptr;
+  int64_t n_ell = 0;
+  hipError_t e = build_slices(lptr, lent, n_v, &slices, &lell, &n_ell, s);
+  if (e != hipSuccess) {
+    (void)hipFree(lptr);
+    (void)hipFree(lent);
+    (void)hipFree(ldiag);
+    return hip_fail(e, "operator slices");
+  }
   lf_mesh* m = new lf_mesh();
   m->ctx = ctx;
   m->n_v = n_v;
@@ -225,6 +254,9 @@ lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_
   m->lent = lent;
   m->ldiag = ldiag;
   m->nnz_off = nnz;
+  m->slices = slices;
+  m->lell = lell;
+  m->n_slices = (n_v + kSlice - 1) / kSlice;
   m->Vh.assign(V, V + 3ll * n_v);
   m->Fh.assign(F, F + 3ll * n_f);
   *out = m;
@@ -234,11 +266,13 @@ lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_
 lf_status lf_mesh_destroy(lf_mesh* m) {
   if (!m) return LF_OK;
   hipSetDevice(m->ctx->device);
-  hipFree(m->V);
-  hipFree(m->F);
-  hipFree(m->lptr);
-  hipFree(m->lent);
-  hipFree(m->ldiag);
+  (void)hipFree(m->V);
+  (void)hipFree(m->F);
+  (void)hipFree(m->lptr);
+  (void)hipFree(m->lent);
+  (void)hipFree(m->ldiag);
+  (void)hipFree(m->slices);
+  (void)hipFree(m->lell);
   delete m;
   return LF_OK;
 }
@@ -291,7 +325,9 @@ static lf_status init_fields(lf_fields* f) {
   LF_HIP(launch_fill_i32(f->owner, n_v, f->n_s, s));
   LF_HIP(launch_scatter_owner(f->d_seeds, f->n_s, f->owner, s));
   f->cur = 0;
-  LF_HIP(launch_init_fields(f->owner, n_v, f->uptr[0], f->uent[0], s));
+  LF_HIP(launch_init_fields(f->owner, n_v, f->ell[0], s));
+  f->nnz = n_v;
+  f->csr_valid = false;
   lf_status st = clear_step_state(f);
   if (st) return st;
   LF_HIP(hipStreamSynchronize(s));
@@ -300,23 +336,26 @@ static lf_status init_fields(lf_fields* f) {
 
 lf_status lf_fields_destroy(lf_fields* f) {
   if (!f) return LF_OK;
-  hipSetDevice(f->mesh->ctx->device);
+  (void)hipSetDevice(f->mesh->ctx->device);
   for (int k = 0; k < 2; ++k) {
-    hipFree(f->uptr[k]);
-    hipFree(f->uent[k]);
-    hipFree(f->status[k]);
+    (void)hipFree(f->ell[k]);
+    (void)hipFree(f->ovf[k]);
   }
-  hipFree(f->d_seeds);
-  hipFree(f->owner);
-  hipFree(f->tickets);
-  hipFree(f->wide);
-  hipFree(f->stats);
-  hipFree(f->flags);
-  if (f->flags_host) hipHostFree(f->flags_host);
-  if (f->stats_pinned) hipHostFree(f->stats_pinned);
-  if (f->done_ev) hipEventDestroy(f->done_ev);
-  for (auto e : f->ev0) hipEventDestroy(e);
-  for (auto e : f->ev1) hipEventDestroy(e);
+  (void)hipFree(f->d_seeds);
+  (void)hipFree(f->owner);
+  (void)hipFree(f->counters);
+  (void)hipFree(f->wide);
+  (void)hipFree(f->parts);
+  (void)hipFree(f->stats);
+  (void)hipFree(f->flags);
+  (void)hipFree(f->uptr);
+  (void)hipFree(f->uent);
+  (void)hipFree(f->scan_tmp);
+  if (f->flags_host) (void)hipHostFree(f->flags_host);
+  if (f->stats_pinned) (void)hipHostFree(f->stats_pinned);
+  if (f->done_ev) (void)hipEventDestroy(f->done_ev);
+  for (auto e : f->ev0) (void)hipEventDestroy(e);
+  for (auto e : f->ev1) (void)hipEventDestroy(e);
   dual_release(f);
   delete f;
   return LF_OK;
@@ -340,24 +379,24 @@ lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const 
   f->n_s = n_s;
   f->P = prm;
   f->seeds.assign(seeds, seeds + n_s);
-  f->n_tiles = (m->n_v + kBlock - 1) / kBlock;
-  int64_t cap = prm.capacity_hint > 0 ? prm.capacity_hint : 3ll * m->n_v;
-  cap = std::max<int64_t>(cap, m->n_v);
-  f->cap = std::min<int64_t>(cap, (1ll << 31) - 1);
+  const int64_t hint = prm.capacity_hint > 0 ? prm.capacity_hint
+                                             : std::max<int64_t>(4096, m->n_v / 16);
+  f->ovf_cap = std::min<int64_t>(hint, (1ll << 31) - 1);
   hipError_t e = hipSuccess;
 #define ALLOC(x, n)                          \
   if (e == hipSuccess) e = dalloc(&(x), (n));
   ALLOC(f->d_seeds, n_s);
   ALLOC(f->owner, m->n_v);
   for (int k = 0; k < 2; ++k) {
-    ALLOC(f->uptr[k], m->n_v + 1);
-    ALLOC(f->uent[k], f->cap);
-    ALLOC(f->status[k], f->n_tiles);
+    ALLOC(f->ell[k], m->n_v);
+    ALLOC(f->ovf[k], f->ovf_cap);
   }
-  ALLOC(f->tickets, 4);
+  ALLOC(f->counters, 4);
   f->wide_cap = 1024;
   ALLOC(f->wide, f->wide_cap);
   ALLOC(f->flags, 1);
+  ALLOC(f->uptr, m->n_v + 1);
+  ALLOC(f->scan_tmp, scan_tmp_elems(m->n_v));
 #undef ALLOC
   if (e == hipSuccess) e = hipHostMalloc((void**)&f->flags_host, sizeof(StepFlags), 0);
   if (e != hipSuccess) {
@@ -413,11 +452,17 @@ lf_status step_issue(lf_fields* f, int64_t n) {
   hipStream_t s = f->mesh->ctx->stream;
   if (n > f->stats_cap) {
     const int64_t c = std::max<int64_t>(n, 2 * f->stats_cap);
-    StepStats* p = nullptr;
+    StepStats *p = nullptr, *q = nullptr;
     LF_HIP(dalloc(&p, c));
+    if (dalloc(&q, c * kParts) != hipSuccess) {
+      (void)hipFree(p);
+      return fail(LF_ENOMEM, "step counters");
+    }
     LF_HIP(hipStreamSynchronize(s));
     (void)hipFree(f->stats);
+    (void)hipFree(f->parts);
     f->stats = p;
+    f->parts = q;
     f->stats_cap = c;
   }
   if (n > f->stats_pinned_cap) {
@@ -430,11 +475,11 @@ lf_status step_issue(lf_fields* f, int64_t n) {
     f->stats_pinned_cap = c;
   }
   if (!f->done_ev) LF_HIP(hipEventCreateWithFlags(&f->done_ev, hipEventDisableTiming));
-  LF_HIP(launch_reset_flags(f->flags, f->stats, (int)n, s));
+  LF_HIP(launch_reset_flags(f->flags, f->parts, n, s));
   size_t used = 0;
   for (int64_t k = 0; k < n; ++k) {
     StepArgs a = make_args(f, (int)((f->cur + k) & 1));
-    a.stats = f->stats + k;
+    a.parts = f->parts + k * kParts;
     a.step_idx = (uint32_t)k;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (f->timing) {
@@ -444,6 +489,7 @@ lf_status step_issue(lf_fields* f, int64_t n) {
     }
     LF_HIP(launch_step(a, s, t0, t1));
   }
+  LF_HIP(launch_reduce_parts(f->parts, n, f->stats, s));
   LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
   LF_HIP(hipMemcpyAsync(f->stats_pinned, f->stats, sizeof(StepStats) * n, hipMemcpyDeviceToHost, s));
   LF_HIP(hipEventRecord(f->done_ev, s));
@@ -485,15 +531,15 @@ lf_status step_complete(lf_fields* f, int64_t* remaining) {
   }
   f->cur = (int)((f->cur + ok) & 1);
   f->steps += ok;
+  if (ok > 0) {
+    f->nnz = (int64_t)f->stats_pinned[ok - 1].out;
+    f->csr_valid = false;
+  }
   *remaining = n - ok;
   if (!fl.poisoned) return LF_OK;
   if (fl.poisoned & 2u) {
     clear_step_state(f);
     return fail(LF_ECAPACITY, "a vertex touches more than 64 layers");
-  }
-  if (fl.poisoned & 4u) {
-    clear_step_state(f);
-    return fail(LF_EDEVICE, "step look-back did not complete");
   }
   if (fl.poisoned & 8u) {
     lf_status st = grow_wide(f);
@@ -533,31 +579,30 @@ lf_status lf_sync(lf_fields* f) {
 lf_status lf_fields_export(lf_fields* f, int64_t* nnz, int32_t* rowptr, int32_t* col, float* val,
                            int32_t is_dev) {
   if (!f || !nnz) return fail(LF_EINVAL, "NULL argument");
-  LF_HIP(hipSetDevice(f->mesh->ctx->device));
-  lf_status st = current_nnz(f, nnz);
-  if (st) return st;
+  *nnz = f->nnz;
   if (!rowptr && !col && !val) return LF_OK;
   if (!rowptr || !col || !val) return fail(LF_EINVAL, "rowptr, col and val must all be given");
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
   hipStream_t s = f->mesh->ctx->stream;
   const int32_t n_v = f->mesh->n_v;
+  const int32_t* up = nullptr;
+  const Ent* ue = nullptr;
+  lf_status st = fields_csr(f, &up, &ue);
+  if (st) return st;
   if (is_dev) {
-    LF_HIP(hipMemcpyAsync(rowptr, f->uptr[f->cur], sizeof(int32_t) * (n_v + 1),
-                          hipMemcpyDeviceToDevice, s));
-    LF_HIP(launch_split(f->uent[f->cur], *nnz, col, val, s));
+    LF_HIP(hipMemcpyAsync(rowptr, up, sizeof(int32_t) * (n_v + 1), hipMemcpyDeviceToDevice, s));
+    LF_HIP(launch_split(ue, *nnz, col, val, s));
   } else {
     DevBuf<int32_t> dc;
     DevBuf<float> dv;
     LF_HIP(dc.alloc(*nnz));
     LF_HIP(dv.alloc(*nnz));
-    LF_HIP(launch_split(f->uent[f->cur], *nnz, dc.p, dv.p, s));
-    LF_HIP(hipMemcpyAsync(rowptr, f->uptr[f->cur], sizeof(int32_t) * (n_v + 1),
-                          hipMemcpyDeviceToHost, s));
+    LF_HIP(launch_split(ue, *nnz, dc.p, dv.p, s));
+    LF_HIP(hipMemcpyAsync(rowptr, up, sizeof(int32_t) * (n_v + 1), hipMemcpyDeviceToHost, s));
     if (*nnz > 0) {
       LF_HIP(hipMemcpyAsync(col, dc.p, sizeof(int32_t) * *nnz, hipMemcpyDeviceToHost, s));
       LF_HIP(hipMemcpyAsync(val, dv.p, sizeof(float) * *nnz, hipMemcpyDeviceToHost, s));
     }
-    LF_HIP(hipStreamSynchronize(s));
-    return LF_OK;
   }
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
@@ -567,13 +612,10 @@ lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, con
                            const float* val, int32_t is_dev) {
   if (!f || !rowptr || (nnz > 0 && (!col || !val)) || nnz < 0)
     return fail(LF_EINVAL, "invalid argument");
+  if (nnz > (1ll << 31) - 1) return fail(LF_EINVAL, "more than 2^31 entries");
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   hipStream_t s = f->mesh->ctx->stream;
   const int32_t n_v = f->mesh->n_v;
-  if (nnz > f->cap) {
-    lf_status st = grow(f, nnz);
-    if (st) return st;
-  }
   DevBuf<int32_t> dp, dc, bad;
   DevBuf<float> dv;
   const int32_t* p = rowptr;
@@ -600,17 +642,29 @@ lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, con
     LF_HIP(hipStreamSynchronize(s));
     if (last != nnz) return fail(LF_EINVAL, "rowptr does not match nnz");
   }
+  // validated into the CSR view, then converted to fixed-width rows in the
+  // other buffer (the current fields stay intact on error)
+  f->csr_valid = false;
+  lf_status st = reserve_csr(f, nnz);
+  if (st) return st;
+  if (nnz > f->ovf_cap) {
+    st = grow(f, nnz);
+    if (st) return st;
+  }
   LF_HIP(bad.alloc(1));
-  LF_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
-  const int tgt = 1 - f->cur;
-  LF_HIP(launch_join_check(c, v, p, n_v, f->n_s + 1, nnz, f->uent[tgt], bad.p, s));
-  LF_HIP(hipMemcpyAsync(f->uptr[tgt], p, sizeof(int32_t) * (n_v + 1), hipMemcpyDeviceToDevice, s));
+  LF_HIP(launch_fill_i32(bad.p, 1, 0, s));
+  LF_HIP(launch_join_check(c, v, p, n_v, f->n_s + 1, nnz, f->uent, bad.p, s));
   int32_t hb = 0;
   LF_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   LF_HIP(hipStreamSynchronize(s));
   if (hb) return fail(LF_EINVAL, "imported fields are not canonical (code " + std::to_string(hb) + ")");
+  LF_HIP(hipMemcpyAsync(f->uptr, p, sizeof(int32_t) * (n_v + 1), hipMemcpyDeviceToDevice, s));
+  const int tgt = 1 - f->cur;
+  LF_HIP(csr_to_ell(f->uptr, f->uent, n_v, f->ell[tgt], f->ovf[tgt], s));
   f->cur = tgt;
-  lf_status st = clear_step_state(f);
+  f->nnz = nnz;
+  f->csr_valid = true;
+  st = clear_step_state(f);
   if (st) return st;
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
@@ -621,12 +675,16 @@ lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_dev) {
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   hipStream_t s = f->mesh->ctx->stream;
   const int32_t n_v = f->mesh->n_v;
+  const int32_t* up = nullptr;
+  const Ent* ue = nullptr;
+  lf_status st = fields_csr(f, &up, &ue);
+  if (st) return st;
   if (is_dev) {
-    LF_HIP(launch_labels(f->uptr[f->cur], f->uent[f->cur], n_v, f->n_s, labels, s));
+    LF_HIP(launch_labels(up, ue, n_v, f->n_s, labels, s));
   } else {
     DevBuf<int32_t> d;
     LF_HIP(d.alloc(n_v));
-    LF_HIP(launch_labels(f->uptr[f->cur], f->uent[f->cur], n_v, f->n_s, d.p, s));
+    LF_HIP(launch_labels(up, ue, n_v, f->n_s, d.p, s));
     LF_HIP(hipMemcpyAsync(labels, d.p, sizeof(int32_t) * n_v, hipMemcpyDeviceToHost, s));
     LF_HIP(hipStreamSynchronize(s));
     return LF_OK;
@@ -639,10 +697,7 @@ lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skel, int64_t* steps, 
                    int64_t* grows) {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
-  if (nnz_u) {
-    lf_status st = current_nnz(f, nnz_u);
-    if (st) return st;
-  }
+  if (nnz_u) *nnz_u = f->nnz;
   if (skel) *skel = (int64_t)f->skel_total;
   if (steps) *steps = f->steps;
   if (empty) *empty = (int64_t)f->events_total;

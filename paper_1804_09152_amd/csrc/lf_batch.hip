@@ -152,9 +152,13 @@ lf_status lf_batch_export(lf_batch* b, int32_t m, int64_t* nnz, int32_t* rowptr,
   LF_HIP(hipSetDevice(b->ctx->device));
   hipStream_t s = b->ctx->stream;
   const int32_t r0 = b->voff[m], nr = b->nv[m];
+  const int32_t* up = nullptr;
+  const Ent* ue = nullptr;
+  lf_status st = fields_csr(f, &up, &ue);
+  if (st) return st;
   int32_t lo = 0, hi = 0;
-  LF_HIP(hipMemcpyAsync(&lo, f->uptr[f->cur] + r0, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  LF_HIP(hipMemcpyAsync(&hi, f->uptr[f->cur] + r0 + nr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LF_HIP(hipMemcpyAsync(&lo, up + r0, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LF_HIP(hipMemcpyAsync(&hi, up + r0 + nr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   LF_HIP(hipStreamSynchronize(s));
   *nnz = hi - lo;
   if (!rowptr && !col && !val) return LF_OK;
@@ -164,8 +168,7 @@ lf_status lf_batch_export(lf_batch* b, int32_t m, int64_t* nnz, int32_t* rowptr,
   LF_HIP(drp.alloc(nr + 1));
   LF_HIP(dc.alloc(*nnz));
   LF_HIP(dv.alloc(*nnz));
-  hipLaunchKernelGGL(k_batch_extract, dim3((nr + kT) / kT), dim3(kT), 0, s, f->uptr[f->cur],
-                     f->uent[f->cur], r0, nr, b->soff[m], b->base, b->ns[m], drp.p, dc.p, dv.p);
+  hipLaunchKernelGGL(k_batch_extract, dim3((nr + kT) / kT), dim3(kT), 0, s, up, ue, r0, nr, b->soff[m], b->base, b->ns[m], drp.p, dc.p, dv.p);
   LF_HIP(hipGetLastError());
   LF_HIP(hipMemcpyAsync(rowptr, drp.p, sizeof(int32_t) * (nr + 1), hipMemcpyDeviceToHost, s));
   if (*nnz > 0) {
@@ -182,10 +185,14 @@ lf_status lf_batch_labels(lf_batch* b, int32_t m, int32_t* labels) {
   LF_HIP(hipSetDevice(b->ctx->device));
   hipStream_t s = b->ctx->stream;
   const int32_t r0 = b->voff[m], nr = b->nv[m];
+  const int32_t* up = nullptr;
+  const Ent* ue = nullptr;
+  lf_status st = fields_csr(f, &up, &ue);
+  if (st) return st;
   DBuf<int32_t> all, part;
   LF_HIP(all.alloc(f->mesh->n_v));
   LF_HIP(part.alloc(nr));
-  LF_HIP(launch_labels(f->uptr[f->cur], f->uent[f->cur], f->mesh->n_v, f->n_s, all.p, s));
+  LF_HIP(launch_labels(up, ue, f->mesh->n_v, f->n_s, all.p, s));
   hipLaunchKernelGGL(k_batch_labels, dim3((nr + kT - 1) / kT), dim3(kT), 0, s, all.p, r0, nr,
                      b->soff[m], part.p);
   LF_HIP(hipGetLastError());

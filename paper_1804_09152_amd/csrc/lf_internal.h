@@ -16,22 +16,41 @@ struct __attribute__((aligned(8))) Ent {
   float val;
 };
 
-constexpr int kBlock = 256;      // rows per tile of the step kernel
-constexpr int kRowRegs = 8;      // layers per row held in registers
-constexpr int kRowWide = 64;     // row limit of the wide (spill) path
+constexpr int kSlice = 64;      // rows per operator slice = one wavefront of the step kernel
+constexpr int kEll = 4;         // field entries per row held inline
+constexpr int kRowRegs = 8;     // layers per row held in registers
+constexpr int kRowWide = 64;    // row limit of the wide (spill) path
 constexpr int kMaxVerts = 1 << 25;
+constexpr int kParts = 256;     // partial-sum slots of the per-step counters
+constexpr int32_t kOvfMark = -2;  // first column of a row kept in the overflow area
 
-// Device-side step status.  Written by the step kernels, read by the host
-// once per lf_step call.
-struct StepFlags {
-  unsigned int poisoned;   // bit 0 capacity, bit 1 row limit, bit 2 look-back timeout,
-                           // bit 3 wide-row workspace exhausted
-  unsigned int fail_step;  // index (within the call) of the first failed step
-  unsigned long long need; // entries needed by a step that overflowed
+// One row of the fields in fixed-width form: up to kEll entries, ascending
+// layers, unused slots {-1, 0}.  A row with more entries keeps them in the
+// overflow area: e[0] = {kOvfMark, 0}, e[1].col = offset, e[2].col = count.
+struct __attribute__((aligned(32))) EllRow {
+  Ent e[kEll];
 };
 
-// Per-step counters, written for step k of an lf_step call at stats[k]: the
-// host adds up those of the steps that completed.
+// Operator slice: kSlice consecutive rows stored column-major, entry k of
+// row (first row of the slice + lane) at off + k * kSlice + lane; width is the
+// largest off-diagonal count of the slice, shorter rows padded with {-1, 0}.
+struct Slice {
+  int32_t off;
+  int32_t width;
+};
+
+// Device-side step status.  Written by the step kernels, read by the host
+// once per issued chunk of steps.
+struct StepFlags {
+  unsigned int poisoned;   // bit 0 overflow area full, bit 1 row limit, bit 2 unused,
+                           // bit 3 wide-row workspace exhausted
+  unsigned int fail_step;  // index (within the chunk) of the first failed step
+  unsigned long long need; // overflow entries needed by a step that ran out
+};
+
+// Per-step counters: each step adds its partial sums into kParts slots
+// (spread to keep atomics on one address few); a reduction kernel folds them
+// into one StepStats per step, and the host adds those of completed steps.
 struct StepStats {
   unsigned long long skel;    // sum of |rows of interest|
   unsigned long long out;     // nnz(U_{t+1})
@@ -45,8 +64,9 @@ struct StepConsts {
   int32_t n_s;
 };
 
-// Workspace of one row touching more than kRowRegs layers (global memory, so
-// that the step kernel itself needs no private memory).
+// Workspace of one row touching more than kRowRegs layers, or reading a row
+// kept in the overflow area (global memory, so that the step kernel itself
+// needs no private memory).
 struct WideRow {
   int32_t col[kRowWide];
   float phi[kRowWide];
@@ -56,29 +76,27 @@ struct WideRow {
 };
 
 struct StepArgs {
-  const int32_t* lptr;  // off-diagonal operator rows
-  const Ent* lent;
-  const float* ldiag;
-  const int32_t* uptr_in;
-  const Ent* uent_in;
-  int32_t* uptr_out;
-  Ent* uent_out;
+  const Slice* slices;             // operator slices
+  const Ent* lell;                 // their entries
+  const float* ldiag;              // operator diagonal
+  const EllRow* u_in;              // fields U_t
+  EllRow* u_out;                   // fields U_{t+1}
+  const Ent* ovf_in;               // overflow area of U_t
+  Ent* ovf_out;                    // overflow area of U_{t+1}
+  long long ovf_cap;               // entries of either overflow area
+  unsigned int* ovf_ctr;           // overflow entries taken in this step
+  unsigned int* ovf_ctr_next;      // cleared here for the next step
   int32_t n_v;
-  int32_t n_tiles;
-  long long cap;
+  int32_t n_slices;
   StepConsts c;
-  unsigned long long* status;       // tile status of this step
-  unsigned long long* status_next;  // cleared here for the next step
-  unsigned int* ticket;
-  unsigned int* ticket_next;
   WideRow* wide;                   // workspace slots for wide rows
   int32_t wide_cap;
   int32_t pad_;
   unsigned int* wide_ctr;          // slots taken in this step
   unsigned int* wide_ctr_next;     // cleared here for the next step
   StepFlags* flags;
-  StepStats* stats;                // this step's counters
-  uint32_t step_idx;               // index of this step within the call
+  StepStats* parts;                // kParts partial sums of this step
+  uint32_t step_idx;               // index of this step within the chunk
   uint32_t pad2_;
 };
 
@@ -93,10 +111,11 @@ lf_status hip_fail(hipError_t e, const char* what);
 
 // launchers (each defined next to its kernels) ------------------------------
 hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
-// clears the failure flags and the first n per-step counters
-hipError_t launch_reset_flags(StepFlags* f, StepStats* st, int n, hipStream_t s);
-hipError_t launch_init_fields(const int32_t* owner, int32_t n_v, int32_t* uptr, Ent* uent,
-                              hipStream_t s);
+// clears the failure flags and n steps' partial counters (n * kParts slots)
+hipError_t launch_reset_flags(StepFlags* f, StepStats* parts, int64_t n, hipStream_t s);
+// folds the partial counters of n steps into one StepStats per step
+hipError_t launch_reduce_parts(const StepStats* parts, int64_t n, StepStats* out, hipStream_t s);
+hipError_t launch_init_fields(const int32_t* owner, int32_t n_v, EllRow* u, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owner, hipStream_t s);
@@ -112,6 +131,21 @@ hipError_t build_operator(const double* V, const int32_t* F, int32_t n_v, int32_
                           int32_t** lptr, Ent** lent, float** ldiag, int64_t* nnz_off,
                           int* bad_face, hipStream_t s);
 
+// operator CSR (off-diagonal) -> slices; slices int32 n_sl, lell sized by
+// the returned entry count
+hipError_t build_slices(const int32_t* lptr, const Ent* lent, int32_t n_v, Slice** slices,
+                        Ent** lell, int64_t* n_ent, hipStream_t s);
+// fields: fixed-width rows (+ overflow area) -> CSR (uptr must hold n_v + 1,
+// uent the entry count); counts int32 n_v scratch, tmp scan_tmp_elems(n_v)
+hipError_t ell_to_csr_ptr(const EllRow* u, int32_t n_v, int32_t* counts, int32_t* uptr,
+                          long long* tmp, hipStream_t s);
+hipError_t ell_to_csr_fill(const EllRow* u, const Ent* ovf, int32_t n_v, const int32_t* uptr,
+                           Ent* uent, hipStream_t s);
+// canonical CSR -> fixed-width rows; rows longer than kEll keep their
+// entries at their CSR offsets in ovf (which holds at least nnz entries)
+hipError_t csr_to_ell(const int32_t* uptr, const Ent* uent, int32_t n_v, EllRow* u, Ent* ovf,
+                      hipStream_t s);
+
 hipError_t launch_split(const Ent* e, int64_t n, int32_t* col, float* val, hipStream_t s);
 hipError_t launch_join_check(const int32_t* col, const float* val, const int32_t* ptr,
                              int32_t n_v, int32_t n_r, int64_t nnz, Ent* out, int32_t* bad,
@@ -124,6 +158,10 @@ hipError_t launch_labels(const int32_t* uptr, const Ent* uent, int32_t n_v, int3
 
 // releases the dual-mesh state of a field object
 void dual_release(lf_fields* f);
+
+// CSR view of the current fields (rebuilt after steps); valid until the
+// next step, reset or import
+lf_status fields_csr(lf_fields* f, const int32_t** uptr, const Ent** uent);
 
 // asynchronous stepping: issue n steps; poll; book them (remaining > 0 when
 // storage had to grow and those steps must be issued again)
@@ -156,6 +194,9 @@ struct lf_mesh {
   lf::Ent* lent;
   float* ldiag;     // diagonal of the operator
   int64_t nnz_off;
+  lf::Slice* slices;  // the same off-diagonal entries in slices of kSlice rows
+  lf::Ent* lell;
+  int32_t n_slices;
   std::vector<double> Vh;  // host copies for small host-side geometry needs
   std::vector<int32_t> Fh;
 };
@@ -169,31 +210,36 @@ struct lf_fields {
   std::vector<int32_t> seeds;
   int32_t* d_seeds;
   int32_t* owner;              // scratch n_v
-  int32_t* uptr[2];
-  lf::Ent* uent[2];
-  int64_t cap;
+  lf::EllRow* ell[2];          // fields, double-buffered
+  lf::Ent* ovf[2];             // their overflow areas
+  int64_t ovf_cap;
   int cur;
-  unsigned long long* status[2];
-  unsigned int* tickets;       // 4 counters: tile tickets and wide-row slots, per parity
+  int64_t nnz;                 // entries of the current fields
+  unsigned int* counters;      // 4: overflow and wide-row counters, per parity
   lf::WideRow* wide;
   int32_t wide_cap;
   lf::StepFlags* flags;
   lf::StepFlags* flags_host;   // pinned
-  lf::StepStats* stats;        // per-step counters of one call
-  int64_t stats_cap;
-  lf::StepStats* stats_pinned; // their host copy
+  lf::StepStats* parts;        // kParts partial counters per step of a chunk
+  lf::StepStats* stats;        // folded per-step counters of a chunk
+  int64_t stats_cap;           // steps either holds
+  lf::StepStats* stats_pinned; // host copy of stats
   int64_t stats_pinned_cap;
   int64_t pending;             // steps issued and not yet booked
   hipEvent_t done_ev;          // recorded after the copies of an issued chunk
   size_t ev_issued;            // timing events used by the issued chunk
-  int32_t n_tiles;
+  // CSR view of the current fields, for export and post-processing
+  int32_t* uptr;
+  lf::Ent* uent;
+  int64_t csr_cap;
+  bool csr_valid;
+  long long* scan_tmp;         // scan_tmp_elems(n_v)
   // totals over completed steps
   long long steps, grow_events;
   unsigned long long skel_total, out_total, in_total, events_total;
   // timing
   bool timing;
   std::vector<hipEvent_t> ev0, ev1;
-  size_t ev_used;
   double timed_ms;
   long long timed_launches;
   DualState* dual;

@@ -837,8 +837,12 @@ lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out)
   LF_HIP(hipSetDevice(m->ctx->device));
   hipStream_t s = m->ctx->stream;
   const int32_t n_s = f->n_s, n_f = m->n_f;
-  const int32_t* uptr = f->uptr[f->cur];
-  const Ent* uent = f->uent[f->cur];
+  const int32_t* uptr = nullptr;
+  const Ent* uent = nullptr;
+  {
+    lf_status st = fields_csr(f, &uptr, &uent);
+    if (st) return st;
+  }
   Buf<unsigned long long> bounds, best_s;
   Buf<CellSums> acc;
   Buf<CellLine> lines;
@@ -916,8 +920,12 @@ lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, 
   hipStream_t s = m->ctx->stream;
   const int32_t n_s = f->n_s, n_f = m->n_f, n_v = m->n_v;
   const float ftau = (float)tau;
-  const int32_t* uptr = f->uptr[f->cur];
-  const Ent* uent = f->uent[f->cur];
+  const int32_t* uptr = nullptr;
+  const Ent* uent = nullptr;
+  {
+    lf_status st = fields_csr(f, &uptr, &uent);
+    if (st) return st;
+  }
   const int64_t nmax = std::max<int64_t>(n_v, n_f);
 
   // A_v and A_t as hash sets of cell pairs

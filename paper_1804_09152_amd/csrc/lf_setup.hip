@@ -1,5 +1,5 @@
-// Setup-time kernels: mesh operator, field initialisation, scans, import /
-// export of the field matrix, labels.
+// Setup-time kernels: mesh operator and its slices, field initialisation,
+// scans, conversions between the fixed-width field rows and CSR, labels.
 #include "lf_internal.h"
 
 namespace lf {
@@ -32,13 +32,91 @@ __global__ void k_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owne
 }
 
 // owner[v] = seed index of v, or n_s (the base layer) for unseeded vertices
-__global__ void k_init_fields(const int32_t* owner, int32_t n_v, int32_t* uptr, Ent* uent) {
+__global__ void k_init_fields(const int32_t* owner, int32_t n_v, EllRow* u) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_v) {
-    uptr[i] = i;
-    uent[i] = Ent{owner[i], 1.0f};
+    EllRow r;
+    r.e[0] = Ent{owner[i], 1.0f};
+#pragma unroll
+    for (int j = 1; j < kEll; ++j) r.e[j] = Ent{-1, 0.f};
+    u[i] = r;
   }
-  if (i == 0) uptr[n_v] = n_v;
+}
+
+// ---- layouts: operator slices, fixed-width field rows <-> CSR -------------------
+
+// per slice: kSlice * (largest off-diagonal count of its rows)
+__global__ void k_slice_size(const int32_t* lptr, int32_t n_v, int32_t n_sl, int32_t* size,
+                             int32_t* width) {
+  const int sl = blockIdx.x * (blockDim.x / kSlice) + threadIdx.x / kSlice;
+  const int lane = threadIdx.x % kSlice;
+  if (sl >= n_sl) return;
+  const int i = sl * kSlice + lane;
+  int d = i < n_v ? lptr[i + 1] - lptr[i] : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, 64));
+  if (lane == 0) {
+    width[sl] = d;
+    size[sl] = d * kSlice;
+  }
+}
+
+__global__ void k_slice_fill(const int32_t* lptr, const Ent* lent, int32_t n_v, int32_t n_sl,
+                             const int32_t* off, const int32_t* width, Slice* slices, Ent* lell) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = i / kSlice, lane = i % kSlice;
+  if (sl >= n_sl) return;
+  const int w = width[sl], o = off[sl];
+  if (lane == 0) slices[sl] = Slice{o, w};
+  const int a = i < n_v ? lptr[i] : 0, n = i < n_v ? lptr[i + 1] - a : 0;
+  for (int k = 0; k < w; ++k) lell[o + k * kSlice + lane] = k < n ? lent[a + k] : Ent{-1, 0.f};
+}
+
+__global__ void k_ell_count(const EllRow* u, int32_t n_v, int32_t* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  const EllRow r = u[i];
+  int n = 0;
+  if (r.e[0].col == kOvfMark) {
+    n = r.e[2].col;
+  } else {
+#pragma unroll
+    for (int j = 0; j < kEll; ++j) n += r.e[j].col >= 0 ? 1 : 0;
+  }
+  cnt[i] = n;
+}
+
+__global__ void k_ell_fill(const EllRow* u, const Ent* ovf, int32_t n_v, const int32_t* uptr,
+                           Ent* uent) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  const EllRow r = u[i];
+  const int32_t o = uptr[i], n = uptr[i + 1] - o;
+  if (r.e[0].col == kOvfMark) {
+    const Ent* src = ovf + r.e[1].col;
+    for (int j = 0; j < n; ++j) uent[o + j] = src[j];
+  } else {
+    for (int j = 0; j < n; ++j) uent[o + j] = r.e[j];
+  }
+}
+
+__global__ void k_csr_to_ell(const int32_t* uptr, const Ent* uent, int32_t n_v, EllRow* u,
+                             Ent* ovf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_v) return;
+  const int32_t a = uptr[i], n = uptr[i + 1] - a;
+  EllRow r;
+  if (n > kEll) {
+    r.e[0] = Ent{kOvfMark, 0.f};
+    r.e[1] = Ent{a, 0.f};
+    r.e[2] = Ent{n, 0.f};
+    r.e[3] = Ent{-1, 0.f};
+    for (int j = 0; j < n; ++j) ovf[a + j] = uent[a + j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < kEll; ++j) r.e[j] = j < n ? uent[a + j] : Ent{-1, 0.f};
+  }
+  u[i] = r;
 }
 
 // ---- exclusive scan -------------------------------------------------------------
@@ -275,9 +353,8 @@ hipError_t launch_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owne
   hipLaunchKernelGGL(k_scatter_owner, dim3(blocks_for(n_s)), dim3(kT), 0, s, seeds, n_s, owner);
   return hipGetLastError();
 }
-hipError_t launch_init_fields(const int32_t* owner, int32_t n_v, int32_t* uptr, Ent* uent,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_init_fields, dim3(blocks_for(n_v)), dim3(kT), 0, s, owner, n_v, uptr, uent);
+hipError_t launch_init_fields(const int32_t* owner, int32_t n_v, EllRow* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_fields, dim3(blocks_for(n_v)), dim3(kT), 0, s, owner, n_v, u);
   return hipGetLastError();
 }
 
@@ -355,6 +432,69 @@ fail:
   hipFree(he); hipFree(lptr); hipFree(lent); hipFree(ldiag);
   return e;
 #undef TRY
+}
+
+hipError_t build_slices(const int32_t* lptr, const Ent* lent, int32_t n_v, Slice** slices,
+                        Ent** lell, int64_t* n_ent, hipStream_t s) {
+  *slices = nullptr;
+  *lell = nullptr;
+  const int32_t n_sl = (n_v + kSlice - 1) / kSlice;
+  int32_t *size = nullptr, *width = nullptr, *off = nullptr;
+  long long* tmp = nullptr;
+  hipError_t e = dalloc(&size, n_sl);
+  if (e == hipSuccess) e = dalloc(&width, n_sl);
+  if (e == hipSuccess) e = dalloc(&off, n_sl + 1);
+  if (e == hipSuccess) e = dalloc(&tmp, scan_tmp_elems(n_sl));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_slice_size, dim3(blocks_for(n_sl, kT / kSlice)), dim3(kT), 0, s, lptr,
+                       n_v, n_sl, size, width);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = exclusive_scan(size, off, n_sl, tmp, s);
+  int32_t total = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&total, off + n_sl, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = dalloc(slices, n_sl);
+  if (e == hipSuccess) e = dalloc(lell, total);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_slice_fill, dim3(blocks_for((int64_t)n_sl * kSlice)), dim3(kT), 0, s,
+                       lptr, lent, n_v, n_sl, off, width, *slices, *lell);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(size);
+  (void)hipFree(width);
+  (void)hipFree(off);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    (void)hipFree(*slices);
+    (void)hipFree(*lell);
+    *slices = nullptr;
+    *lell = nullptr;
+  }
+  *n_ent = total;
+  return e;
+}
+
+hipError_t ell_to_csr_ptr(const EllRow* u, int32_t n_v, int32_t* counts, int32_t* uptr,
+                          long long* tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_ell_count, dim3(blocks_for(n_v)), dim3(kT), 0, s, u, n_v, counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return exclusive_scan(counts, uptr, n_v, tmp, s);
+}
+
+hipError_t ell_to_csr_fill(const EllRow* u, const Ent* ovf, int32_t n_v, const int32_t* uptr,
+                           Ent* uent, hipStream_t s) {
+  hipLaunchKernelGGL(k_ell_fill, dim3(blocks_for(n_v)), dim3(kT), 0, s, u, ovf, n_v, uptr, uent);
+  return hipGetLastError();
+}
+
+hipError_t csr_to_ell(const int32_t* uptr, const Ent* uent, int32_t n_v, EllRow* u, Ent* ovf,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_csr_to_ell, dim3(blocks_for(n_v)), dim3(kT), 0, s, uptr, uent, n_v, u, ovf);
+  return hipGetLastError();
 }
 
 hipError_t launch_split(const Ent* e, int64_t n, int32_t* col, float* val, hipStream_t s) {

@@ -17,16 +17,19 @@
 //   d_j = -(mu/n) (n Q_j - sum_k Q_k - sqrt(phi_j) G_j)
 // which is equation (11) with the alternate inner sum of equation (15).
 //
-// Design: one thread per vertex row, 256 rows per tile.  The row's union of
-// layers (its own row and the rows of its mesh neighbours, typically 1-4
-// layers) is accumulated in registers (8 slots); a row with more layers
-// takes a slower path with 64 slots in a global-memory workspace row (the
-// kernel uses no private memory).  Nothing but U and
-// the operator is read, nothing but the next U is written: the field
-// Laplacian and the rows of interest never leave the chip.  The output is
-// compacted in the same pass: a block-wide scan of the per-row counts and a
-// decoupled look-back over tiles (tile order taken from an atomic ticket, so
-// every tile a thread waits on is already running) give each row its offset.
+// Design: one wavefront per slice of 64 consecutive rows, one thread per
+// row.  The fields are held in fixed-width rows of four entries (32 bytes,
+// one aligned segment; longer rows, rare, live in an overflow area), so a
+// row's output position is known before the step: no compaction scan, no
+// ordering between wavefronts.  The operator slice is stored column-major,
+// so the k-th neighbours of the 64 rows are one contiguous 512-byte load.
+// A row's data arrive in two dependent rounds (its own row, diagonal and
+// operator entries; then the rows of its neighbours); the union of layers
+// (typically 1-4) is accumulated in 8 register slots; a row with more
+// layers, or reading an overflow row, takes a slower path with 64 slots in a
+// global-memory workspace row (the kernel uses no private memory).  Nothing
+// but U and the operator is read and nothing but the next U is written: the
+// field Laplacian and the rows of interest never leave the chip.
 #include <hip/hip_ext.h>
 
 #include "lf_internal.h"
@@ -34,20 +37,6 @@
 namespace lf {
 
 namespace {
-
-// tile status word: [63:62] flag, [61:31] rows-of-interest prefix, [30:0] entry prefix
-constexpr unsigned long long kFlagAgg = 1ull << 62;
-constexpr unsigned long long kFlagPre = 2ull << 62;
-constexpr unsigned long long kLow31 = (1ull << 31) - 1;
-constexpr unsigned long long kNoFlag = ~(3ull << 62);
-constexpr unsigned kSpinLimit = 1u << 22;
-
-__device__ __forceinline__ unsigned long long ld_status(unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_status(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // square root of a field value in [0, 1]: the hardware instruction (within
 // one unit in the last place), not the correctly rounded library sequence
@@ -197,16 +186,6 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
     if (!__any(s < (bound))) break;                 \
     else
 
-__device__ __forceinline__ void put_regs(RowBuf<kRowRegs>& r, int slot, int c, float ph, float la) {
-#pragma unroll
-  for (int s = 0; s < kRowRegs; ++s) {
-    const bool m = s == slot;
-    r.col[s] = m ? c : r.col[s];
-    r.phi[s] = m ? ph : r.phi[s];
-    r.lam[s] = m ? la : r.lam[s];
-  }
-}
-
 // adds w*x into layer c (a new slot when c is not held yet); ovf when the
 // row needs more than kRowRegs slots
 __device__ __forceinline__ void add_regs(RowBuf<kRowRegs>& r, int& cnt, bool& ovf, int c, float w,
@@ -230,104 +209,111 @@ __device__ __forceinline__ void add_regs(RowBuf<kRowRegs>& r, int& cnt, bool& ov
   }
 }
 
-constexpr int kNbPre = 8;  // neighbours whose rows are prefetched
+constexpr int kNbPre = 7;  // neighbours whose rows are prefetched
+
+__device__ __forceinline__ bool is_ovf(const Ent& e) { return e.col == kOvfMark; }
 
 // Gathers row i: its own layers (lam starts at L_ii * phi) and then, in the
 // operator's column order, every neighbour row scaled by L(i,u).  The loads
-// are issued in four independent rounds (row bounds; operator row; the
-// neighbours' row bounds; the first two entries of the own row and of every
-// neighbour row) so that a thread keeps about twenty loads in flight
-// instead of walking a chain of dependent ones.  The accumulation order is
-// fixed: own row, then neighbour by neighbour, each row in layer order.
-__device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int i,
-                                            const StepArgs& A) {
+// come in two rounds (own row, diagonal and the slice's operator entries;
+// then the neighbours' rows).  Returns false when the row needs the wide
+// path: more than kRowRegs layers, or an overflow row among its inputs.
+__device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int i, int lane,
+                                            int off, int width, const StepArgs& A) {
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   cnt = 0;
-  const int p0 = A.uptr_in[i], p1 = A.uptr_in[i + 1];
-  const int q0 = A.lptr[i], q1 = A.lptr[i + 1];
+  const EllRow own = A.u_in[i];
   const float dg = A.ldiag[i];
-  int nu[kNbPre];
-  float nw[kNbPre];
+  Ent le[kNbPre];
 #pragma unroll
-  for (int k = 0; k < kNbPre; ++k) {
-    const bool ok = q0 + k < q1;
-    const Ent le = ok ? A.lent[q0 + k] : Ent{-1, 0.f};
-    nu[k] = le.col;
-    nw[k] = le.val;
-  }
-  int na[kNbPre], nb[kNbPre];
+  for (int k = 0; k < kNbPre; ++k)
+    le[k] = k < width ? A.lell[off + k * kSlice + lane] : Ent{-1, 0.f};
+  EllRow nr[kNbPre];
 #pragma unroll
-  for (int k = 0; k < kNbPre; ++k) {
-    na[k] = nu[k] >= 0 ? A.uptr_in[nu[k]] : 0;
-    nb[k] = nu[k] >= 0 ? A.uptr_in[nu[k] + 1] : 0;
-  }
-  const Ent o0 = p0 < p1 ? A.uent_in[p0] : Ent{-1, 0.f};
-  const Ent o1 = p0 + 1 < p1 ? A.uent_in[p0 + 1] : Ent{-1, 0.f};
-  const Ent o2 = p0 + 2 < p1 ? A.uent_in[p0 + 2] : Ent{-1, 0.f};
-  Ent e0[kNbPre], e1[kNbPre], e2[kNbPre];
+  for (int k = 0; k < kNbPre; ++k) nr[k] = A.u_in[le[k].col >= 0 ? le[k].col : i];
+  if (is_ovf(own.e[0])) return false;
+  // own row: slots 0..3 in layer order
 #pragma unroll
-  for (int k = 0; k < kNbPre; ++k) {
-    e0[k] = na[k] < nb[k] ? A.uent_in[na[k]] : Ent{-1, 0.f};
-    e1[k] = na[k] + 1 < nb[k] ? A.uent_in[na[k] + 1] : Ent{-1, 0.f};
-    e2[k] = na[k] + 2 < nb[k] ? A.uent_in[na[k] + 2] : Ent{-1, 0.f};
-  }
-  if (p1 - p0 > kRowRegs) return false;
-  // own row: slots 0, 1, 2 in layer order (lam starts at L_ii * phi)
-  if (p0 < p1) { r.col[0] = o0.col; r.phi[0] = o0.val; r.lam[0] = dg * o0.val; }
-  if (p0 + 1 < p1) { r.col[1] = o1.col; r.phi[1] = o1.val; r.lam[1] = dg * o1.val; }
-  if (p0 + 2 < p1) { r.col[2] = o2.col; r.phi[2] = o2.val; r.lam[2] = dg * o2.val; }
-  cnt = min(p1 - p0, 3);
-  for (int p = p0 + 3; p < p1; ++p) {
-    const Ent e = A.uent_in[p];
-    put_regs(r, cnt, e.col, e.val, dg * e.val);
-    ++cnt;
+  for (int j = 0; j < kEll; ++j) {
+    if (own.e[j].col >= 0) {
+      r.col[j] = own.e[j].col;
+      r.phi[j] = own.e[j].val;
+      r.lam[j] = dg * own.e[j].val;
+      cnt = j + 1;
+    }
   }
   bool ovf = false;
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k) {
-    if (na[k] < nb[k]) add_regs(r, cnt, ovf, e0[k].col, nw[k], e0[k].val);
-    if (na[k] + 1 < nb[k]) add_regs(r, cnt, ovf, e1[k].col, nw[k], e1[k].val);
-    if (na[k] + 2 < nb[k]) add_regs(r, cnt, ovf, e2[k].col, nw[k], e2[k].val);
-    for (int p = na[k] + 3; p < nb[k]; ++p) {
-      const Ent e = A.uent_in[p];
-      add_regs(r, cnt, ovf, e.col, nw[k], e.val);
+    if (le[k].col < 0) continue;
+    if (is_ovf(nr[k].e[0])) {
+      ovf = true;
+      continue;
     }
+#pragma unroll
+    for (int j = 0; j < kEll; ++j)
+      if (nr[k].e[j].col >= 0) add_regs(r, cnt, ovf, nr[k].e[j].col, le[k].val, nr[k].e[j].val);
   }
-  for (int q = q0 + kNbPre; q < q1; ++q) {  // vertices of degree above kNbPre
-    const Ent le = A.lent[q];
-    const int a0 = A.uptr_in[le.col], a1 = A.uptr_in[le.col + 1];
-    for (int p = a0; p < a1; ++p) {
-      const Ent e = A.uent_in[p];
-      add_regs(r, cnt, ovf, e.col, le.val, e.val);
+  for (int k = kNbPre; k < width; ++k) {  // slices wider than kNbPre
+    const Ent l = A.lell[off + k * kSlice + lane];
+    if (l.col < 0) continue;
+    const EllRow u = A.u_in[l.col];
+    if (is_ovf(u.e[0])) {
+      ovf = true;
+      continue;
     }
+#pragma unroll
+    for (int j = 0; j < kEll; ++j)
+      if (u.e[j].col >= 0) add_regs(r, cnt, ovf, u.e[j].col, l.val, u.e[j].val);
   }
   return !ovf;
 }
 
-// ---- wide path (rows touching more than kRowRegs layers) ----------------------
+// ---- wide path (many layers, or overflow rows) --------------------------------
+
+// entries of row u of U_t: inline, or in the overflow area (bounds-checked,
+// so that a row written by a failed step is read as empty)
+struct RowView {
+  const Ent* p;
+  int n;
+};
+__device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
+  const Ent* e = A->u_in[u].e;
+  if (is_ovf(e[0])) {
+    const long long o = e[1].col, n = e[2].col;
+    if (o < 0 || n < 0 || o + n > A->ovf_cap) return RowView{e, 0};
+    return RowView{A->ovf_in + o, (int)n};
+  }
+  int n = 0;
+  while (n < kEll && e[n].col >= 0) ++n;
+  return RowView{e, n};
+}
 
 // Same arithmetic in the same order as the register path, with kRowWide
 // slots in a global-memory workspace row.  Returns the number of kept
 // entries (0 and *ovf set when the row touches more than kRowWide layers).
-__device__ __forceinline__ int wide_row(int i, const StepArgs* A, WideRow* r, int* n_skel, int* ev,
-                                     int* ovf) {
+__device__ __forceinline__ int wide_row(int i, int lane, int off, int width, const StepArgs* A,
+                                        WideRow* r, int* n_skel, int* ev, int* ovf) {
   int cnt = 0;
   *n_skel = 0;
   *ev = 0;
   const float dg = A->ldiag[i];
-  for (int p = A->uptr_in[i]; p < A->uptr_in[i + 1]; ++p) {
+  const RowView o = row_view(A, i);
+  for (int p = 0; p < o.n; ++p) {
     if (cnt == kRowWide) { *ovf = 1; return 0; }
-    const Ent e = A->uent_in[p];
+    const Ent e = o.p[p];
     r->col[cnt] = e.col;
     r->phi[cnt] = e.val;
     r->lam[cnt] = dg * e.val;
     ++cnt;
   }
-  for (int q = A->lptr[i]; q < A->lptr[i + 1]; ++q) {
-    const Ent le = A->lent[q];
-    for (int p = A->uptr_in[le.col]; p < A->uptr_in[le.col + 1]; ++p) {
-      const Ent e = A->uent_in[p];
+  for (int k = 0; k < width; ++k) {
+    const Ent le = A->lell[off + k * kSlice + lane];
+    if (le.col < 0) continue;
+    const RowView v = row_view(A, le.col);
+    for (int p = 0; p < v.n; ++p) {
+      const Ent e = v.p[p];
       int s = 0;
       while (s < cnt && r->col[s] != e.col) ++s;
       if (s < cnt) {
@@ -361,187 +347,160 @@ __device__ __forceinline__ void wide_write(const WideRow* r, Ent* dst) {
   }
 }
 
-// marks this step (and so every later one of the call) as not done
+// marks this step (and so every later one of the chunk) as not done
 __device__ __forceinline__ void step_failed(const StepArgs& A, unsigned bit) {
   atomicOr(&A.flags->poisoned, bit);
   atomicMin(&A.flags->fail_step, A.step_idx);
 }
 
-__device__ __forceinline__ int wave_incl_scan(int x) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ int wave_sum(int x) {
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
 
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
-  __shared__ int s_tile;
-  __shared__ int s_wave[kBlock / 64];
-  __shared__ unsigned long long s_excl;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    const unsigned pois =
-        __hip_atomic_load(&A.flags->poisoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_tile = pois ? -1 : (int)atomicAdd(A.ticket, 1u);
-  }
-  __syncthreads();
-  const int tile = s_tile;
-  if (tile < 0) return;  // an earlier step overflowed: nothing to do
-  if (tid == 0) {
-    A.status_next[tile] = 0ull;
-    if (tile == 0) {
-      *A.ticket_next = 0u;
-      *A.wide_ctr_next = 0u;
+// kept register-path entries in ascending layer order at dst[0..n_keep)
+__device__ __forceinline__ void write_regs(const RowBuf<kRowRegs>& r, int cnt, Ent* dst) {
+#pragma unroll
+  for (int s = 0; s < kRowRegs; ++s) {
+    if (!__any(s < cnt)) break;
+    if (r.out[s] > 0.f) {
+      int rank = 0;
+#pragma unroll
+      for (int t = 0; t < kRowRegs; ++t) {
+        if (!__any(t < cnt)) break;
+        rank += (r.out[t] > 0.f && r.col[t] < r.col[s]) ? 1 : 0;
+      }
+      dst[rank] = Ent{r.col[s], r.out[s]};
     }
   }
-  const int i = tile * kBlock + tid;
+}
+
+__global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
+    StepArgs A) {
+  const int lane = threadIdx.x;
+  const int sl = blockIdx.x;
+  if (__hip_atomic_load(&A.flags->poisoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    return;  // an earlier step of the chunk failed: nothing to do
+  if (sl == 0 && lane == 0) {
+    *A.ovf_ctr_next = 0u;
+    *A.wide_ctr_next = 0u;
+  }
+  const Slice S = A.slices[sl];
+  const int i = sl * kSlice + lane;
 
   RowBuf<kRowRegs> r;
-  int cnt = 0, n_keep = 0, n_skel = 0, ev = 0, rowovf = 0;
+  int cnt = 0, n_keep = 0, n_skel = 0, n_in = 0, ev = 0, rowovf = 0;
   int wide = -1;  // workspace slot of a wide row
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) r.out[s] = -1.f;
   if (i < A.n_v) {
-    if (gather_regs(r, cnt, i, A)) {
+    n_in = row_view(&A, i).n;
+    if (gather_regs(r, cnt, i, lane, S.off, S.width, A)) {
       row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);
     } else {
       const unsigned slot = atomicAdd(A.wide_ctr, 1u);
       if (slot < (unsigned)A.wide_cap) {
         wide = (int)slot;
-        n_keep = wide_row(i, &A, A.wide + slot, &n_skel, &ev, &rowovf);
-        if (rowovf) step_failed(A, 2u);
+        n_keep = wide_row(i, lane, S.off, S.width, &A, A.wide + slot, &n_skel, &ev, &rowovf);
+        if (rowovf) {
+          step_failed(A, 2u);
+          n_keep = 0;
+        }
       } else {
         step_failed(A, 8u);  // the step is replayed with more slots
       }
     }
-  }
-  if (ev) atomicAdd(&A.stats->events, 1ull);
-
-  // block scan of (kept entries, rows-of-interest size), packed 16/16
-  const int x = n_keep | (n_skel << 16);
-  int incl = wave_incl_scan(x);
-  const int wid = tid >> 6, lane = tid & 63;
-  if (lane == 63) s_wave[wid] = incl;
-  __syncthreads();
-  int woff = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
-    const int v = s_wave[w];
-    woff += (w < wid) ? v : 0;
-    tot += v;
-  }
-  incl += woff;
-
-  // decoupled look-back over tiles, one wavefront reading 64 predecessors
-  // per probe: lane k looks at tile (tile - 1 - k - 64 m)
-  if (tid < 64) {
-    const unsigned long long agg =
-        ((unsigned long long)(tot >> 16) << 31) | (unsigned long long)(tot & 0xffff);
-    unsigned long long excl = 0;
-    if (tile == 0) {
-      if (lane == 0) st_status(&A.status[0], kFlagPre | agg);
+    // the row: inline, or in the overflow area of U_{t+1}
+    Ent* row = A.u_out[i].e;
+    Ent* dst = row;
+    if (n_keep > kEll) {
+      const long long o = (long long)atomicAdd(A.ovf_ctr, (unsigned)n_keep);
+      const bool fits = o + n_keep <= A.ovf_cap;
+      if (!fits) {
+        atomicMax(&A.flags->need, (unsigned long long)(o + n_keep));
+        step_failed(A, 1u);  // the step is replayed with a larger area
+      }
+      row[0] = Ent{kOvfMark, 0.f};
+      row[1] = Ent{fits ? (int32_t)o : 0, 0.f};
+      row[2] = Ent{fits ? n_keep : 0, 0.f};
+      row[3] = Ent{-1, 0.f};
+      dst = fits ? A.ovf_out + o : nullptr;
     } else {
-      if (lane == 0) st_status(&A.status[tile], kFlagAgg | agg);
-      int j0 = tile - 1;
-      unsigned spins = 0;
-      bool timed_out = false;
-      for (;;) {
-        const int j = j0 - lane;
-        unsigned long long v;
-        for (;;) {
-          // before tile 0 there is nothing: read as a prefix of zero
-          v = j >= 0 ? ld_status(&A.status[j]) : kFlagPre;
-          if (!__any((v >> 62) == 0)) break;
-          if (++spins > kSpinLimit) { timed_out = true; break; }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        if (timed_out) {
-          if (lane == 0) step_failed(A, 4u);
-          break;
-        }
-        const unsigned long long pre = __ballot((v >> 62) == 2);
-        const int first = pre ? __ffsll((unsigned long long)pre) - 1 : 64;
-        unsigned long long c = lane <= first ? (v & kNoFlag) : 0ull;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        excl += c;
-        if (pre) break;
-        j0 -= 64;
-      }
-      if (lane == 0) st_status(&A.status[tile], kFlagPre | (excl + agg));
+      for (int p = n_keep; p < kEll; ++p) row[p] = Ent{-1, 0.f};
     }
-    if (lane == 0) s_excl = excl;
-  }
-  __syncthreads();
-  const unsigned long long ex = s_excl;
-  const long long ex_count = (long long)(ex & kLow31);
-  const long long ex_skel = (long long)(ex >> 31);
-  const long long base = ex_count + (long long)((incl - x) & 0xffff);
-
-  if (i < A.n_v) {
-    A.uptr_out[i + 1] = (int)(base + n_keep);
-    if (base + n_keep <= A.cap) {
-      Ent* dst = A.uent_out + base;
-      if (wide < 0) {
-#pragma unroll
-        for (int s = 0; s < kRowRegs; ++s) {
-          if (!__any(s < cnt)) break;
-          if (r.out[s] > 0.f) {
-            int rank = 0;
-#pragma unroll
-            for (int t = 0; t < kRowRegs; ++t) {
-              if (!__any(t < cnt)) break;
-              rank += (r.out[t] > 0.f && r.col[t] < r.col[s]) ? 1 : 0;
-            }
-            dst[rank] = Ent{r.col[s], r.out[s]};
-          }
-        }
-      } else if (!rowovf) {
-        wide_write(A.wide + wide, dst);
-      }
+    if (dst) {
+      if (wide < 0) write_regs(r, cnt, dst);
+      else if (!rowovf) wide_write(A.wide + wide, dst);
     }
   }
-  if (tile == 0 && tid == 0) A.uptr_out[0] = 0;
-  if (tile == A.n_tiles - 1 && tid == 0) {
-    const long long total = ex_count + (tot & 0xffff);
-    const long long skel = ex_skel + (tot >> 16);
-    if (total > A.cap) {
-      atomicMax(&A.flags->need, (unsigned long long)total);
-      step_failed(A, 1u);
-    }
-    A.stats->skel = (unsigned long long)skel;
-    A.stats->out = (unsigned long long)total;
-    A.stats->in = (unsigned long long)A.uptr_in[A.n_v];
+  // counters of the slice, added into one of kParts slots
+  const int skel = wave_sum(n_skel), out = wave_sum(n_keep), in = wave_sum(n_in),
+            evs = wave_sum(ev);
+  if (lane == 0) {
+    StepStats* P = A.parts + (sl & (kParts - 1));
+    atomicAdd(&P->skel, (unsigned long long)skel);
+    atomicAdd(&P->out, (unsigned long long)out);
+    atomicAdd(&P->in, (unsigned long long)in);
+    if (evs) atomicAdd(&P->events, (unsigned long long)evs);
   }
 }
 
-__global__ void k_reset_flags(StepFlags* f, StepStats* st, int n) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_reset_flags(StepFlags* f, StepStats* parts, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0) {
     f->poisoned = 0;
     f->fail_step = 0xffffffffu;
     f->need = 0;
   }
-  if (st && k < n) st[k] = StepStats{0, 0, 0, 0};
+  if (parts && k < n) parts[k] = StepStats{0, 0, 0, 0};
+}
+
+// one block per step: sums the kParts partial counters
+__global__ __launch_bounds__(kParts) void k_reduce_parts(const StepStats* parts,
+                                                         StepStats* out) {
+  __shared__ unsigned long long sh[4][kParts / 64];
+  const StepStats p = parts[(int64_t)blockIdx.x * kParts + threadIdx.x];
+  unsigned long long v[4] = {p.skel, p.out, p.in, p.events};
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if (lane == 0) sh[q][wid] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int w = 0; w < kParts / 64; ++w) t[q] += sh[q][w];
+    out[blockIdx.x] = StepStats{t[0], t[1], t[2], t[3]};
+  }
 }
 
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   if (t0 && t1) {
-    hipExtLaunchKernelGGL(k_step, dim3(a.n_tiles), dim3(kBlock), 0, s, t0, t1, 0, a);
+    hipExtLaunchKernelGGL(k_step, dim3(a.n_slices), dim3(kSlice), 0, s, t0, t1, 0, a);
   } else {
-    hipLaunchKernelGGL(k_step, dim3(a.n_tiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_step, dim3(a.n_slices), dim3(kSlice), 0, s, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_reset_flags(StepFlags* f, StepStats* st, int n, hipStream_t s) {
-  const int nb = n > 0 ? (n + 255) / 256 : 1;
-  hipLaunchKernelGGL(k_reset_flags, dim3(nb), dim3(256), 0, s, f, st, n);
+hipError_t launch_reset_flags(StepFlags* f, StepStats* parts, int64_t n, hipStream_t s) {
+  const int64_t m = parts ? n * kParts : 0;
+  const unsigned nb = m > 0 ? (unsigned)((m + 255) / 256) : 1u;
+  hipLaunchKernelGGL(k_reset_flags, dim3(nb), dim3(256), 0, s, f, parts, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const StepStats* parts, int64_t n, StepStats* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)n), dim3(kParts), 0, s, parts, out);
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ def _same_csr(a, b):
 def test_batch_equals_solo(lf, op, cap):
     lfb, ctx = lf
     items = I.batch_tori(8, seed=3, nv_lo=150, nv_hi=6000, s_lo=3, s_hi=80)
-    # capacity_hint 1 forces storage growth and replayed steps inside the batch
+    # capacity_hint 1: a one-entry overflow area (grown if a row needs it)
     params = lfb.default_params(capacity_hint=cap) if cap else lfb.default_params()
     steps = 45
     say(f"batch op={op} cap={cap}: {[m.n_v for m, _ in items]} vertices")
@@ -49,8 +49,6 @@ def test_batch_equals_solo(lf, op, cap):
     B.step(steps)
     st = B.stats()
     assert st["steps"] == steps
-    if cap:
-        assert st["grow_events"] > 0
     for k, (mesh, seeds) in enumerate(items):
         M, f = _solo_fields(lfb, ctx, mesh, seeds, op, params, steps)
         assert _same_csr(B.export(k), f.export()), f"mesh {k} fields differ from its solo run"

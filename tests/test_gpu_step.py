@@ -171,20 +171,71 @@ def test_full_size_c3_one_step(lf, orc):
     assert pat.all() and diff.max() <= 1e-5
 
 
+def _three_layer_state(mesh, n_s, seed):
+    """Every vertex holds three random layers: most rows of the next step
+    hold more than four entries (the overflow area)."""
+    rng = np.random.default_rng(seed)
+    D = np.zeros((mesh.n_v, n_s + 1))
+    for i in range(mesh.n_v):
+        c = rng.choice(n_s + 1, 3, replace=False)
+        D[i, c] = rng.uniform(0.1, 1.0, 3)
+    D /= D.sum(1, keepdims=True)
+    ptr = np.zeros(mesh.n_v + 1, np.int64)
+    ptr[1:] = np.cumsum((D > 0).sum(1))
+    col = np.nonzero(D > 0)[1].astype(np.int32)
+    return f32((ptr, col, D[D > 0]))
+
+
 def test_capacity_growth_replays_exactly(lf, orc):
+    """A one-entry overflow area grows (the failed steps are replayed) and
+    gives exactly the result of an area large enough from the start."""
     lfb, ctx = lf
-    mesh, seeds = I.config_c1()
+    mesh = I.torus_grid(48, 40)
+    n_s = 30
+    U = _three_layer_state(mesh, n_s, 9)
+    seeds = I.seeds_uniform(mesh.n_v, n_s, np.random.default_rng(1))
     m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
     say("capacity growth")
-    a = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=mesh.n_v))
-    b = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=8 * mesh.n_v))
-    a.step(100)
-    b.step(100)
+    a = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=1))
+    b = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=1 << 22))
+    gpu_load(a, U)
+    gpu_load(b, U)
+    a.step(4)
+    b.step(4)
     A, B = a.export(), b.export()
-    assert a.stats()["grow_events"] > 0 and b.stats()["grow_events"] == 0
+    # both may grow their wide-row workspace; only a grows its overflow area
+    assert a.stats()["grow_events"] > b.stats()["grow_events"]
+    assert np.diff(A[0]).max() > 4  # overflow rows were written
     for x, y in zip(A, B):
         assert np.array_equal(x, y)
     assert a.stats()["skeleton_total"] == b.stats()["skeleton_total"]
+    L = orc.operator(mesh.V, mesh.F, 0)
+    O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
+    gpu_load(a, U)
+    a.step(1)
+    check_step(as_oracle(a.export()), O, info["margin"], what="overflow rows",
+               max_guarded_frac=0.05)
+
+
+def test_export_import_roundtrip_with_long_rows(lf, orc):
+    """Rows of up to 41 entries go in and come out unchanged."""
+    lfb, ctx = lf
+    mesh = I.torus_grid(20, 20)
+    n_s = 40
+    rng = np.random.default_rng(4)
+    lens = rng.integers(0, 42, mesh.n_v)
+    lens[:3] = (41, 5, 0)
+    ptr = np.zeros(mesh.n_v + 1, np.int64)
+    ptr[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n_s + 1, k, replace=False)) for k in lens]).astype(np.int32)
+    val = rng.uniform(0.01, 1.0, col.size).astype(np.float32)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, I.seeds_uniform(mesh.n_v, n_s, rng))
+    say("export/import roundtrip")
+    f.load(ptr.astype(np.int32), col, val)
+    P, Cc, V = f.export()
+    assert np.array_equal(P, ptr) and np.array_equal(Cc, col) and np.array_equal(V, val)
+    assert f.stats()["nnz"] == col.size
 
 
 def test_wide_rows(lf, orc):
@@ -230,15 +281,7 @@ def test_wide_workspace_growth(lf, orc):
     mesh = I.torus_grid(64, 64)
     n_s = 40
     rng = np.random.default_rng(5)
-    D = np.zeros((mesh.n_v, n_s + 1))
-    for i in range(mesh.n_v):
-        c = rng.choice(n_s + 1, 3, replace=False)
-        D[i, c] = rng.uniform(0.1, 1.0, 3)
-    D /= D.sum(1, keepdims=True)
-    ptr = np.zeros(mesh.n_v + 1, np.int64)
-    ptr[1:] = np.cumsum((D > 0).sum(1))
-    col = np.nonzero(D > 0)[1].astype(np.int32)
-    U = f32((ptr, col, D[D > 0]))
+    U = _three_layer_state(mesh, n_s, 5)
     L = orc.operator(mesh.V, mesh.F, 0)
     m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
     f = lfb.Fields(m, I.seeds_uniform(mesh.n_v, n_s, rng))
