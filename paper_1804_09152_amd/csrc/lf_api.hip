@@ -558,16 +558,21 @@ extern "C" {
 
 lf_status lf_step(lf_fields* f, int32_t n) {
   if (!f || n < 0) return fail(LF_EINVAL, "invalid argument");
-  if (n == 0) return LF_OK;
-  int64_t remaining = n;
-  for (int grows = 0;; ++grows) {
-    if (grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
-    lf_status st = step_issue(f, remaining);
+  int64_t left = n;
+  int grows = 0;
+  while (left > 0) {
+    // chunks of at most kMaxChunk steps: the steps issued after a failed
+    // one run for nothing, so a failure wastes at most one chunk
+    const int64_t m = std::min<int64_t>(left, kMaxChunk);
+    lf_status st = step_issue(f, m);
     if (st) return st;
-    st = step_complete(f, &remaining);
+    int64_t rem = 0;
+    st = step_complete(f, &rem);
     if (st) return st;
-    if (remaining == 0) return LF_OK;
+    left -= m - rem;
+    if (rem > 0 && ++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
   }
+  return LF_OK;
 }
 
 lf_status lf_sync(lf_fields* f) {

@@ -23,6 +23,7 @@ constexpr int kRowWide = 64;    // row limit of the wide (spill) path
 constexpr int kMaxVerts = 1 << 25;
 constexpr int kParts = 256;     // partial-sum slots of the per-step counters
 constexpr int32_t kOvfMark = -2;  // first column of a row kept in the overflow area
+constexpr int64_t kMaxChunk = 256;  // steps lf_step issues before it books them
 
 // One row of the fields in fixed-width form: up to kEll entries, ascending
 // layers, unused slots {-1, 0}.  A row with more entries keeps them in the
@@ -164,7 +165,9 @@ void dual_release(lf_fields* f);
 lf_status fields_csr(lf_fields* f, const int32_t** uptr, const Ent** uent);
 
 // asynchronous stepping: issue n steps; poll; book them (remaining > 0 when
-// storage had to grow and those steps must be issued again)
+// storage had to grow and those steps must be issued again).  Steps issued
+// after a failed one still run (on well-formed data) and are discarded, so
+// callers keep n modest.
 lf_status step_issue(lf_fields* f, int64_t n);
 bool step_ready(lf_fields* f);
 lf_status step_complete(lf_fields* f, int64_t* remaining);

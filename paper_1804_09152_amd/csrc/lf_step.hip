@@ -46,9 +46,14 @@ template <int K>
 struct RowBuf {
   int col[K];
   float phi[K];
-  float lam[K];
-  float out[K];
+  float lam[K];  // field Laplacian; after the update, the output value
 };
+
+// output value of slot s: in registers it replaces the field Laplacian,
+// which is dead once the slot is updated; the workspace row keeps both
+template <int K>
+__device__ __forceinline__ float& out_of(RowBuf<K>& r, int s) { return r.lam[s]; }
+__device__ __forceinline__ float& out_of(WideRow& r, int s) { return r.out[s]; }
 
 template <int K>
 struct MaskT {
@@ -61,7 +66,8 @@ struct MaskT<kRowRegs> {
 
 // Closed-form update of one row's active layers.  Slots s < cnt hold the
 // row's union of layers (col, phi = U(i,col), lam = field Laplacian).
-// out[s] receives the normalised kept value or -1.
+// out_of(r, s) receives the normalised kept value, or -1 (or 0 in register
+// slots beyond the wavefront's largest count).
 template <int K, bool UNROLL, class B>
 __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, int& n_keep,
                                            int& n_skel, int& ev) {
@@ -79,7 +85,6 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
 #define LF_SLOTS_RT _Pragma("unroll 1") for (int s = 0; s < K; ++s)
   if constexpr (UNROLL) {
     LF_SLOTS {
-      r.out[s] = -1.f;
       if (s < cnt) {
         const float ph = r.phi[s];
         if (ph > 0.f || (ph == 0.f && r.lam[s] > 0.f)) {
@@ -96,7 +101,6 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
     }
   } else {
     LF_SLOTS_RT {
-      r.out[s] = -1.f;
       if (s < cnt) {
         const float ph = r.phi[s];
         if (ph > 0.f || (ph == 0.f && r.lam[s] > 0.f)) {
@@ -115,7 +119,14 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
   n_skel = n;
   n_keep = 0;
   ev = 0;
-  if (n == 0) return;
+  if (n == 0) {
+    if constexpr (UNROLL) {
+      LF_SLOTS out_of(r, s) = -1.f;
+    } else {
+      LF_SLOTS_RT out_of(r, s) = -1.f;
+    }
+    return;
+  }
   const float ha = 0.5f * c.a;
   const float fn = (float)n;
   const float sumQ = (c.base_mode == 0)
@@ -140,20 +151,20 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
     float v = ph + c.dt * d;
     if (v > 1.f) v = 1.f;
     if (v <= 0.f) v = 0.f;
-    r.out[s] = v;
+    out_of(r, s) = v;
     V += v;
   };
   if constexpr (UNROLL) {
-    LF_SLOTS if ((act >> s) & 1) upd(s);
+    LF_SLOTS if ((act >> s) & 1) upd(s); else out_of(r, s) = -1.f;
   } else {
-    LF_SLOTS_RT if ((act >> s) & 1) upd(s);
+    LF_SLOTS_RT if ((act >> s) & 1) upd(s); else out_of(r, s) = -1.f;
   }
   if (!(V > 0.f)) {
     ev = 1;
     if constexpr (UNROLL) {
-      LF_SLOTS r.out[s] = -1.f;
+      LF_SLOTS out_of(r, s) = -1.f;
     } else {
-      LF_SLOTS_RT r.out[s] = -1.f;
+      LF_SLOTS_RT out_of(r, s) = -1.f;
     }
     return;
   }
@@ -161,9 +172,9 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
   // one division per row; a single active layer normalises to exactly 1
   const float inv = 1.f / V;
   auto fin = [&](int s) {
-    const float o = n == 1 ? 1.f : r.out[s] * inv;
+    const float o = n == 1 ? 1.f : out_of(r, s) * inv;
     const bool keep = o > 0.f && o >= c.theta;
-    r.out[s] = keep ? o : -1.f;
+    out_of(r, s) = keep ? o : -1.f;
     k += keep ? 1 : 0;
   };
   if constexpr (UNROLL) {
@@ -209,7 +220,11 @@ __device__ __forceinline__ void add_regs(RowBuf<kRowRegs>& r, int& cnt, bool& ov
   }
 }
 
-constexpr int kNbPre = 7;  // neighbours whose rows are prefetched
+constexpr int kNbPre = 7;  // neighbours whose operator entries are prefetched
+#ifndef LF_WIN
+#define LF_WIN 4
+#endif
+constexpr int kWin = LF_WIN;  // neighbour rows in flight
 
 __device__ __forceinline__ bool is_ovf(const Ent& e) { return e.col == kOvfMark; }
 
@@ -218,20 +233,32 @@ __device__ __forceinline__ bool is_ovf(const Ent& e) { return e.col == kOvfMark;
 // come in two rounds (own row, diagonal and the slice's operator entries;
 // then the neighbours' rows).  Returns false when the row needs the wide
 // path: more than kRowRegs layers, or an overflow row among its inputs.
-__device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int i, int lane,
-                                            int off, int width, const StepArgs& A) {
+__device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n_in, int i,
+                                            int lane, int& off, int& width, const StepArgs& A) {
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   cnt = 0;
+  // own row and diagonal first: they do not wait for the slice descriptor
   const EllRow own = A.u_in[i];
   const float dg = A.ldiag[i];
+  const Slice S = A.slices[i / kSlice];
+  off = S.off;
+  width = S.width;
+  // entries of U_t in this row (for the counters)
+  n_in = 0;
+#pragma unroll
+  for (int j = 0; j < kEll; ++j) n_in += own.e[j].col >= 0 ? 1 : 0;
+  if (is_ovf(own.e[0])) n_in = own.e[2].col;
   Ent le[kNbPre];
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k)
     le[k] = k < width ? A.lell[off + k * kSlice + lane] : Ent{-1, 0.f};
-  EllRow nr[kNbPre];
+  // neighbour rows stream through a window of kWin rows: the row of
+  // neighbour k + kWin is requested before neighbour k is merged, so a few
+  // loads stay in flight without holding every neighbour row in registers
+  EllRow win[kWin];
 #pragma unroll
-  for (int k = 0; k < kNbPre; ++k) nr[k] = A.u_in[le[k].col >= 0 ? le[k].col : i];
+  for (int k = 0; k < kWin; ++k) win[k] = A.u_in[le[k].col >= 0 ? le[k].col : i];
   if (is_ovf(own.e[0])) return false;
   // own row: slots 0..3 in layer order
 #pragma unroll
@@ -246,14 +273,17 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int i
   bool ovf = false;
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k) {
+    const EllRow u = win[k % kWin];
+    if (k + kWin < kNbPre)
+      win[k % kWin] = A.u_in[le[k + kWin].col >= 0 ? le[k + kWin].col : i];
     if (le[k].col < 0) continue;
-    if (is_ovf(nr[k].e[0])) {
+    if (is_ovf(u.e[0])) {
       ovf = true;
       continue;
     }
 #pragma unroll
     for (int j = 0; j < kEll; ++j)
-      if (nr[k].e[j].col >= 0) add_regs(r, cnt, ovf, nr[k].e[j].col, le[k].val, nr[k].e[j].val);
+      if (u.e[j].col >= 0) add_regs(r, cnt, ovf, u.e[j].col, le[k].val, u.e[j].val);
   }
   for (int k = kNbPre; k < width; ++k) {  // slices wider than kNbPre
     const Ent l = A.lell[off + k * kSlice + lane];
@@ -364,45 +394,75 @@ __device__ __forceinline__ void write_regs(const RowBuf<kRowRegs>& r, int cnt, E
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) {
     if (!__any(s < cnt)) break;
-    if (r.out[s] > 0.f) {
+    if (r.lam[s] > 0.f) {
       int rank = 0;
 #pragma unroll
       for (int t = 0; t < kRowRegs; ++t) {
         if (!__any(t < cnt)) break;
-        rank += (r.out[t] > 0.f && r.col[t] < r.col[s]) ? 1 : 0;
+        rank += (r.lam[t] > 0.f && r.col[t] < r.col[s]) ? 1 : 0;
       }
-      dst[rank] = Ent{r.col[s], r.out[s]};
+      dst[rank] = Ent{r.col[s], r.lam[s]};
     }
   }
+}
+
+// kept register-path entries (at most kEll) as one fixed-width row
+__device__ __forceinline__ EllRow row_regs(const RowBuf<kRowRegs>& r, int cnt) {
+  EllRow o;
+#pragma unroll
+  for (int p = 0; p < kEll; ++p) o.e[p] = Ent{-1, 0.f};
+#pragma unroll
+  for (int s = 0; s < kRowRegs; ++s) {
+    if (!__any(s < cnt)) break;
+    int rank = 0;
+#pragma unroll
+    for (int t = 0; t < kRowRegs; ++t) {
+      if (!__any(t < cnt)) break;
+      rank += (r.lam[t] > 0.f && r.col[t] < r.col[s]) ? 1 : 0;
+    }
+    const bool kept = r.lam[s] > 0.f;
+#pragma unroll
+    for (int p = 0; p < kEll; ++p) {
+      const bool m = kept && rank == p;
+      o.e[p].col = m ? r.col[s] : o.e[p].col;
+      o.e[p].val = m ? r.lam[s] : o.e[p].val;
+    }
+  }
+  return o;
 }
 
 __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
     StepArgs A) {
   const int lane = threadIdx.x;
   const int sl = blockIdx.x;
-  if (__hip_atomic_load(&A.flags->poisoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    return;  // an earlier step of the chunk failed: nothing to do
+  // An earlier step of the chunk failed: write nothing, so that the last
+  // good fields (the input of the failed step, which this step would
+  // overwrite) survive for the replay.  The flag is set by atomics in an
+  // earlier launch; a scalar load sees it (caches are made coherent between
+  // launches) and costs no vector-memory round trip.
+  if (*(const __attribute__((address_space(4))) unsigned int*)&A.flags->poisoned) return;
   if (sl == 0 && lane == 0) {
     *A.ovf_ctr_next = 0u;
     *A.wide_ctr_next = 0u;
   }
-  const Slice S = A.slices[sl];
   const int i = sl * kSlice + lane;
 
   RowBuf<kRowRegs> r;
   int cnt = 0, n_keep = 0, n_skel = 0, n_in = 0, ev = 0, rowovf = 0;
   int wide = -1;  // workspace slot of a wide row
 #pragma unroll
-  for (int s = 0; s < kRowRegs; ++s) r.out[s] = -1.f;
+  for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
+  bool in_regs = false;
+  int off = 0, width = 0;
+  if (i < A.n_v) in_regs = gather_regs(r, cnt, n_in, i, lane, off, width, A);
   if (i < A.n_v) {
-    n_in = row_view(&A, i).n;
-    if (gather_regs(r, cnt, i, lane, S.off, S.width, A)) {
+    if (in_regs) {
       row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);
     } else {
       const unsigned slot = atomicAdd(A.wide_ctr, 1u);
       if (slot < (unsigned)A.wide_cap) {
         wide = (int)slot;
-        n_keep = wide_row(i, lane, S.off, S.width, &A, A.wide + slot, &n_skel, &ev, &rowovf);
+        n_keep = wide_row(i, lane, off, width, &A, A.wide + slot, &n_skel, &ev, &rowovf);
         if (rowovf) {
           step_failed(A, 2u);
           n_keep = 0;
@@ -426,6 +486,11 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
       row[2] = Ent{fits ? n_keep : 0, 0.f};
       row[3] = Ent{-1, 0.f};
       dst = fits ? A.ovf_out + o : nullptr;
+    } else if (wide < 0) {
+      // the whole row from registers: two 16-byte stores, contiguous across
+      // the wavefront
+      A.u_out[i] = row_regs(r, cnt);
+      dst = nullptr;
     } else {
       for (int p = n_keep; p < kEll; ++p) row[p] = Ent{-1, 0.f};
     }
