@@ -43,8 +43,11 @@ struct DevBuf {
 static StepArgs make_args(lf_fields* f, int parity) {
   StepArgs a;
   lf_mesh* m = f->mesh;
-  a.slices = m->slices;
   a.lell = m->lell;
+  a.lptr = m->lptr;
+  a.lent = m->lent;
+  a.op_w = m->op_w;
+  a.pad0_ = 0;
   a.ldiag = m->ldiag;
   a.u_in = f->ell[parity];
   a.u_out = f->ell[1 - parity];
@@ -233,10 +236,9 @@ lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_
     (void)hipFree(ldiag);
     return fail(LF_EINVAL, "zero-area face: cotangent weights undefined");
   }
-  Slice* slices = nullptr;
   Ent* lell = nullptr;
-  int64_t n_ell = 0;
-  hipError_t e = build_slices(lptr, lent, n_v, &slices, &lell, &n_ell, s);
+  int32_t op_w = 0;
+  hipError_t e = build_slices(lptr, lent, n_v, &lell, &op_w, s);
   if (e != hipSuccess) {
     (void)hipFree(lptr);
     (void)hipFree(lent);
@@ -254,8 +256,8 @@ lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_
   m->lent = lent;
   m->ldiag = ldiag;
   m->nnz_off = nnz;
-  m->slices = slices;
   m->lell = lell;
+  m->op_w = op_w;
   m->n_slices = (n_v + kSlice - 1) / kSlice;
   m->Vh.assign(V, V + 3ll * n_v);
   m->Fh.assign(F, F + 3ll * n_f);
@@ -271,7 +273,6 @@ lf_status lf_mesh_destroy(lf_mesh* m) {
   (void)hipFree(m->lptr);
   (void)hipFree(m->lent);
   (void)hipFree(m->ldiag);
-  (void)hipFree(m->slices);
   (void)hipFree(m->lell);
   delete m;
   return LF_OK;

@@ -32,13 +32,12 @@ struct __attribute__((aligned(32))) EllRow {
   Ent e[kEll];
 };
 
-// Operator slice: kSlice consecutive rows stored column-major, entry k of
-// row (first row of the slice + lane) at off + k * kSlice + lane; width is the
-// largest off-diagonal count of the slice, shorter rows padded with {-1, 0}.
-struct Slice {
-  int32_t off;
-  int32_t width;
-};
+// The operator's off-diagonal entries for the step, in slices of kSlice
+// rows stored column-major with one width w for all slices: entry k < w of
+// row i at ((i / kSlice) * w + k) * kSlice + i % kSlice, shorter rows padded
+// with {-1, 0}.  w = min(largest row, kOpWidth); a longer row keeps its
+// entries from w on in the CSR copy (lptr / lent), in the same order.
+constexpr int kOpWidth = 8;
 
 // Device-side step status.  Written by the step kernels, read by the host
 // once per issued chunk of steps.
@@ -77,8 +76,9 @@ struct WideRow {
 };
 
 struct StepArgs {
-  const Slice* slices;             // operator slices
-  const Ent* lell;                 // their entries
+  const Ent* lell;                 // operator slices (see kOpWidth)
+  const int32_t* lptr;             // operator CSR rows (entries beyond the slices)
+  const Ent* lent;
   const float* ldiag;              // operator diagonal
   const EllRow* u_in;              // fields U_t
   EllRow* u_out;                   // fields U_{t+1}
@@ -89,6 +89,8 @@ struct StepArgs {
   unsigned int* ovf_ctr_next;      // cleared here for the next step
   int32_t n_v;
   int32_t n_slices;
+  int32_t op_w;                    // slice width w
+  int32_t pad0_;
   StepConsts c;
   WideRow* wide;                   // workspace slots for wide rows
   int32_t wide_cap;
@@ -132,10 +134,9 @@ hipError_t build_operator(const double* V, const int32_t* F, int32_t n_v, int32_
                           int32_t** lptr, Ent** lent, float** ldiag, int64_t* nnz_off,
                           int* bad_face, hipStream_t s);
 
-// operator CSR (off-diagonal) -> slices; slices int32 n_sl, lell sized by
-// the returned entry count
-hipError_t build_slices(const int32_t* lptr, const Ent* lent, int32_t n_v, Slice** slices,
-                        Ent** lell, int64_t* n_ent, hipStream_t s);
+// operator CSR (off-diagonal) -> slices of one width (kOpWidth at most)
+hipError_t build_slices(const int32_t* lptr, const Ent* lent, int32_t n_v, Ent** lell,
+                        int32_t* width, hipStream_t s);
 // fields: fixed-width rows (+ overflow area) -> CSR (uptr must hold n_v + 1,
 // uent the entry count); counts int32 n_v scratch, tmp scan_tmp_elems(n_v)
 hipError_t ell_to_csr_ptr(const EllRow* u, int32_t n_v, int32_t* counts, int32_t* uptr,
@@ -197,8 +198,8 @@ struct lf_mesh {
   lf::Ent* lent;
   float* ldiag;     // diagonal of the operator
   int64_t nnz_off;
-  lf::Slice* slices;  // the same off-diagonal entries in slices of kSlice rows
-  lf::Ent* lell;
+  lf::Ent* lell;      // the same off-diagonal entries in slices of kSlice rows
+  int32_t op_w;       // their width
   int32_t n_slices;
   std::vector<double> Vh;  // host copies for small host-side geometry needs
   std::vector<int32_t> Fh;

@@ -45,31 +45,23 @@ __global__ void k_init_fields(const int32_t* owner, int32_t n_v, EllRow* u) {
 
 // ---- layouts: operator slices, fixed-width field rows <-> CSR -------------------
 
-// per slice: kSlice * (largest off-diagonal count of its rows)
-__global__ void k_slice_size(const int32_t* lptr, int32_t n_v, int32_t n_sl, int32_t* size,
-                             int32_t* width) {
-  const int sl = blockIdx.x * (blockDim.x / kSlice) + threadIdx.x / kSlice;
-  const int lane = threadIdx.x % kSlice;
-  if (sl >= n_sl) return;
-  const int i = sl * kSlice + lane;
+// largest off-diagonal count of any row
+__global__ void k_max_degree(const int32_t* lptr, int32_t n_v, int32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int d = i < n_v ? lptr[i + 1] - lptr[i] : 0;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, 64));
-  if (lane == 0) {
-    width[sl] = d;
-    size[sl] = d * kSlice;
-  }
+  if ((threadIdx.x & 63) == 0 && d > 0) atomicMax(out, d);
 }
 
 __global__ void k_slice_fill(const int32_t* lptr, const Ent* lent, int32_t n_v, int32_t n_sl,
-                             const int32_t* off, const int32_t* width, Slice* slices, Ent* lell) {
+                             int32_t w, Ent* lell) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int sl = i / kSlice, lane = i % kSlice;
   if (sl >= n_sl) return;
-  const int w = width[sl], o = off[sl];
-  if (lane == 0) slices[sl] = Slice{o, w};
   const int a = i < n_v ? lptr[i] : 0, n = i < n_v ? lptr[i + 1] - a : 0;
-  for (int k = 0; k < w; ++k) lell[o + k * kSlice + lane] = k < n ? lent[a + k] : Ent{-1, 0.f};
+  for (int k = 0; k < w; ++k)
+    lell[((int64_t)sl * w + k) * kSlice + lane] = k < n ? lent[a + k] : Ent{-1, 0.f};
 }
 
 __global__ void k_ell_count(const EllRow* u, int32_t n_v, int32_t* cnt) {
@@ -434,46 +426,34 @@ fail:
 #undef TRY
 }
 
-hipError_t build_slices(const int32_t* lptr, const Ent* lent, int32_t n_v, Slice** slices,
-                        Ent** lell, int64_t* n_ent, hipStream_t s) {
-  *slices = nullptr;
+hipError_t build_slices(const int32_t* lptr, const Ent* lent, int32_t n_v, Ent** lell,
+                        int32_t* width, hipStream_t s) {
   *lell = nullptr;
   const int32_t n_sl = (n_v + kSlice - 1) / kSlice;
-  int32_t *size = nullptr, *width = nullptr, *off = nullptr;
-  long long* tmp = nullptr;
-  hipError_t e = dalloc(&size, n_sl);
-  if (e == hipSuccess) e = dalloc(&width, n_sl);
-  if (e == hipSuccess) e = dalloc(&off, n_sl + 1);
-  if (e == hipSuccess) e = dalloc(&tmp, scan_tmp_elems(n_sl));
+  int32_t* dmax = nullptr;
+  hipError_t e = dalloc(&dmax, 1);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_slice_size, dim3(blocks_for(n_sl, kT / kSlice)), dim3(kT), 0, s, lptr,
-                       n_v, n_sl, size, width);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kT), 0, s, dmax, (int64_t)1, 0);
+    hipLaunchKernelGGL(k_max_degree, dim3(blocks_for(n_v)), dim3(kT), 0, s, lptr, n_v, dmax);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = exclusive_scan(size, off, n_sl, tmp, s);
-  int32_t total = 0;
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(&total, off + n_sl, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  int32_t d = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&d, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess) e = dalloc(slices, n_sl);
-  if (e == hipSuccess) e = dalloc(lell, total);
-  if (e == hipSuccess) {
+  (void)hipFree(dmax);
+  const int32_t w = d < kOpWidth ? d : kOpWidth;
+  if (e == hipSuccess) e = dalloc(lell, (int64_t)n_sl * kSlice * (w > 0 ? w : 1));
+  if (e == hipSuccess && w > 0) {
     hipLaunchKernelGGL(k_slice_fill, dim3(blocks_for((int64_t)n_sl * kSlice)), dim3(kT), 0, s,
-                       lptr, lent, n_v, n_sl, off, width, *slices, *lell);
+                       lptr, lent, n_v, n_sl, w, *lell);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(size);
-  (void)hipFree(width);
-  (void)hipFree(off);
-  (void)hipFree(tmp);
   if (e != hipSuccess) {
-    (void)hipFree(*slices);
     (void)hipFree(*lell);
-    *slices = nullptr;
     *lell = nullptr;
   }
-  *n_ent = total;
+  *width = w;
   return e;
 }
 

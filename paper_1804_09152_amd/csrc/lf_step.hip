@@ -22,7 +22,8 @@
 // one aligned segment; longer rows, rare, live in an overflow area), so a
 // row's output position is known before the step: no compaction scan, no
 // ordering between wavefronts.  The operator slice is stored column-major,
-// so the k-th neighbours of the 64 rows are one contiguous 512-byte load.
+// so the k-th neighbours of the 64 rows are one contiguous 512-byte load
+// whose address follows from the wavefront's index alone.
 // A row's data arrive in two dependent rounds (its own row, diagonal and
 // operator entries; then the rows of its neighbours); the union of layers
 // (typically 1-4) is accumulated in 8 register slots; a row with more
@@ -234,16 +235,13 @@ __device__ __forceinline__ bool is_ovf(const Ent& e) { return e.col == kOvfMark;
 // then the neighbours' rows).  Returns false when the row needs the wide
 // path: more than kRowRegs layers, or an overflow row among its inputs.
 __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n_in, int i,
-                                            int lane, int& off, int& width, const StepArgs& A) {
+                                            const Ent* ops, const StepArgs& A) {
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   cnt = 0;
   // own row and diagonal first: they do not wait for the slice descriptor
   const EllRow own = A.u_in[i];
   const float dg = A.ldiag[i];
-  const Slice S = A.slices[i / kSlice];
-  off = S.off;
-  width = S.width;
   // entries of U_t in this row (for the counters)
   n_in = 0;
 #pragma unroll
@@ -252,7 +250,7 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& 
   Ent le[kNbPre];
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k)
-    le[k] = k < width ? A.lell[off + k * kSlice + lane] : Ent{-1, 0.f};
+    le[k] = k < A.op_w ? ops[k * kSlice] : Ent{-1, 0.f};
   // neighbour rows stream through a window of kWin rows: the row of
   // neighbour k + kWin is requested before neighbour k is merged, so a few
   // loads stay in flight without holding every neighbour row in registers
@@ -285,18 +283,20 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& 
     for (int j = 0; j < kEll; ++j)
       if (u.e[j].col >= 0) add_regs(r, cnt, ovf, u.e[j].col, le[k].val, u.e[j].val);
   }
-  for (int k = kNbPre; k < width; ++k) {  // slices wider than kNbPre
-    const Ent l = A.lell[off + k * kSlice + lane];
-    if (l.col < 0) continue;
+  auto more = [&](const Ent& l) {  // neighbours beyond the prefetched ones
+    if (l.col < 0) return;
     const EllRow u = A.u_in[l.col];
     if (is_ovf(u.e[0])) {
       ovf = true;
-      continue;
+      return;
     }
 #pragma unroll
     for (int j = 0; j < kEll; ++j)
       if (u.e[j].col >= 0) add_regs(r, cnt, ovf, u.e[j].col, l.val, u.e[j].val);
-  }
+  };
+  for (int k = kNbPre; k < A.op_w; ++k) more(ops[k * kSlice]);
+  if (A.op_w == kOpWidth && ops[(kOpWidth - 1) * kSlice].col >= 0)  // rows beyond the slices
+    for (int q = A.lptr[i] + kOpWidth; q < A.lptr[i + 1]; ++q) more(A.lent[q]);
   return !ovf;
 }
 
@@ -323,8 +323,8 @@ __device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
 // Same arithmetic in the same order as the register path, with kRowWide
 // slots in a global-memory workspace row.  Returns the number of kept
 // entries (0 and *ovf set when the row touches more than kRowWide layers).
-__device__ __forceinline__ int wide_row(int i, int lane, int off, int width, const StepArgs* A,
-                                        WideRow* r, int* n_skel, int* ev, int* ovf) {
+__device__ __forceinline__ int wide_row(int i, const Ent* ops, const StepArgs* A, WideRow* r,
+                                        int* n_skel, int* ev, int* ovf) {
   int cnt = 0;
   *n_skel = 0;
   *ev = 0;
@@ -338,8 +338,9 @@ __device__ __forceinline__ int wide_row(int i, int lane, int off, int width, con
     r->lam[cnt] = dg * e.val;
     ++cnt;
   }
-  for (int k = 0; k < width; ++k) {
-    const Ent le = A->lell[off + k * kSlice + lane];
+  const int q0 = A->lptr[i], deg = A->lptr[i + 1] - q0;
+  for (int k = 0; k < deg; ++k) {
+    const Ent le = k < A->op_w ? ops[k * kSlice] : A->lent[q0 + k];
     if (le.col < 0) continue;
     const RowView v = row_view(A, le.col);
     for (int p = 0; p < v.n; ++p) {
@@ -453,8 +454,9 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   bool in_regs = false;
-  int off = 0, width = 0;
-  if (i < A.n_v) in_regs = gather_regs(r, cnt, n_in, i, lane, off, width, A);
+  // this row's operator entries: column-major in the wavefront's slice
+  const Ent* ops = A.lell + (int64_t)sl * A.op_w * kSlice + lane;
+  if (i < A.n_v) in_regs = gather_regs(r, cnt, n_in, i, ops, A);
   if (i < A.n_v) {
     if (in_regs) {
       row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);
@@ -462,7 +464,7 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
       const unsigned slot = atomicAdd(A.wide_ctr, 1u);
       if (slot < (unsigned)A.wide_cap) {
         wide = (int)slot;
-        n_keep = wide_row(i, lane, off, width, &A, A.wide + slot, &n_skel, &ev, &rowovf);
+        n_keep = wide_row(i, ops, &A, A.wide + slot, &n_skel, &ev, &rowovf);
         if (rowovf) {
           step_failed(A, 2u);
           n_keep = 0;
