@@ -63,6 +63,42 @@ def traffic_from_profile(alg_bytes_per_launch: float):
     return d.get("hbm_bytes_per_launch")
 
 
+def _counter_means(d: str, kernel: str):
+    """Mean per dispatch of each counter of `kernel` in a rocprofv3 CSV folder."""
+    import csv
+    import glob
+    acc = {}
+    for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            if kernel in r["Kernel_Name"]:
+                acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def summarize_counters(fetch_dir, write_dir, copyf_dir, copyw_dir, probe_mib, out_path):
+    """HBM bytes per step-kernel launch from FETCH_SIZE / WRITE_SIZE runs,
+    each scaled by what the same counter reads for a device copy of known
+    size (the copy probe of this script)."""
+    probe = probe_mib * (1 << 20)
+    cf, _ = _counter_means(copyf_dir, "copyBuffer")
+    cw, _ = _counter_means(copyw_dir, "copyBuffer")
+    kf, nf = _counter_means(fetch_dir, "k_step")
+    kw, nw = _counter_means(write_dir, "k_step")
+    f_scale = probe / (cf["FETCH_SIZE"] * 1024)
+    w_scale = probe / (cw["WRITE_SIZE"] * 1024)
+    fetch = kf["FETCH_SIZE"] * 1024 * f_scale
+    write = kw["WRITE_SIZE"] * 1024 * w_scale
+    d = {"kernel": "k_step", "kernel_src_sha": kernel_source_sha(),
+         "fetch_size_kib_per_launch": kf["FETCH_SIZE"], "write_size_kib_per_launch": kw["WRITE_SIZE"],
+         "launches": [nf["FETCH_SIZE"], nw["WRITE_SIZE"]],
+         "copy_probe_bytes": probe, "fetch_scale": f_scale, "write_scale": w_scale,
+         "hbm_read_bytes_per_launch": fetch, "hbm_write_bytes_per_launch": write,
+         "hbm_bytes_per_launch": fetch + write}
+    with open(out_path, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps(d))
+
+
 def cpu_baseline(mesh, seeds, seconds: float, max_steps: int = 200):
     import oracle
     oracle.build()
@@ -228,10 +264,17 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
+                    help="only summarize rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the step "
+                         "kernel and of the copy probe into profiles/k_step_c3_counters.json")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB ten times (calibrates "
                          "the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.counters:
+        summarize_counters(*args.counters, probe_mib=1024,
+                           out_path=os.path.join(ROOT, "profiles", "k_step_c3_counters.json"))
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe * (1 << 20) // 4
