@@ -44,11 +44,11 @@ static StepArgs make_args(lf_fields* f, int parity) {
   StepArgs a;
   lf_mesh* m = f->mesh;
   a.lell = m->lell;
-  a.lptr = m->lptr;
-  a.lent = m->lent;
+  a.lptr = m->slptr;
+  a.lent = m->slent;
   a.op_w = m->op_w;
   a.pad0_ = 0;
-  a.ldiag = m->ldiag;
+  a.ldiag = m->sldiag;
   a.u_in = f->ell[parity];
   a.u_out = f->ell[1 - parity];
   a.ovf_in = f->ovf[parity];
@@ -140,8 +140,8 @@ lf_status fields_csr(lf_fields* f, const int32_t** uptr, const Ent** uent) {
     const int32_t n_v = f->mesh->n_v;
     lf_status st = reserve_csr(f, f->nnz);
     if (st) return st;
-    LF_HIP(ell_to_csr_ptr(f->ell[f->cur], n_v, f->owner, f->uptr, f->scan_tmp, s));
-    LF_HIP(ell_to_csr_fill(f->ell[f->cur], f->ovf[f->cur], n_v, f->uptr, f->uent, s));
+    LF_HIP(ell_to_csr_ptr(f->ell[f->cur], f->mesh->inv, n_v, f->owner, f->uptr, f->scan_tmp, s));
+    LF_HIP(ell_to_csr_fill(f->ell[f->cur], f->ovf[f->cur], f->mesh->inv, n_v, f->uptr, f->uent, s));
     f->csr_valid = true;
   }
   *uptr = f->uptr;
@@ -202,8 +202,56 @@ lf_status lf_ctx_destroy(lf_ctx* c) {
   return LF_OK;
 }
 
-lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* F, int32_t n_f,
-                         int32_t op, lf_mesh** out) {
+}  // extern "C"
+
+namespace lf {
+
+// spreads the low 21 bits of x to every third bit
+static uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+// Vertex order of the step: within each part [part_off[p], part_off[p+1]),
+// vertices sorted along a Morton (Z-order) curve of their positions, so
+// that a vertex's neighbours are mostly close to it in memory.
+static std::vector<int32_t> locality_order(const double* V, const int32_t* part_off,
+                                           int32_t n_parts) {
+  std::vector<int32_t> perm((size_t)part_off[n_parts]);
+  std::vector<std::pair<uint64_t, int32_t>> key;
+  for (int32_t p = 0; p < n_parts; ++p) {
+    const int32_t a = part_off[p], b = part_off[p + 1];
+    double lo[3] = {V[3ll * a], V[3ll * a + 1], V[3ll * a + 2]}, hi[3] = {lo[0], lo[1], lo[2]};
+    for (int32_t v = a; v < b; ++v)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = std::min(lo[d], V[3ll * v + d]);
+        hi[d] = std::max(hi[d], V[3ll * v + d]);
+      }
+    key.resize((size_t)(b - a));
+    for (int32_t v = a; v < b; ++v) {
+      uint64_t c = 0;
+      for (int d = 0; d < 3; ++d) {
+        const double span = hi[d] - lo[d];
+        double t = span > 0 ? (V[3ll * v + d] - lo[d]) / span : 0.0;
+        if (!(t >= 0.0)) t = 0.0;  // also NaN
+        if (t > 1.0) t = 1.0;
+        c |= spread3((uint64_t)(t * 2097151.0)) << d;
+      }
+      key[(size_t)(v - a)] = {c, v};
+    }
+    std::sort(key.begin(), key.end());
+    for (int32_t v = a; v < b; ++v) perm[(size_t)v] = key[(size_t)(v - a)].second;
+  }
+  return perm;
+}
+
+lf_status mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* F, int32_t n_f,
+                      int32_t op, const int32_t* part_off, int32_t n_parts, lf_mesh** out) {
   if (!ctx || !V || !F || !out) return fail(LF_EINVAL, "NULL argument");
   *out = nullptr;
   if (n_v < 3 || n_v >= kMaxVerts || n_f < 1 || (int64_t)n_f > 4ll * n_v)
@@ -218,51 +266,59 @@ lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_
   }
   LF_HIP(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
-  DevBuf<double> dV;
-  DevBuf<int32_t> dF;
-  LF_HIP(dV.alloc(3ll * n_v));
-  LF_HIP(dF.alloc(3ll * n_f));
-  LF_HIP(hipMemcpyAsync(dV.p, V, sizeof(double) * 3 * n_v, hipMemcpyHostToDevice, s));
-  LF_HIP(hipMemcpyAsync(dF.p, F, sizeof(int32_t) * 3 * n_f, hipMemcpyHostToDevice, s));
-  int32_t* lptr = nullptr;
-  Ent* lent = nullptr;
-  float* ldiag = nullptr;
-  int64_t nnz = 0;
-  int bad = 0;
-  LF_HIP(build_operator(dV.p, dF.p, n_v, n_f, op, &lptr, &lent, &ldiag, &nnz, &bad, s));
-  if (bad) {
-    (void)hipFree(lptr);
-    (void)hipFree(lent);
-    (void)hipFree(ldiag);
-    return fail(LF_EINVAL, "zero-area face: cotangent weights undefined");
-  }
-  Ent* lell = nullptr;
-  int32_t op_w = 0;
-  hipError_t e = build_slices(lptr, lent, n_v, &lell, &op_w, s);
-  if (e != hipSuccess) {
-    (void)hipFree(lptr);
-    (void)hipFree(lent);
-    (void)hipFree(ldiag);
-    return hip_fail(e, "operator slices");
-  }
   lf_mesh* m = new lf_mesh();
   m->ctx = ctx;
   m->n_v = n_v;
   m->n_f = n_f;
   m->op = op;
-  m->V = dV.release();
-  m->F = dF.release();
-  m->lptr = lptr;
-  m->lent = lent;
-  m->ldiag = ldiag;
-  m->nnz_off = nnz;
-  m->lell = lell;
-  m->op_w = op_w;
   m->n_slices = (n_v + kSlice - 1) / kSlice;
+  auto bail = [&](hipError_t e, const char* what) {
+    lf_mesh_destroy(m);
+    return hip_fail(e, what);
+  };
+  hipError_t e = dalloc(&m->V, 3ll * n_v);
+  if (e == hipSuccess) e = dalloc(&m->F, 3ll * n_f);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->V, V, sizeof(double) * 3 * n_v, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->F, F, sizeof(int32_t) * 3 * n_f, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return bail(e, "mesh upload");
+  int bad = 0;
+  e = build_operator(m->V, m->F, n_v, n_f, op, &m->lptr, &m->lent, &m->ldiag, &m->nnz_off, &bad, s);
+  if (e != hipSuccess) return bail(e, "operator");
+  if (bad) {
+    lf_mesh_destroy(m);
+    return fail(LF_EINVAL, "zero-area face: cotangent weights undefined");
+  }
+  // the step's vertex order and its copy of the operator
+  const std::vector<int32_t> perm = locality_order(V, part_off, n_parts);
+  std::vector<int32_t> inv((size_t)n_v);
+  for (int32_t k = 0; k < n_v; ++k) inv[(size_t)perm[(size_t)k]] = k;
+  e = dalloc(&m->perm, n_v);
+  if (e == hipSuccess) e = dalloc(&m->inv, n_v);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->perm, perm.data(), sizeof(int32_t) * n_v, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->inv, inv.data(), sizeof(int32_t) * n_v, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = permute_operator(m->lptr, m->lent, m->ldiag, m->perm, m->inv, n_v, m->nnz_off, &m->slptr,
+                         &m->slent, &m->sldiag, s);
+  if (e == hipSuccess) e = build_slices(m->slptr, m->slent, n_v, &m->lell, &m->op_w, s);
+  if (e != hipSuccess) return bail(e, "operator in step order");
   m->Vh.assign(V, V + 3ll * n_v);
   m->Fh.assign(F, F + 3ll * n_f);
   *out = m;
   return LF_OK;
+}
+
+}  // namespace lf
+
+extern "C" {
+
+lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* F, int32_t n_f,
+                         int32_t op, lf_mesh** out) {
+  const int32_t part[2] = {0, n_v};
+  return mesh_create(ctx, V, n_v, F, n_f, op, part, 1, out);
 }
 
 lf_status lf_mesh_destroy(lf_mesh* m) {
@@ -274,6 +330,11 @@ lf_status lf_mesh_destroy(lf_mesh* m) {
   (void)hipFree(m->lent);
   (void)hipFree(m->ldiag);
   (void)hipFree(m->lell);
+  (void)hipFree(m->perm);
+  (void)hipFree(m->inv);
+  (void)hipFree(m->slptr);
+  (void)hipFree(m->slent);
+  (void)hipFree(m->sldiag);
   delete m;
   return LF_OK;
 }
@@ -326,7 +387,7 @@ static lf_status init_fields(lf_fields* f) {
   LF_HIP(launch_fill_i32(f->owner, n_v, f->n_s, s));
   LF_HIP(launch_scatter_owner(f->d_seeds, f->n_s, f->owner, s));
   f->cur = 0;
-  LF_HIP(launch_init_fields(f->owner, n_v, f->ell[0], s));
+  LF_HIP(launch_init_fields(f->owner, f->mesh->perm, n_v, f->ell[0], s));
   f->nnz = n_v;
   f->csr_valid = false;
   lf_status st = clear_step_state(f);
@@ -666,7 +727,7 @@ lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, con
   if (hb) return fail(LF_EINVAL, "imported fields are not canonical (code " + std::to_string(hb) + ")");
   LF_HIP(hipMemcpyAsync(f->uptr, p, sizeof(int32_t) * (n_v + 1), hipMemcpyDeviceToDevice, s));
   const int tgt = 1 - f->cur;
-  LF_HIP(csr_to_ell(f->uptr, f->uent, n_v, f->ell[tgt], f->ovf[tgt], s));
+  LF_HIP(csr_to_ell(f->uptr, f->uent, f->mesh->inv, n_v, f->ell[tgt], f->ovf[tgt], s));
   f->cur = tgt;
   f->nnz = nnz;
   f->csr_valid = true;

@@ -116,7 +116,10 @@ lf_status lf_batch_create(lf_ctx* ctx, int32_t n, const double* const* V, const 
     so += n_s[m];
   }
   b->base = (int32_t)ts;
-  lf_status st = lf_mesh_create(ctx, Vc.data(), (int32_t)tv, Fc.data(), (int32_t)tf, op, &b->mesh);
+  std::vector<int32_t> parts(b->voff);
+  parts.push_back((int32_t)tv);
+  lf_status st = lf::mesh_create(ctx, Vc.data(), (int32_t)tv, Fc.data(), (int32_t)tf, op,
+                                 parts.data(), n, &b->mesh);
   if (st) {
     delete b;
     return st;

@@ -118,7 +118,8 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent
 hipError_t launch_reset_flags(StepFlags* f, StepStats* parts, int64_t n, hipStream_t s);
 // folds the partial counters of n steps into one StepStats per step
 hipError_t launch_reduce_parts(const StepStats* parts, int64_t n, StepStats* out, hipStream_t s);
-hipError_t launch_init_fields(const int32_t* owner, int32_t n_v, EllRow* u, hipStream_t s);
+hipError_t launch_init_fields(const int32_t* owner, const int32_t* perm, int32_t n_v, EllRow* u,
+                              hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owner, hipStream_t s);
@@ -137,16 +138,27 @@ hipError_t build_operator(const double* V, const int32_t* F, int32_t n_v, int32_
 // operator CSR (off-diagonal) -> slices of one width (kOpWidth at most)
 hipError_t build_slices(const int32_t* lptr, const Ent* lent, int32_t n_v, Ent** lell,
                         int32_t* width, hipStream_t s);
-// fields: fixed-width rows (+ overflow area) -> CSR (uptr must hold n_v + 1,
-// uent the entry count); counts int32 n_v scratch, tmp scan_tmp_elems(n_v)
-hipError_t ell_to_csr_ptr(const EllRow* u, int32_t n_v, int32_t* counts, int32_t* uptr,
-                          long long* tmp, hipStream_t s);
-hipError_t ell_to_csr_fill(const EllRow* u, const Ent* ovf, int32_t n_v, const int32_t* uptr,
-                           Ent* uent, hipStream_t s);
-// canonical CSR -> fixed-width rows; rows longer than kEll keep their
-// entries at their CSR offsets in ovf (which holds at least nnz entries)
-hipError_t csr_to_ell(const int32_t* uptr, const Ent* uent, int32_t n_v, EllRow* u, Ent* ovf,
-                      hipStream_t s);
+// The step works in its own vertex order (a locality-preserving order chosen
+// at mesh creation): fields row k and step-operator row k belong to vertex
+// perm[k]; vertex v is row inv[v].  Everything at the boundary (CSR view,
+// import, seeds, labels) is in the caller's order.
+// fields: fixed-width rows (+ overflow area) -> CSR in the caller's order
+// (uptr must hold n_v + 1, uent the entry count); counts int32 n_v
+// scratch, tmp scan_tmp_elems(n_v)
+hipError_t ell_to_csr_ptr(const EllRow* u, const int32_t* inv, int32_t n_v, int32_t* counts,
+                          int32_t* uptr, long long* tmp, hipStream_t s);
+hipError_t ell_to_csr_fill(const EllRow* u, const Ent* ovf, const int32_t* inv, int32_t n_v,
+                           const int32_t* uptr, Ent* uent, hipStream_t s);
+// canonical CSR (caller's order) -> fixed-width rows; rows longer than kEll
+// keep their entries at their CSR offsets in ovf (which holds at least nnz
+// entries)
+hipError_t csr_to_ell(const int32_t* uptr, const Ent* uent, const int32_t* inv, int32_t n_v,
+                      EllRow* u, Ent* ovf, hipStream_t s);
+// the operator in the step's order (rows permuted, columns renumbered,
+// entries of a row in their original order)
+hipError_t permute_operator(const int32_t* lptr, const Ent* lent, const float* ldiag,
+                            const int32_t* perm, const int32_t* inv, int32_t n_v, int64_t nnz,
+                            int32_t** plptr, Ent** plent, float** pldiag, hipStream_t s);
 
 hipError_t launch_split(const Ent* e, int64_t n, int32_t* col, float* val, hipStream_t s);
 hipError_t launch_join_check(const int32_t* col, const float* val, const int32_t* ptr,
@@ -157,6 +169,12 @@ hipError_t launch_operator_export(const int32_t* lptr, const Ent* lent, const fl
                                   hipStream_t s);
 hipError_t launch_labels(const int32_t* uptr, const Ent* uent, int32_t n_v, int32_t n_s,
                          int32_t* labels, hipStream_t s);
+
+// lf_mesh_create with the vertex order of the step chosen per part: the
+// vertices of part p are [part_off[p], part_off[p+1]) (a batch keeps each
+// mesh's rows together)
+lf_status mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* F, int32_t n_f,
+                      int32_t op, const int32_t* part_off, int32_t n_parts, lf_mesh** out);
 
 // releases the dual-mesh state of a field object
 void dual_release(lf_fields* f);
@@ -194,12 +212,17 @@ struct lf_mesh {
   int32_t n_v, n_f, op;
   double* V;        // device float64 positions
   int32_t* F;       // device triangles
-  int32_t* lptr;    // off-diagonal operator, CSR
+  int32_t* lptr;    // off-diagonal operator, CSR, caller's vertex order
   lf::Ent* lent;
   float* ldiag;     // diagonal of the operator
   int64_t nnz_off;
-  lf::Ent* lell;      // the same off-diagonal entries in slices of kSlice rows
-  int32_t op_w;       // their width
+  int32_t* perm;    // step order: row k is vertex perm[k]
+  int32_t* inv;     // vertex v is row inv[v]
+  int32_t* slptr;   // the operator in the step's order
+  lf::Ent* slent;
+  float* sldiag;
+  lf::Ent* lell;    // the same off-diagonal entries in slices of kSlice rows
+  int32_t op_w;     // their width
   int32_t n_slices;
   std::vector<double> Vh;  // host copies for small host-side geometry needs
   std::vector<int32_t> Fh;

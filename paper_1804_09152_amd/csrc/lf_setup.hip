@@ -32,11 +32,12 @@ __global__ void k_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owne
 }
 
 // owner[v] = seed index of v, or n_s (the base layer) for unseeded vertices
-__global__ void k_init_fields(const int32_t* owner, int32_t n_v, EllRow* u) {
+// (fields rows are in the step's vertex order: row k holds vertex perm[k])
+__global__ void k_init_fields(const int32_t* owner, const int32_t* perm, int32_t n_v, EllRow* u) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_v) {
     EllRow r;
-    r.e[0] = Ent{owner[i], 1.0f};
+    r.e[0] = Ent{owner[perm[i]], 1.0f};
 #pragma unroll
     for (int j = 1; j < kEll; ++j) r.e[j] = Ent{-1, 0.f};
     u[i] = r;
@@ -64,10 +65,11 @@ __global__ void k_slice_fill(const int32_t* lptr, const Ent* lent, int32_t n_v, 
     lell[((int64_t)sl * w + k) * kSlice + lane] = k < n ? lent[a + k] : Ent{-1, 0.f};
 }
 
-__global__ void k_ell_count(const EllRow* u, int32_t n_v, int32_t* cnt) {
+// CSR row i (caller's vertex order) is fields row inv[i]
+__global__ void k_ell_count(const EllRow* u, const int32_t* inv, int32_t n_v, int32_t* cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_v) return;
-  const EllRow r = u[i];
+  const EllRow r = u[inv[i]];
   int n = 0;
   if (r.e[0].col == kOvfMark) {
     n = r.e[2].col;
@@ -78,11 +80,11 @@ __global__ void k_ell_count(const EllRow* u, int32_t n_v, int32_t* cnt) {
   cnt[i] = n;
 }
 
-__global__ void k_ell_fill(const EllRow* u, const Ent* ovf, int32_t n_v, const int32_t* uptr,
-                           Ent* uent) {
+__global__ void k_ell_fill(const EllRow* u, const Ent* ovf, const int32_t* inv, int32_t n_v,
+                           const int32_t* uptr, Ent* uent) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_v) return;
-  const EllRow r = u[i];
+  const EllRow r = u[inv[i]];
   const int32_t o = uptr[i], n = uptr[i + 1] - o;
   if (r.e[0].col == kOvfMark) {
     const Ent* src = ovf + r.e[1].col;
@@ -92,8 +94,8 @@ __global__ void k_ell_fill(const EllRow* u, const Ent* ovf, int32_t n_v, const i
   }
 }
 
-__global__ void k_csr_to_ell(const int32_t* uptr, const Ent* uent, int32_t n_v, EllRow* u,
-                             Ent* ovf) {
+__global__ void k_csr_to_ell(const int32_t* uptr, const Ent* uent, const int32_t* inv,
+                             int32_t n_v, EllRow* u, Ent* ovf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_v) return;
   const int32_t a = uptr[i], n = uptr[i + 1] - a;
@@ -108,7 +110,27 @@ __global__ void k_csr_to_ell(const int32_t* uptr, const Ent* uent, int32_t n_v, 
 #pragma unroll
     for (int j = 0; j < kEll; ++j) r.e[j] = j < n ? uent[a + j] : Ent{-1, 0.f};
   }
-  u[i] = r;
+  u[inv[i]] = r;
+}
+
+// the step's operator: row k is vertex perm[k], columns renumbered through
+// inv, entries kept in their order (so every row sums in the same order)
+__global__ void k_perm_count(const int32_t* lptr, const int32_t* perm, int32_t n_v, int32_t* cnt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_v) cnt[k] = lptr[perm[k] + 1] - lptr[perm[k]];
+}
+
+__global__ void k_perm_fill(const int32_t* lptr, const Ent* lent, const float* ldiag,
+                            const int32_t* perm, const int32_t* inv, int32_t n_v,
+                            const int32_t* plptr, Ent* plent, float* pldiag) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_v) return;
+  const int32_t v = perm[k], a = lptr[v], n = lptr[v + 1] - a, o = plptr[k];
+  for (int j = 0; j < n; ++j) {
+    const Ent e = lent[a + j];
+    plent[o + j] = Ent{inv[e.col], e.val};
+  }
+  pldiag[k] = ldiag[v];
 }
 
 // ---- exclusive scan -------------------------------------------------------------
@@ -345,8 +367,9 @@ hipError_t launch_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owne
   hipLaunchKernelGGL(k_scatter_owner, dim3(blocks_for(n_s)), dim3(kT), 0, s, seeds, n_s, owner);
   return hipGetLastError();
 }
-hipError_t launch_init_fields(const int32_t* owner, int32_t n_v, EllRow* u, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_fields, dim3(blocks_for(n_v)), dim3(kT), 0, s, owner, n_v, u);
+hipError_t launch_init_fields(const int32_t* owner, const int32_t* perm, int32_t n_v, EllRow* u,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_init_fields, dim3(blocks_for(n_v)), dim3(kT), 0, s, owner, perm, n_v, u);
   return hipGetLastError();
 }
 
@@ -457,24 +480,63 @@ hipError_t build_slices(const int32_t* lptr, const Ent* lent, int32_t n_v, Ent**
   return e;
 }
 
-hipError_t ell_to_csr_ptr(const EllRow* u, int32_t n_v, int32_t* counts, int32_t* uptr,
-                          long long* tmp, hipStream_t s) {
-  hipLaunchKernelGGL(k_ell_count, dim3(blocks_for(n_v)), dim3(kT), 0, s, u, n_v, counts);
+hipError_t ell_to_csr_ptr(const EllRow* u, const int32_t* inv, int32_t n_v, int32_t* counts,
+                          int32_t* uptr, long long* tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_ell_count, dim3(blocks_for(n_v)), dim3(kT), 0, s, u, inv, n_v, counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return exclusive_scan(counts, uptr, n_v, tmp, s);
 }
 
-hipError_t ell_to_csr_fill(const EllRow* u, const Ent* ovf, int32_t n_v, const int32_t* uptr,
-                           Ent* uent, hipStream_t s) {
-  hipLaunchKernelGGL(k_ell_fill, dim3(blocks_for(n_v)), dim3(kT), 0, s, u, ovf, n_v, uptr, uent);
+hipError_t ell_to_csr_fill(const EllRow* u, const Ent* ovf, const int32_t* inv, int32_t n_v,
+                           const int32_t* uptr, Ent* uent, hipStream_t s) {
+  hipLaunchKernelGGL(k_ell_fill, dim3(blocks_for(n_v)), dim3(kT), 0, s, u, ovf, inv, n_v, uptr,
+                     uent);
   return hipGetLastError();
 }
 
-hipError_t csr_to_ell(const int32_t* uptr, const Ent* uent, int32_t n_v, EllRow* u, Ent* ovf,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_csr_to_ell, dim3(blocks_for(n_v)), dim3(kT), 0, s, uptr, uent, n_v, u, ovf);
+hipError_t csr_to_ell(const int32_t* uptr, const Ent* uent, const int32_t* inv, int32_t n_v,
+                      EllRow* u, Ent* ovf, hipStream_t s) {
+  hipLaunchKernelGGL(k_csr_to_ell, dim3(blocks_for(n_v)), dim3(kT), 0, s, uptr, uent, inv, n_v, u,
+                     ovf);
   return hipGetLastError();
+}
+
+hipError_t permute_operator(const int32_t* lptr, const Ent* lent, const float* ldiag,
+                            const int32_t* perm, const int32_t* inv, int32_t n_v, int64_t nnz,
+                            int32_t** plptr, Ent** plent, float** pldiag, hipStream_t s) {
+  *plptr = nullptr;
+  *plent = nullptr;
+  *pldiag = nullptr;
+  int32_t* cnt = nullptr;
+  long long* tmp = nullptr;
+  hipError_t e = dalloc(&cnt, n_v);
+  if (e == hipSuccess) e = dalloc(&tmp, scan_tmp_elems(n_v));
+  if (e == hipSuccess) e = dalloc(plptr, n_v + 1);
+  if (e == hipSuccess) e = dalloc(plent, nnz);
+  if (e == hipSuccess) e = dalloc(pldiag, n_v);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_perm_count, dim3(blocks_for(n_v)), dim3(kT), 0, s, lptr, perm, n_v, cnt);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = exclusive_scan(cnt, *plptr, n_v, tmp, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_perm_fill, dim3(blocks_for(n_v)), dim3(kT), 0, s, lptr, lent, ldiag,
+                       perm, inv, n_v, *plptr, *plent, *pldiag);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(cnt);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    (void)hipFree(*plptr);
+    (void)hipFree(*plent);
+    (void)hipFree(*pldiag);
+    *plptr = nullptr;
+    *plent = nullptr;
+    *pldiag = nullptr;
+  }
+  return e;
 }
 
 hipError_t launch_split(const Ent* e, int64_t n, int32_t* col, float* val, hipStream_t s) {

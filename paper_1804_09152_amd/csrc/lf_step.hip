@@ -221,6 +221,7 @@ __device__ __forceinline__ void add_regs(RowBuf<kRowRegs>& r, int& cnt, bool& ov
   }
 }
 
+constexpr int kXcds = 8;   // accelerator dies of the MI355X, each with its own L2
 constexpr int kNbPre = 7;  // neighbours whose operator entries are prefetched
 #ifndef LF_WIN
 #define LF_WIN 4
@@ -435,7 +436,12 @@ __device__ __forceinline__ EllRow row_regs(const RowBuf<kRowRegs>& r, int cnt) {
 __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
     StepArgs A) {
   const int lane = threadIdx.x;
-  const int sl = blockIdx.x;
+  // XCD-aware: workgroups are dealt to the 8 XCDs round-robin, so XCD x runs
+  // blocks x, x + 8, ...; giving it the contiguous slices [x * per, (x+1) * per)
+  // keeps neighbouring rows (close in the step's vertex order) in one L2
+  const int per = (A.n_slices + kXcds - 1) / kXcds;
+  const int sl = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  if (sl >= A.n_slices) return;
   // An earlier step of the chunk failed: write nothing, so that the last
   // good fields (the input of the failed step, which this step would
   // overwrite) survive for the replay.  The flag is set by atomics in an
@@ -550,10 +556,11 @@ __global__ __launch_bounds__(kParts) void k_reduce_parts(const StepStats* parts,
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  const dim3 grid((unsigned)(kXcds * ((a.n_slices + kXcds - 1) / kXcds)));
   if (t0 && t1) {
-    hipExtLaunchKernelGGL(k_step, dim3(a.n_slices), dim3(kSlice), 0, s, t0, t1, 0, a);
+    hipExtLaunchKernelGGL(k_step, grid, dim3(kSlice), 0, s, t0, t1, 0, a);
   } else {
-    hipLaunchKernelGGL(k_step, dim3(a.n_slices), dim3(kSlice), 0, s, a);
+    hipLaunchKernelGGL(k_step, grid, dim3(kSlice), 0, s, a);
   }
   return hipGetLastError();
 }
