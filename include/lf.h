@@ -111,6 +111,23 @@ lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds);
  * vertex touches more layers than the row limit (64) or storage cannot
  * grow. */
 lf_status lf_step(lf_fields* f, int32_t n_steps);
+/* Convergence (the paper's fields "until converged", Sections 4 and 7,
+ * made concrete).  A step changes a row when the row's label (argmax over
+ * the cells) or its set of layers at or above params.tau changes.  The
+ * fields have converged at the end of the first whole chunk of check_every
+ * (<= 256) steps in which no step changed any row and no value moved by
+ * more than eps.  (With the theta prune the values can end in a period-2
+ * oscillation of size about theta, and the first steps from seeds are
+ * quiet for a few steps, so eps should exceed theta and check_every that
+ * start-up; 1e-2 and 32 are safe.)  Runs up to max_steps steps; *steps_done
+ * counts the steps run, *converged_at is the step (1-based, within this
+ * call) that ended the quiet chunk, or 0. */
+lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t check_every,
+                        int64_t* steps_done, int64_t* converged_at);
+/* Change made by the last completed step: rows it changed (label or layers
+ * at or above tau) and max |U_{t+1} - U_t| over all (vertex, layer) pairs
+ * (0 before any step). */
+lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta);
 lf_status lf_sync(lf_fields* f);
 
 /* Export U.  Size query with NULL buffers (*nnz always written).  rowptr
@@ -208,7 +225,8 @@ lf_status lf_batch_labels(lf_batch* b, int32_t mesh, int32_t* labels);
  * completion, and its memory is released as soon as it finishes, which lets
  * queued jobs in.  A job runs `steps` Euler steps, then `lloyd_rounds` times
  * (re-seed, re-initialise, `steps` steps), then labels and optionally the
- * dual mesh.  Each job computes exactly what it computes alone.  The caller
+ * dual mesh (with conv_eps > 0, each phase stops at convergence instead).
+ * Each job computes exactly what it computes alone.  The caller
  * drives the loop with lf_server_poll (non-blocking apart from short waits
  * at job phase boundaries). */
 typedef struct lf_server lf_server;
@@ -219,6 +237,10 @@ typedef struct {
   int32_t n_v, n_f, n_s, op;
   int32_t steps, lloyd_rounds, dual_mesh, pad_;
   lf_params params;
+  double conv_eps;     /* > 0: a phase ends at convergence (lf_step_until's rule */
+  int32_t conv_every;  /*      with eps = conv_eps, check_every = conv_every); steps
+                        *      is then the cap */
+  int32_t pad2_;
 } lf_job;
 /* hbm_budget: bytes the active jobs may hold (estimated per job from its
  * size); max_active: concurrent jobs; chunk: steps issued per job per poll. */

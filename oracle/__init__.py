@@ -14,6 +14,18 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
              identity, constant-field invariance, flooding, mirror symmetry,
              front speed, partition of unity, bounds.
   labels     pinned: definition on hand-built rows; Voronoi agreement.
+  change     pinned: hand-computed two-step example (golden file), zero for a
+             constant field and for a step onto itself.
+  run_until  pinned: convergence reached on a lattice of seeds, later steps
+             change nothing; Delta-t insensitivity (Section 7): labels after
+             convergence agree across time steps 1 to 5.  Reading: with the
+             theta prune the values can end in a period-2 oscillation of size
+             about theta (entries near theta appear and vanish), and the first
+             steps from seeds are quiet too (first-ring values are pruned), so
+             convergence is a whole quiet chunk: labels and tau pattern fixed,
+             values moving by at most eps (above that oscillation).
+  init_regions pinned: single-vertex regions reproduce init(seeds); a
+             region's vertices all start in its layer.
   lloyd      pinned: hand-built single-cell cases with known centroids and hit
              faces, a miss keeps the seed, collision rule cases.
   dual_mesh  pinned: hand-built adjacency cases, regular lattice on a torus
@@ -179,6 +191,71 @@ def run(L, U, n_s: int, params: dict, steps: int, record=None):
         if record is not None:
             record(t + 1, U)
     return U, {"skel_total": skel_total, "events": events}
+
+
+def change(U_old, U_new, n_s: int, tau: float = 0.25):
+    """Change made by a step, from its definition: the number of rows whose
+    label (argmax over the cell layers, lowest layer on ties, -1 for none)
+    or whose set of layers at or above tau (Phibar, Section 5.1) differs,
+    and max |U_new(i,l) - U_old(i,l)| over every (vertex, layer) pair
+    (absent entries are 0).  Plain row loop."""
+    Po, Co, Vo = U_old
+    Pn, Cn, Vn = U_new
+
+    def label(r):
+        best, bv = -1, 0.0
+        for c in sorted(r):
+            if c < n_s and (best < 0 or r[c] > bv):
+                best, bv = c, r[c]
+        return best
+
+    changed, dmax = 0, 0.0
+    for i in range(len(Po) - 1):
+        a = {int(c): float(v) for c, v in zip(Co[Po[i]:Po[i + 1]], Vo[Po[i]:Po[i + 1]])}
+        b = {int(c): float(v) for c, v in zip(Cn[Pn[i]:Pn[i + 1]], Vn[Pn[i]:Pn[i + 1]])}
+        if (label(a) != label(b)
+                or {c for c in a if a[c] >= tau} != {c for c in b if b[c] >= tau}):
+            changed += 1
+        for c in set(a) | set(b):
+            dmax = max(dmax, abs(b.get(c, 0.0) - a.get(c, 0.0)))
+    return changed, dmax
+
+
+def run_until(L, U, n_s: int, params: dict, max_steps: int, eps: float, check_every: int,
+              tau: float = 0.25):
+    """Steps until converged, the rule of the library's lf_step_until: steps
+    run in chunks of check_every; the fields have converged at the end of the
+    first whole chunk in which no step changed any row (label or tau
+    pattern) and no value moved by more than eps.  Returns (U, steps_done,
+    converged_at (1-based, 0 if none), per-step (changed, dmax))."""
+    done, conv, hist = 0, 0, []
+    while done < max_steps and not conv:
+        m = min(check_every, max_steps - done)
+        quiet = m == check_every
+        for _ in range(m):
+            U1 = step(L, U, n_s, params)
+            c = change(U, U1, n_s, tau)
+            hist.append(c)
+            quiet = quiet and c[0] == 0 and c[1] <= eps
+            U = U1
+        done += m
+        if quiet:
+            conv = done
+    return U, done, conv, hist
+
+
+def init_regions(n_v: int, region_ptr, region_vertices):
+    """Initial fields from initial regions (Algorithm 1, first line: "seeds
+    and/or initial regions"): U(v, k) = 1 for every vertex v of region k,
+    U(v, base) = 1 for every other vertex; regions must be disjoint."""
+    n_s = len(region_ptr) - 1
+    owner = np.full(n_v, n_s, dtype=np.int32)
+    for k in range(n_s):
+        for v in region_vertices[region_ptr[k]:region_ptr[k + 1]]:
+            if owner[v] != n_s:
+                raise ValueError("regions overlap")
+            owner[v] = k
+    return np.arange(n_v + 1, dtype=np.int64), owner, np.ones(n_v)
 
 
 def labels(U, n_s: int):

@@ -44,14 +44,15 @@ class lf_job(C.Structure):
     _fields_ = [("V", C.c_void_p), ("F", C.c_void_p), ("seeds", C.c_void_p),
                 ("n_v", C.c_int32), ("n_f", C.c_int32), ("n_s", C.c_int32), ("op", C.c_int32),
                 ("steps", C.c_int32), ("lloyd_rounds", C.c_int32), ("dual_mesh", C.c_int32),
-                ("pad_", C.c_int32), ("params", lf_params)]
+                ("pad_", C.c_int32), ("params", lf_params), ("conv_eps", C.c_double),
+                ("conv_every", C.c_int32), ("pad2_", C.c_int32)]
 
 
 EXPORTS = [
     "lf_last_error", "lf_params_default", "lf_ctx_create", "lf_ctx_destroy", "lf_mesh_create",
     "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
     "lf_fields_reset", "lf_fields_seeds", "lf_step", "lf_sync", "lf_fields_export",
-    "lf_fields_import", "lf_labels", "lf_lloyd_reseed", "lf_dual_mesh", "lf_dual_matrix",
+    "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_dual_mesh", "lf_dual_matrix",
     "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
     "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
     "lf_server_create", "lf_server_destroy", "lf_server_submit", "lf_server_poll",
@@ -99,6 +100,8 @@ def load(path: str | None = None):
         "lf_fields_reset": (C.c_int, [V, V]),
         "lf_fields_seeds": (C.c_int, [V, V]),
         "lf_step": (C.c_int, [V, I32]),
+        "lf_step_until": (C.c_int, [V, I32, D, I32, V, V]),
+        "lf_last_change": (C.c_int, [V, V, V]),
         "lf_sync": (C.c_int, [V]),
         "lf_fields_export": (C.c_int, [V, V, V, V, V, I32]),
         "lf_fields_import": (C.c_int, [V, I64, V, V, V, I32]),
@@ -216,6 +219,20 @@ def lf_fields_seeds(f, out: np.ndarray):
 
 def lf_step(f, n_steps: int):
     _check(load().lf_step(f, n_steps))
+
+
+def lf_step_until(f, max_steps: int, eps: float, check_every: int):
+    """Returns (steps_done, converged_at)."""
+    a, b = C.c_int64(), C.c_int64()
+    _check(load().lf_step_until(f, max_steps, eps, check_every, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def lf_last_change(f):
+    """Returns (changed_rows, max_delta) of the last completed step."""
+    a, b = C.c_int64(), C.c_double()
+    _check(load().lf_last_change(f, C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def lf_sync(f):
@@ -488,7 +505,8 @@ class Server:
         self.shape = {}
 
     def submit(self, V, F, seeds, steps: int, lloyd_rounds: int = 0, dual_mesh: bool = False,
-               op: int = LF_OP_GRAPH, params: lf_params | None = None) -> int:
+               op: int = LF_OP_GRAPH, params: lf_params | None = None, conv_eps: float = 0.0,
+               conv_every: int = 16) -> int:
         V = np.ascontiguousarray(V, np.float64)
         F = np.ascontiguousarray(F, np.int32)
         S = np.ascontiguousarray(seeds, np.int32)
@@ -497,6 +515,7 @@ class Server:
         j.n_v, j.n_f, j.n_s, j.op = V.shape[0], F.shape[0], S.size, op
         j.steps, j.lloyd_rounds, j.dual_mesh = steps, lloyd_rounds, int(bool(dual_mesh))
         j.params = params if params is not None else default_params()
+        j.conv_eps, j.conv_every = conv_eps, conv_every
         i = lf_server_submit(self.h, j)
         self.shape[i] = (V.shape[0], S.size)
         return i
@@ -553,6 +572,12 @@ class Fields:
 
     def step(self, n: int = 1):
         lf_step(self.h, n)
+
+    def step_until(self, max_steps: int, eps: float = 1e-4, check_every: int = 16):
+        return lf_step_until(self.h, max_steps, eps, check_every)
+
+    def last_change(self):
+        return lf_last_change(self.h)
 
     def reset(self, seeds):
         lf_fields_reset(self.h, seeds)

@@ -40,6 +40,14 @@ struct DevBuf {
   }
 };
 
+// a float kept as its bit pattern in an integer counter
+static float bits_float(unsigned long long u) {
+  const uint32_t w = (uint32_t)u;
+  float x;
+  memcpy(&x, &w, sizeof x);
+  return x;
+}
+
 static StepArgs make_args(lf_fields* f, int parity) {
   StepArgs a;
   lf_mesh* m = f->mesh;
@@ -66,6 +74,8 @@ static StepArgs make_args(lf_fields* f, int parity) {
   a.c.theta = (float)f->P.theta;
   a.c.base_mode = f->P.base_mode;
   a.c.n_s = f->n_s;
+  a.c.tau = (float)f->P.tau;
+  a.c.pad_ = 0;
   a.wide = f->wide;
   a.wide_cap = f->wide_cap;
   a.pad_ = 0;
@@ -596,6 +606,8 @@ lf_status step_complete(lf_fields* f, int64_t* remaining) {
   if (ok > 0) {
     f->nnz = (int64_t)f->stats_pinned[ok - 1].out;
     f->csr_valid = false;
+    f->last_changed = f->stats_pinned[ok - 1].changed;
+    f->last_dmax = bits_float(f->stats_pinned[ok - 1].dmax);
   }
   *remaining = n - ok;
   if (!fl.poisoned) return LF_OK;
@@ -614,9 +626,53 @@ lf_status step_complete(lf_fields* f, int64_t* remaining) {
   return clear_step_state(f);
 }
 
+bool chunk_quiet(const lf_fields* f, int64_t n, double eps) {
+  for (int64_t k = 0; k < n; ++k) {
+    const StepStats& t = f->stats_pinned[k];
+    if (t.changed != 0 || (double)bits_float(t.dmax) > eps) return false;
+  }
+  return n > 0;
+}
+
 }  // namespace lf
 
 extern "C" {
+
+lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta) {
+  if (!f) return fail(LF_EINVAL, "NULL argument");
+  if (changed_rows) *changed_rows = (int64_t)f->last_changed;
+  if (max_delta) *max_delta = (double)f->last_dmax;
+  return LF_OK;
+}
+
+lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t check_every,
+                        int64_t* steps_done, int64_t* converged_at) {
+  if (!f || max_steps < 0 || check_every < 1 || check_every > kMaxChunk || !(eps >= 0))
+    return fail(LF_EINVAL, "invalid argument");
+  int64_t done = 0, conv = 0;
+  int grows = 0;
+  while (done < max_steps && !conv) {
+    const int64_t m = std::min<int64_t>((int64_t)max_steps - done, check_every);
+    int64_t ok = 0;  // the chunk, replaying what storage growth interrupted
+    while (ok < m) {
+      lf_status st = step_issue(f, m - ok);
+      if (st) return st;
+      int64_t rem = 0;
+      st = step_complete(f, &rem);
+      if (st) return st;
+      // a chunk is judged whole: any step of it that was not quiet, even one
+      // before a replay, makes it not converged
+      if (!chunk_quiet(f, m - ok - rem, eps)) conv = -1;
+      ok += m - ok - rem;
+      if (rem > 0 && ++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
+    }
+    done += m;
+    conv = (conv == 0 && m == check_every) ? done : 0;
+  }
+  if (steps_done) *steps_done = done;
+  if (converged_at) *converged_at = conv;
+  return LF_OK;
+}
 
 lf_status lf_step(lf_fields* f, int32_t n) {
   if (!f || n < 0) return fail(LF_EINVAL, "invalid argument");

@@ -52,16 +52,21 @@ struct StepFlags {
 // (spread to keep atomics on one address few); a reduction kernel folds them
 // into one StepStats per step, and the host adds those of completed steps.
 struct StepStats {
-  unsigned long long skel;    // sum of |rows of interest|
-  unsigned long long out;     // nnz(U_{t+1})
-  unsigned long long in;      // nnz(U_t)
-  unsigned long long events;  // columns whose normalisation sum was zero
+  unsigned long long skel;     // sum of |rows of interest|
+  unsigned long long out;      // nnz(U_{t+1})
+  unsigned long long in;       // nnz(U_t)
+  unsigned long long events;   // columns whose normalisation sum was zero
+  unsigned long long changed;  // rows whose label or set of layers >= tau changed
+  unsigned long long dmax;     // max |U_{t+1} - U_t| (float bits; non-negative, so the
+                               // integer maximum is the float maximum)
 };
 
 struct StepConsts {
   float a, w, e, mu, dt, theta;
   int32_t base_mode;
   int32_t n_s;
+  float tau;  // threshold of the rows' tau pattern (convergence measure)
+  int32_t pad_;
 };
 
 // Workspace of one row touching more than kRowRegs layers, or reading a row
@@ -190,6 +195,10 @@ lf_status fields_csr(lf_fields* f, const int32_t** uptr, const Ent** uent);
 lf_status step_issue(lf_fields* f, int64_t n);
 bool step_ready(lf_fields* f);
 lf_status step_complete(lf_fields* f, int64_t* remaining);
+// whether all of the first n steps booked by the last step_complete were
+// quiet: no row changed its label or its layers at or above tau, and no
+// value moved by more than eps
+bool chunk_quiet(const lf_fields* f, int64_t n, double eps);
 
 // device allocation helpers
 template <class T>
@@ -264,6 +273,8 @@ struct lf_fields {
   // totals over completed steps
   long long steps, grow_events;
   unsigned long long skel_total, out_total, in_total, events_total;
+  unsigned long long last_changed;  // change made by the last completed step
+  float last_dmax;
   // timing
   bool timing;
   std::vector<hipEvent_t> ev0, ev1;

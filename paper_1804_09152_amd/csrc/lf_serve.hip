@@ -4,6 +4,7 @@
 // a finished job's memory is released at once.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <deque>
 #include <map>
@@ -27,6 +28,10 @@ struct Job {
   std::vector<int32_t> F, seeds;
   int32_t n_v = 0, n_f = 0, n_s = 0, op = 0, steps = 0, rounds = 0, dual = 0;
   lf_params P;
+  double conv_eps = 0;  // > 0: phases end at convergence
+  int32_t conv_every = 0;
+  bool chunk_quiet = true;  // the current chunk has been quiet so far
+  int64_t chunk_pos = 0;     // steps of the current chunk done
   int64_t bytes = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   JobState state = kQueued;
@@ -110,6 +115,8 @@ lf_status next_phase(lf_server* s, Job* j, bool* finished) {
     if (st) return st;
     ++j->round;
     j->left = j->steps;
+    j->chunk_pos = 0;
+    j->chunk_quiet = true;
     return LF_OK;
   }
   j->labels.resize((size_t)j->n_v);
@@ -169,7 +176,8 @@ lf_status lf_server_destroy(lf_server* s) {
 
 lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id) {
   if (!s || !job || !id || !job->V || !job->F || !job->seeds || job->n_v < 3 || job->n_f < 1 ||
-      job->n_s < 1 || job->steps < 0 || job->lloyd_rounds < 0)
+      job->n_s < 1 || job->steps < 0 || job->lloyd_rounds < 0 || job->conv_eps < 0 ||
+      (job->conv_eps > 0 && job->conv_every < 1))
     return sfail(LF_EINVAL, "invalid job");
   Job* j = new Job();
   j->bytes = job_bytes(job->n_v, job->n_f);
@@ -189,6 +197,8 @@ lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id) {
   j->rounds = job->lloyd_rounds;
   j->dual = job->dual_mesh;
   j->P = job->params;
+  j->conv_eps = job->conv_eps;
+  j->conv_every = job->conv_every;
   j->t_submit = now_ms();
   s->queue.push_back(j);
   s->jobs[j->id] = j;
@@ -221,13 +231,25 @@ lf_status lf_server_poll(lf_server* s, int32_t* n_queued, int32_t* n_active, int
       int64_t rem = 0;
       st = lf::step_complete(j->f, &rem);
       j->in_flight = false;
-      j->left -= j->issued - rem;
-      j->steps_run += j->issued - rem;
+      const int64_t ok = j->issued - rem;
+      j->left -= ok;
+      j->steps_run += ok;
+      // a phase converges at the end of a whole quiet chunk of conv_every steps
+      if (!st && j->conv_eps > 0) {
+        j->chunk_quiet = j->chunk_quiet && lf::chunk_quiet(j->f, ok, j->conv_eps);
+        j->chunk_pos += ok;
+        if (j->chunk_pos == j->conv_every) {
+          if (j->chunk_quiet) j->left = 0;
+          j->chunk_pos = 0;
+          j->chunk_quiet = true;
+        }
+      }
     }
     if (!st && !j->in_flight) {
       if (j->left == 0) st = next_phase(s, j, &gone);
       if (!st && !gone && j->left > 0) {
-        j->issued = std::min<int64_t>(s->chunk, j->left);
+        j->issued = std::min<int64_t>(
+            j->conv_eps > 0 ? j->conv_every - j->chunk_pos : s->chunk, j->left);
         st = lf::step_issue(j->f, j->issued);
         j->in_flight = !st;
       }

@@ -391,6 +391,54 @@ __device__ __forceinline__ int wave_sum(int x) {
   return x;
 }
 
+// Change of the row in this step (convergence measures): changed = 1 when
+// its label (argmax over the cell layers, lowest layer on ties) or its set of
+// layers at or above tau differs, and dmax = the largest
+// |U_{t+1}(i,l) - U_t(i,l)| over the layers of either step.  phi is the old
+// value (0 if absent), o the new one (<= 0 if absent).
+struct ChangeAcc {
+  int lo = -1, ln = -1;  // old and new label
+  float vo = 0.f, vn = 0.f;
+  bool tau_diff = false;
+  float dmax = 0.f;
+  __device__ __forceinline__ void add(int c, float phi, float o, const StepConsts& k) {
+    tau_diff = tau_diff || ((phi >= k.tau) != (o >= k.tau));
+    dmax = fmaxf(dmax, fabsf((o > 0.f ? o : 0.f) - phi));
+    if (c >= 0 && c < k.n_s) {
+      if (phi > 0.f && (lo < 0 || phi > vo || (phi == vo && c < lo))) { lo = c; vo = phi; }
+      if (o > 0.f && (ln < 0 || o > vn || (o == vn && c < ln))) { ln = c; vn = o; }
+    }
+  }
+  __device__ __forceinline__ int changed() const { return (tau_diff || lo != ln) ? 1 : 0; }
+};
+
+// after the update, lam holds the kept output value or a value <= 0
+__device__ __forceinline__ void row_change(const RowBuf<kRowRegs>& r, int cnt,
+                                           const StepConsts& k, int& changed, float& dmax) {
+  ChangeAcc a;
+#pragma unroll
+  for (int s = 0; s < kRowRegs; ++s) {
+    if (!__any(s < cnt)) break;
+    a.add(r.col[s], r.phi[s], r.lam[s], k);
+  }
+  changed = a.changed();
+  dmax = a.dmax;
+}
+
+__device__ __forceinline__ void wide_change(const WideRow* r, const StepConsts& k, int& changed,
+                                            float& dmax) {
+  ChangeAcc a;
+  for (int s = 0; s < r->cnt; ++s) a.add(r->col[s], r->phi[s], r->out[s], k);
+  changed = a.changed();
+  dmax = a.dmax;
+}
+
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
 // kept register-path entries in ascending layer order at dst[0..n_keep)
 __device__ __forceinline__ void write_regs(const RowBuf<kRowRegs>& r, int cnt, Ent* dst) {
 #pragma unroll
@@ -455,7 +503,8 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int i = sl * kSlice + lane;
 
   RowBuf<kRowRegs> r;
-  int cnt = 0, n_keep = 0, n_skel = 0, n_in = 0, ev = 0, rowovf = 0;
+  int cnt = 0, n_keep = 0, n_skel = 0, n_in = 0, ev = 0, rowovf = 0, changed = 0;
+  float dmax = 0.f;
   int wide = -1;  // workspace slot of a wide row
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
@@ -466,6 +515,7 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   if (i < A.n_v) {
     if (in_regs) {
       row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);
+      row_change(r, cnt, A.c, changed, dmax);
     } else {
       const unsigned slot = atomicAdd(A.wide_ctr, 1u);
       if (slot < (unsigned)A.wide_cap) {
@@ -474,6 +524,8 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
         if (rowovf) {
           step_failed(A, 2u);
           n_keep = 0;
+        } else {
+          wide_change(A.wide + slot, A.c, changed, dmax);
         }
       } else {
         step_failed(A, 8u);  // the step is replayed with more slots
@@ -509,13 +561,16 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   }
   // counters of the slice, added into one of kParts slots
   const int skel = wave_sum(n_skel), out = wave_sum(n_keep), in = wave_sum(n_in),
-            evs = wave_sum(ev);
+            evs = wave_sum(ev), chg = wave_sum(changed);
+  const float dm = wave_max(dmax);
   if (lane == 0) {
     StepStats* P = A.parts + (sl & (kParts - 1));
     atomicAdd(&P->skel, (unsigned long long)skel);
     atomicAdd(&P->out, (unsigned long long)out);
     atomicAdd(&P->in, (unsigned long long)in);
     if (evs) atomicAdd(&P->events, (unsigned long long)evs);
+    if (chg) atomicAdd(&P->changed, (unsigned long long)chg);
+    if (dm > 0.f) atomicMax(&P->dmax, (unsigned long long)__float_as_uint(dm));
   }
 }
 
@@ -526,30 +581,35 @@ __global__ void k_reset_flags(StepFlags* f, StepStats* parts, int64_t n) {
     f->fail_step = 0xffffffffu;
     f->need = 0;
   }
-  if (parts && k < n) parts[k] = StepStats{0, 0, 0, 0};
+  if (parts && k < n) parts[k] = StepStats{0, 0, 0, 0, 0, 0};
 }
 
-// one block per step: sums the kParts partial counters
+// one block per step: sums the kParts partial counters (maximum for dmax)
 __global__ __launch_bounds__(kParts) void k_reduce_parts(const StepStats* parts,
                                                          StepStats* out) {
-  __shared__ unsigned long long sh[4][kParts / 64];
+  constexpr int kF = 6;
+  __shared__ unsigned long long sh[kF][kParts / 64];
   const StepStats p = parts[(int64_t)blockIdx.x * kParts + threadIdx.x];
-  unsigned long long v[4] = {p.skel, p.out, p.in, p.events};
+  unsigned long long v[kF] = {p.skel, p.out, p.in, p.events, p.changed, p.dmax};
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kF; ++q) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long y = __shfl_xor(v[q], o, 64);
+      v[q] = q == kF - 1 ? (y > v[q] ? y : v[q]) : v[q] + y;
+    }
     if (lane == 0) sh[q][wid] = v[q];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long t[4] = {0, 0, 0, 0};
+    unsigned long long t[kF] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < kF; ++q)
 #pragma unroll
-      for (int w = 0; w < kParts / 64; ++w) t[q] += sh[q][w];
-    out[blockIdx.x] = StepStats{t[0], t[1], t[2], t[3]};
+      for (int w = 0; w < kParts / 64; ++w)
+        t[q] = q == kF - 1 ? (sh[q][w] > t[q] ? sh[q][w] : t[q]) : t[q] + sh[q][w];
+    out[blockIdx.x] = StepStats{t[0], t[1], t[2], t[3], t[4], t[5]};
   }
 }
 

@@ -1,0 +1,133 @@
+"""Convergence measures and the stopping rule on the GPU against the FP64
+oracle; the time-step study of Section 7 on a jittered icosphere."""
+import numpy as np
+import pytest
+
+from paper_1804_09152_amd import inputs as I
+from tests.gpu_common import as_oracle, f32, gpu_load, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_09152_amd as lfb
+    lfb.load()
+    ctx = lfb.Context(0)
+    yield lfb, ctx
+
+
+def _rows(U):
+    P, C, V = U
+    return [{int(c): float(v) for c, v in zip(C[P[i]:P[i + 1]], V[P[i]:P[i + 1]])}
+            for i in range(len(P) - 1)]
+
+
+def _ambiguous_rows(U_old, U_new, n_s, tau=0.25, g=1e-5):
+    """Rows where a float decision of the measures lies within g of its
+    threshold: a value within g of tau, or a top-2 cell gap within g."""
+    amb = 0
+    for a, b in zip(_rows(U_old), _rows(U_new)):
+        near = any(abs(v - tau) < g for v in list(a.values()) + list(b.values()))
+        for r in (a, b):
+            cells = sorted((v for c, v in r.items() if c < n_s), reverse=True)
+            if len(cells) > 1 and cells[0] - cells[1] < g:
+                near = True
+        amb += near
+    return amb
+
+
+def test_change_measures_teacher_forced(lf, orc):
+    """One step at a time from the oracle's own trajectory (rounded to
+    float32): the GPU's changed-row count lies within the rows whose
+    decisions are ambiguous at 1e-5, and max |dU| agrees within 1e-5."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c1()
+    L = orc.operator(mesh.V, mesh.F, 0)
+    P = orc.default_params()
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, seeds)
+    U = orc.init(mesh.n_v, seeds)
+    say("change measures, C1")
+    for t in range(1, 61):
+        Uf = f32(U)
+        gpu_load(f, Uf)
+        f.step(1)
+        gc, gd = f.last_change()
+        O = orc.step(L, Uf, seeds.size, P)
+        oc, od = orc.change(Uf, O, seeds.size)
+        if gc != oc:
+            assert abs(gc - oc) <= _ambiguous_rows(Uf, O, seeds.size), (t, gc, oc)
+        assert abs(gd - od) <= 1e-5, (t, gd, od)
+        U = O
+
+
+def test_step_until_matches_oracle(lf, orc):
+    lfb, ctx = lf
+    mesh = I.torus_grid(32, 32)
+    seeds = I.seeds_uniform(mesh.n_v, 12, np.random.default_rng(2))
+    L = orc.operator(mesh.V, mesh.F, 0)
+    P = orc.default_params()
+    _, o_done, o_conv, _ = orc.run_until(L, orc.init(mesh.n_v, seeds), seeds.size, P, 3000,
+                                         1e-2, 32)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, seeds)
+    say("step_until")
+    done, conv = f.step_until(3000, 1e-2, 32)
+    assert o_conv > 0
+    assert (done, conv) == (o_done, o_conv)
+    # resuming a converged run converges in the first chunk
+    done2, conv2 = f.step_until(3000, 1e-2, 32)
+    assert (done2, conv2) == (32, 32)
+
+
+def test_server_stops_at_convergence(lf, orc):
+    lfb, ctx = lf
+    rng = np.random.default_rng(3)
+    mesh = I.jitter(I.icosphere(4), rng)
+    seeds = I.seeds_uniform(mesh.n_v, 24, rng)
+    S = lfb.Server(0, 1 << 30, 4, 64)
+    say("server with convergence")
+    i = S.submit(mesh.V, mesh.F, seeds, 3000, 1, False, 1, conv_eps=1e-2, conv_every=32)
+    S.run()
+    r = S.result(i)
+    # the same phases solo
+    M = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    f = lfb.Fields(M, seeds)
+    d1, c1 = f.step_until(3000, 1e-2, 32)
+    s2, _ = f.lloyd_reseed()
+    f.reset(s2)
+    d2, c2 = f.step_until(3000, 1e-2, 32)
+    assert c1 > 0 and c2 > 0
+    assert r["steps"] == d1 + d2
+    assert np.array_equal(r["seeds"], f.seeds())
+    assert np.array_equal(r["labels"], f.labels())
+    S.release(i)
+    S.close()
+
+
+def test_time_step_study(lf):
+    """Section 7 on a jittered icosphere (40,962 vertices, 256 seeds,
+    cotangent operator): larger time steps converge in fewer steps, and the
+    tessellation after convergence hardly changes for dt up to 5."""
+    lfb, ctx = lf
+    rng = np.random.default_rng(7)
+    mesh = I.jitter(I.icosphere(6), rng)
+    seeds = I.seeds_uniform(mesh.n_v, 256, rng)
+    M = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    res = {}
+    for dt in (1.0, 2.5, 5.0, 10.0):
+        f = lfb.Fields(M, seeds, lfb.default_params(dt=dt))
+        done, conv = f.step_until(20000, 1e-2, 32)
+        res[dt] = (f.labels(), conv)
+        say(f"dt={dt}: converged after {conv} steps")
+        f.close()
+    ref = res[1.0][0]
+    agree = {dt: float((res[dt][0] == ref).mean()) for dt in res}
+    say(f"label agreement with dt=1: {agree}")
+    assert all(res[dt][1] > 0 for dt in (1.0, 2.5, 5.0))
+    assert res[5.0][1] < res[2.5][1] < res[1.0][1]
+    assert agree[2.5] >= 0.95 and agree[5.0] >= 0.95

@@ -1,0 +1,123 @@
+"""Pins for the oracle's convergence measures, its stopping rule, the time
+step study of Section 7 and initialisation from initial regions."""
+import os
+
+import numpy as np
+
+from paper_1804_09152_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _parse_rows(txt):
+    rows = []
+    for part in txt.split("|"):
+        r = {}
+        for tok in part.split():
+            c, v = tok.split(":")
+            r[int(c)] = float(v)
+        rows.append(r)
+    return rows
+
+
+def _csr(rows):
+    ptr = np.zeros(len(rows) + 1, np.int64)
+    col, val = [], []
+    for i, r in enumerate(rows):
+        for c, v in sorted(r.items()):
+            col.append(c)
+            val.append(v)
+        ptr[i + 1] = len(col)
+    return ptr, np.array(col, np.int32), np.array(val, float)
+
+
+def test_change_golden(orc):
+    d = {}
+    for line in open(os.path.join(GOLDEN, "change_example.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        key, rest = line.split(None, 1)
+        d[key] = rest.strip()
+    changed, dmax = orc.change(_csr(_parse_rows(d["old"])), _csr(_parse_rows(d["new"])), 3)
+    assert changed == int(d["changed"])
+    assert abs(dmax - float(d["dmax"])) < 1e-15
+
+
+def test_change_zero_for_a_constant_field(orc):
+    mesh = I.torus_grid(12, 10)
+    L = orc.operator(mesh.V, mesh.F, 0)
+    n_s = 3
+    # every vertex wholly in the base layer: a fixed point of the step
+    U = (np.arange(mesh.n_v + 1, dtype=np.int64), np.full(mesh.n_v, n_s, np.int32),
+         np.ones(mesh.n_v))
+    U1 = orc.step(L, U, n_s, orc.default_params())
+    assert orc.change(U, U1, n_s) == (0, 0.0)
+    assert orc.change(U1, U1, n_s) == (0, 0.0)
+
+
+def test_run_until_converges_on_a_lattice(orc):
+    nx = 16
+    mesh = I.torus_grid(nx, nx)
+    seeds = np.array([0, nx // 2, nx * nx // 2, nx * nx // 2 + nx // 2], np.int32)
+    L = orc.operator(mesh.V, mesh.F, 0)
+    P = orc.default_params()
+    U0 = orc.init(mesh.n_v, seeds)
+    U, done, conv, hist = orc.run_until(L, U0, seeds.size, P, 800, 1e-2, 16)
+    assert 0 < conv == done <= 800 and done % 16 == 0
+    assert all(c == 0 and d <= 1e-2 for c, d in hist[conv - 16:conv])
+    # every earlier chunk had a change
+    for k in range(0, conv - 16, 16):
+        assert any(c > 0 or d > 1e-2 for c, d in hist[k:k + 16])
+    # past convergence labels and tau pattern stay put
+    for t in range(200):
+        U1 = orc.step(L, U, seeds.size, P)
+        c, d = orc.change(U, U1, seeds.size)
+        assert c == 0 and d <= 1e-2
+        U = U1
+    # four cells that cover the torus
+    lab, _ = orc.labels(U, seeds.size)
+    assert (lab >= 0).all() and sorted(set(lab.tolist())) == [0, 1, 2, 3]
+
+
+def test_time_step_insensitivity(orc):
+    """Section 7: after convergence the tessellation hardly depends on the
+    time step (the paper: 0.1 to 5), while larger steps need fewer
+    iterations."""
+    mesh = I.torus_grid(24, 24)
+    seeds = I.seeds_uniform(mesh.n_v, 8, np.random.default_rng(5))
+    L = orc.operator(mesh.V, mesh.F, 0)
+    out = {}
+    for dt in (0.5, 1.0, 2.5, 5.0):
+        P = orc.default_params(dt=dt)
+        U, done, conv, _ = orc.run_until(L, orc.init(mesh.n_v, seeds), seeds.size, P, 3000,
+                                         1e-2, 32)
+        assert conv > 0
+        out[dt] = (orc.labels(U, seeds.size)[0], conv)
+    # measured on this coarse graph torus (72 vertices per cell): 99.7%, 98.6%
+    # and 96.4% of the labels agree with dt = 1; convergence after 672, 288,
+    # 224 and 128 steps
+    ref = out[1.0][0]
+    for dt, bound in ((0.5, 0.99), (2.5, 0.975), (5.0, 0.95)):
+        assert (out[dt][0] == ref).mean() >= bound
+    assert out[5.0][1] < out[2.5][1] < out[1.0][1] < out[0.5][1]
+
+
+def test_init_regions(orc):
+    n_v = 50
+    seeds = np.array([3, 17, 40], np.int32)
+    a = orc.init(n_v, seeds)
+    b = orc.init_regions(n_v, [0, 1, 2, 3], seeds)
+    for x, y in zip(a, b):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    ptr = [0, 3, 4]
+    verts = [5, 6, 9, 30]
+    U = orc.init_regions(n_v, ptr, verts)
+    col = np.asarray(U[1])
+    assert (col[[5, 6, 9]] == 0).all() and col[30] == 1
+    assert (np.delete(col, verts) == 2).all()
+    try:
+        orc.init_regions(n_v, [0, 2, 3], [5, 6, 6])
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("overlapping regions accepted")
