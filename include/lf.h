@@ -97,6 +97,21 @@ lf_status lf_mesh_operator(lf_mesh* mesh, int64_t* nnz, int32_t* rowptr, int32_t
 lf_status lf_fields_create(lf_mesh* mesh, const int32_t* seeds, int32_t n_s,
                            const lf_params* params, lf_fields** out);
 lf_status lf_fields_destroy(lf_fields* f);
+/* Fields from initial regions (Algorithm 1, first line: "seeds and/or
+ * initial regions"): cell k starts as the vertices
+ * region_vertices[region_ptr[k] .. region_ptr[k+1]), each with 1 in layer k;
+ * every other vertex starts with 1 in the base layer.  Host arrays:
+ * region_ptr int32[n_s+1] from 0, region_vertices int32[region_ptr[n_s]].
+ * Regions must be non-empty and disjoint (LF_EINVAL otherwise).  A 1-ring
+ * seed is the region {s} + its neighbours.  The seed of cell k (kept by a
+ * Lloyd round whose line misses, and the dual vertex's position) is the
+ * region's first vertex. */
+lf_status lf_fields_create_regions(lf_mesh* mesh, const int32_t* region_ptr,
+                                   const int32_t* region_vertices, int32_t n_s,
+                                   const lf_params* params, lf_fields** out);
+/* Re-initialise from new regions (same count). */
+lf_status lf_fields_reset_regions(lf_fields* f, const int32_t* region_ptr,
+                                  const int32_t* region_vertices);
 /* Re-initialise from new seeds (same count), as after a Lloyd re-seeding. */
 lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds);
 /* Current seeds, int32[n_s] host. */

@@ -51,7 +51,7 @@ class lf_job(C.Structure):
 EXPORTS = [
     "lf_last_error", "lf_params_default", "lf_ctx_create", "lf_ctx_destroy", "lf_mesh_create",
     "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
-    "lf_fields_reset", "lf_fields_seeds", "lf_step", "lf_sync", "lf_fields_export",
+    "lf_fields_reset", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_step", "lf_sync", "lf_fields_export",
     "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_dual_mesh", "lf_dual_matrix",
     "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
     "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
@@ -98,6 +98,8 @@ def load(path: str | None = None):
         "lf_fields_create": (C.c_int, [V, V, I32, C.POINTER(lf_params), PV]),
         "lf_fields_destroy": (C.c_int, [V]),
         "lf_fields_reset": (C.c_int, [V, V]),
+        "lf_fields_create_regions": (C.c_int, [V, V, V, I32, C.POINTER(lf_params), PV]),
+        "lf_fields_reset_regions": (C.c_int, [V, V, V]),
         "lf_fields_seeds": (C.c_int, [V, V]),
         "lf_step": (C.c_int, [V, I32]),
         "lf_step_until": (C.c_int, [V, I32, D, I32, V, V]),
@@ -202,6 +204,22 @@ def lf_fields_create(mesh, seeds, params: lf_params | None = None):
     _check(load().lf_fields_create(mesh, seeds.ctypes.data, seeds.size,
                                    C.byref(params) if params is not None else None, C.byref(h)))
     return h
+
+
+def lf_fields_create_regions(mesh, region_ptr, region_vertices, params: lf_params | None = None):
+    rp = np.ascontiguousarray(region_ptr, dtype=np.int32)
+    rv = np.ascontiguousarray(region_vertices, dtype=np.int32)
+    h = C.c_void_p()
+    _check(load().lf_fields_create_regions(mesh, rp.ctypes.data, rv.ctypes.data, rp.size - 1,
+                                           C.byref(params) if params is not None else None,
+                                           C.byref(h)))
+    return h
+
+
+def lf_fields_reset_regions(f, region_ptr, region_vertices):
+    rp = np.ascontiguousarray(region_ptr, dtype=np.int32)
+    rv = np.ascontiguousarray(region_vertices, dtype=np.int32)
+    _check(load().lf_fields_reset_regions(f, rp.ctypes.data, rv.ctypes.data))
 
 
 def lf_fields_destroy(f):
@@ -565,15 +583,25 @@ class Server:
 
 
 class Fields:
-    def __init__(self, mesh: Mesh, seeds, params: lf_params | None = None):
+    def __init__(self, mesh: Mesh, seeds=None, params: lf_params | None = None, regions=None):
+        """From seeds (int32 vertex ids), or from initial regions given as
+        (region_ptr, region_vertices)."""
         self.mesh = mesh
-        self.n_s = int(np.asarray(seeds).size)
-        self.h = lf_fields_create(mesh.h, seeds, params)
+        if regions is not None:
+            rp, rv = regions
+            self.n_s = int(np.asarray(rp).size) - 1
+            self.h = lf_fields_create_regions(mesh.h, rp, rv, params)
+        else:
+            self.n_s = int(np.asarray(seeds).size)
+            self.h = lf_fields_create(mesh.h, seeds, params)
+
+    def reset_regions(self, region_ptr, region_vertices):
+        lf_fields_reset_regions(self.h, region_ptr, region_vertices)
 
     def step(self, n: int = 1):
         lf_step(self.h, n)
 
-    def step_until(self, max_steps: int, eps: float = 1e-4, check_every: int = 16):
+    def step_until(self, max_steps: int, eps: float = 1e-2, check_every: int = 32):
         return lf_step_until(self.h, max_steps, eps, check_every)
 
     def last_change(self):

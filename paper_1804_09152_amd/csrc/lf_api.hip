@@ -394,8 +394,13 @@ static lf_status init_fields(lf_fields* f) {
   const int32_t n_v = f->mesh->n_v;
   LF_HIP(hipMemcpyAsync(f->d_seeds, f->seeds.data(), sizeof(int32_t) * f->n_s,
                         hipMemcpyHostToDevice, s));
-  LF_HIP(launch_fill_i32(f->owner, n_v, f->n_s, s));
-  LF_HIP(launch_scatter_owner(f->d_seeds, f->n_s, f->owner, s));
+  if (f->region_owner.empty()) {
+    LF_HIP(launch_fill_i32(f->owner, n_v, f->n_s, s));
+    LF_HIP(launch_scatter_owner(f->d_seeds, f->n_s, f->owner, s));
+  } else {
+    LF_HIP(hipMemcpyAsync(f->owner, f->region_owner.data(), sizeof(int32_t) * n_v,
+                          hipMemcpyHostToDevice, s));
+  }
   f->cur = 0;
   LF_HIP(launch_init_fields(f->owner, f->mesh->perm, n_v, f->ell[0], s));
   f->nnz = n_v;
@@ -433,12 +438,71 @@ lf_status lf_fields_destroy(lf_fields* f) {
   return LF_OK;
 }
 
+// owner of every vertex (region id, n_s outside all regions) and the first
+// vertex of every region, from a caller's region lists
+static lf_status check_regions(const int32_t* ptr, const int32_t* verts, int32_t n_s, int32_t n_v,
+                               std::vector<int32_t>& owner, std::vector<int32_t>& first) {
+  if (!ptr || !verts) return fail(LF_EINVAL, "NULL argument");
+  if (n_s < 1 || n_s >= n_v) return fail(LF_EINVAL, "need 1 <= n_s < n_v regions");
+  if (ptr[0] != 0) return fail(LF_EINVAL, "region_ptr[0] must be 0");
+  owner.assign((size_t)n_v, n_s);
+  first.resize((size_t)n_s);
+  for (int32_t k = 0; k < n_s; ++k) {
+    if (ptr[k + 1] <= ptr[k]) return fail(LF_EINVAL, "region " + std::to_string(k) + " is empty");
+    if (ptr[k + 1] > n_v) return fail(LF_EINVAL, "regions hold more vertices than the mesh");
+    first[(size_t)k] = verts[ptr[k]];
+    for (int32_t p = ptr[k]; p < ptr[k + 1]; ++p) {
+      const int32_t v = verts[p];
+      if (v < 0 || v >= n_v)
+        return fail(LF_EINVAL, "region " + std::to_string(k) + " has a vertex out of range");
+      if (owner[(size_t)v] != n_s)
+        return fail(LF_EINVAL, "vertex " + std::to_string(v) + " is in two regions");
+      owner[(size_t)v] = k;
+    }
+  }
+  return LF_OK;
+}
+
+static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const lf_params* P,
+                            std::vector<int32_t>&& region_owner, lf_fields** out);
+
 lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const lf_params* P,
                            lf_fields** out) {
   if (!m || !out) return fail(LF_EINVAL, "NULL argument");
   *out = nullptr;
   lf_status st = check_seeds(seeds, n_s, m->n_v);
   if (st) return st;
+  return fields_new(m, seeds, n_s, P, std::vector<int32_t>(), out);
+}
+
+lf_status lf_fields_create_regions(lf_mesh* m, const int32_t* region_ptr,
+                                   const int32_t* region_vertices, int32_t n_s, const lf_params* P,
+                                   lf_fields** out) {
+  if (!m || !out) return fail(LF_EINVAL, "NULL argument");
+  *out = nullptr;
+  std::vector<int32_t> owner, first;
+  lf_status st = check_regions(region_ptr, region_vertices, n_s, m->n_v, owner, first);
+  if (st) return st;
+  return fields_new(m, first.data(), n_s, P, std::move(owner), out);
+}
+
+lf_status lf_fields_reset_regions(lf_fields* f, const int32_t* region_ptr,
+                                  const int32_t* region_vertices) {
+  if (!f) return fail(LF_EINVAL, "NULL argument");
+  std::vector<int32_t> owner, first;
+  lf_status st = check_regions(region_ptr, region_vertices, f->n_s, f->mesh->n_v, owner, first);
+  if (st) return st;
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  f->seeds = std::move(first);
+  f->region_owner = std::move(owner);
+  return init_fields(f);
+}
+
+}  // extern "C"
+
+static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const lf_params* P,
+                            std::vector<int32_t>&& region_owner, lf_fields** out) {
+  lf_status st = LF_OK;
   lf_params prm;
   if (P) prm = *P;
   else lf_params_default(&prm);
@@ -451,6 +515,7 @@ lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const 
   f->n_s = n_s;
   f->P = prm;
   f->seeds.assign(seeds, seeds + n_s);
+  f->region_owner = std::move(region_owner);
   const int64_t hint = prm.capacity_hint > 0 ? prm.capacity_hint
                                              : std::max<int64_t>(4096, m->n_v / 16);
   f->ovf_cap = std::min<int64_t>(hint, (1ll << 31) - 1);
@@ -489,12 +554,15 @@ lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const 
   return LF_OK;
 }
 
+extern "C" {
+
 lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds) {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   lf_status st = check_seeds(seeds, f->n_s, f->mesh->n_v);
   if (st) return st;
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   f->seeds.assign(seeds, seeds + f->n_s);
+  f->region_owner.clear();
   return init_fields(f);
 }
 

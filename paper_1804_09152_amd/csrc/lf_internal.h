@@ -244,6 +244,7 @@ struct lf_fields {
   int32_t n_s;
   lf_params P;
   std::vector<int32_t> seeds;
+  std::vector<int32_t> region_owner;  // initial regions: owner of every vertex (empty: seeds)
   int32_t* d_seeds;
   int32_t* owner;              // scratch n_v
   lf::EllRow* ell[2];          // fields, double-buffered
