@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark of the layered-field hot path on one MI355X.
 
-Workload (one bench "step" = one whole job): icosphere level 9 (2,621,442
+Workload (one bench "step" = one whole job; the single-mesh roofline
+configuration): icosphere level 9 (2,621,442
 vertices, 5,242,880 triangles) radially displaced by 8 random real spherical
 harmonics (max amplitude 0.2), cotangent operator, 16,384 seeds; the fields
 are initialised from the seeds, advanced by 2,000 explicit Euler steps,
@@ -11,9 +12,11 @@ resident in HBM before the timed region.
 Prints one JSON line: field nnz-updates/s (sum over steps of the rows-of-
 interest sizes divided by wall time), the step kernel's roofline (algorithmic
 bytes per launch over its event-timed duration, against 8 TB/s), and the
-FP64 CPU oracle timed on a bounded sample of the same job.  Two more
-objects in the same line:
+FP64 CPU oracle timed on a bounded sample of the same job.  More objects
+in the same line:
 
+* "c2": jittered icosphere level 7 (163,842 vertices), 1,024 seeds,
+  cotangent operator, 1,000 steps + 5 Lloyd rounds + labels + dual mesh.
 * "batch": 256 torus grids of uneven size (vertex counts log-uniform in
   [1e3, 1e5], seed counts log-uniform in [8, 512]), graph operator, 500 steps
   + labels each, advanced as one batch and, on the same GPU, one mesh at a
@@ -120,6 +123,48 @@ def cpu_baseline(mesh, seeds, seconds: float, max_steps: int = 200):
     return {"value": skel / dt, "unit": "nnz-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} Euler steps of the same job from its seeds, FP64 C oracle, "
                       f"one thread, operator build excluded ({dt:.1f} s)"}
+
+
+def run_c2(lfb, I, steps: int, rounds: int, jobs: int):
+    """C2: jittered icosphere level 7 (163,842 vertices), 1,024 seeds,
+    cotangent operator, `steps` steps + `rounds` x (Lloyd re-seed,
+    re-initialise, `steps` steps) + labels + dual mesh, inputs resident."""
+    import torch
+    mesh, seeds = I.config_c2()
+    ctx = lfb.Context(0)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, lfb.LF_OP_COTAN)
+    f = lfb.Fields(m, seeds)
+    dev = torch.device("cuda", 0)
+    lab = torch.empty(mesh.n_v, dtype=torch.int32, device=dev)
+
+    def job():
+        f.reset(seeds)
+        f.step(steps)
+        for _ in range(rounds):
+            s, _ = f.lloyd_reseed()
+            f.reset(s)
+            f.step(steps)
+        lfb.lf_labels(f.h, lab)
+        f.dual_mesh(0.25)
+
+    job()  # warm-up
+    torch.cuda.synchronize()
+    sk0 = f.stats()["skeleton_total"]
+    f.timing(1)
+    t0 = time.perf_counter()
+    for _ in range(jobs):
+        job()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, n = f.timing(0)
+    skel = f.stats()["skeleton_total"] - sk0
+    f.close()
+    m.close()
+    log(f"c2: {wall / jobs * 1e3:.1f} ms per job")
+    return {"workload": (f"jittered icosphere level 7 (163,842 vertices), 1024 seeds, cotangent "
+                         f"operator, {steps} steps + {rounds} Lloyd rounds + labels + dual mesh"),
+            "value": skel / wall, "unit": "nnz-updates/s", "ms_per_job": wall / jobs * 1e3,
+            "jobs": jobs, "step_kernel_us": ms / max(n, 1) * 1e3}
 
 
 def run_batch(lfb, I, n_meshes: int, steps: int):
@@ -262,6 +307,7 @@ def main():
     ap.add_argument("--serve-rounds", type=int, default=3)
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
@@ -386,6 +432,8 @@ def main():
     }
     f.close()
     m.close()
+    if not args.no_c2:
+        out["c2"] = run_c2(lfb, I, 1000, 5, 3)
     if not args.no_batch:
         out["batch"] = run_batch(lfb, I, args.batch_meshes, args.batch_steps)
     if not args.no_serve:

@@ -174,20 +174,34 @@ __device__ __forceinline__ double unfx(unsigned long long v, double scale) {
 
 // largest face area and coordinate magnitude (non-negative doubles order
 // like their bit patterns)
+// largest face area and largest |coordinate| (non-negative doubles, so their
+// bit patterns order like the values): reduced per wavefront, one atomic each
 __global__ void k_bounds(const double* V, const int32_t* F, int32_t n_f, unsigned long long* amax,
                          unsigned long long* xmax) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= n_f) return;
-  const Vec3 p0 = vload(V, F[3 * (int64_t)f]), p1 = vload(V, F[3 * (int64_t)f + 1]),
-             p2 = vload(V, F[3 * (int64_t)f + 2]);
-  const Vec3 c = vcross(vsub(p1, p0), vsub(p2, p0));
-  const double area = 0.5 * sqrt(vdot(c, c));
-  double m = 0.0;
-  const Vec3 ps[3] = {p0, p1, p2};
-  for (int k = 0; k < 3; ++k)
-    m = fmax(m, fmax(fabs(ps[k].x), fmax(fabs(ps[k].y), fabs(ps[k].z))));
-  atomicMax(amax, (unsigned long long)__double_as_longlong(area));
-  atomicMax(xmax, (unsigned long long)__double_as_longlong(m));
+  unsigned long long a = 0, x = 0;
+  if (f < n_f) {
+    const Vec3 p0 = vload(V, F[3 * (int64_t)f]), p1 = vload(V, F[3 * (int64_t)f + 1]),
+               p2 = vload(V, F[3 * (int64_t)f + 2]);
+    const Vec3 c = vcross(vsub(p1, p0), vsub(p2, p0));
+    const double area = 0.5 * sqrt(vdot(c, c));
+    double m = 0.0;
+    const Vec3 ps[3] = {p0, p1, p2};
+    for (int k = 0; k < 3; ++k)
+      m = fmax(m, fmax(fabs(ps[k].x), fmax(fabs(ps[k].y), fabs(ps[k].z))));
+    a = (unsigned long long)__double_as_longlong(area);
+    x = (unsigned long long)__double_as_longlong(m);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long ya = __shfl_xor(a, o, 64), yx = __shfl_xor(x, o, 64);
+    a = ya > a ? ya : a;
+    x = yx > x ? yx : x;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(amax, a);
+    atomicMax(xmax, x);
+  }
 }
 
 // per face: area, area * barycentre and area * unit normal, added to every

@@ -46,11 +46,15 @@ struct Job {
   std::string err_msg;
 };
 
-// HBM a job holds while active (an upper estimate): positions and faces,
-// the operator with its assembly scratch, two field buffers of three
-// entries per vertex with pointers and tile state, workspace rows.
+// HBM a job holds while active (an upper estimate).  Per vertex: positions
+// 24, the operator twice (caller's and step order: row pointers, diagonal,
+// about 7 off-diagonal entries of 8 bytes each) and its slices (8 x 8),
+// vertex order 8, two fixed-width field buffers 64, CSR view and scratch
+// about 40: 320 bytes.  Per face: indices 12 and the operator assembly's
+// half-edges (transient, 3 x 20): 80 bytes.  Plus overflow areas, counters
+// and workspace rows: 4 MiB.
 int64_t job_bytes(int64_t n_v, int64_t n_f) {
-  return 92 * n_v + 132 * n_f + (2 << 20);
+  return 320 * n_v + 80 * n_f + (4 << 20);
 }
 
 void release(Job* j) {

@@ -230,17 +230,56 @@ constexpr int kWin = LF_WIN;  // neighbour rows in flight
 
 __device__ __forceinline__ bool is_ovf(const Ent& e) { return e.col == kOvfMark; }
 
+// entries of a row of U_t
+struct RowView {
+  const Ent* p;
+  int n;
+};
+
+// the entries of an overflow row (bounds-checked, so that a row written by
+// a failed step reads as empty)
+__device__ __forceinline__ RowView ovf_view(const StepArgs& A, const EllRow& u) {
+  const long long o = u.e[1].col, n = u.e[2].col;
+  if (o < 0 || n < 0 || o + n > A.ovf_cap) return RowView{A.ovf_in, 0};
+  return RowView{A.ovf_in + o, (int)n};
+}
+
+// entries of row u of U_t: inline, or in the overflow area
+__device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
+  const Ent* e = A->u_in[u].e;
+  if (is_ovf(e[0])) return ovf_view(*A, A->u_in[u]);
+  int n = 0;
+  while (n < kEll && e[n].col >= 0) ++n;
+  return RowView{e, n};
+}
+
+// sets phi of slot s (s from 0 to kRowRegs - 1)
+__device__ __forceinline__ void put_phi(RowBuf<kRowRegs>& r, int s, float ph) {
+#pragma unroll
+  for (int t = 0; t < kRowRegs; ++t) r.phi[t] = t == s ? ph : r.phi[t];
+}
+
 // Gathers row i: its own layers (lam starts at L_ii * phi) and then, in the
 // operator's column order, every neighbour row scaled by L(i,u).  The loads
 // come in two rounds (own row, diagonal and the slice's operator entries;
 // then the neighbours' rows).  Returns false when the row needs the wide
 // path: more than kRowRegs layers, or an overflow row among its inputs.
-__device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n_in, int i,
-                                            const Ent* ops, const StepArgs& A) {
+// Row i's gather into register slots: its own layers (lam starts at L_ii *
+// phi) and then, in the operator's column order, every neighbour row scaled
+// by L(i,u), each row in layer order.  The fast path streams the neighbour
+// rows through a window of kWin rows (the row of neighbour k + kWin is
+// requested before neighbour k is merged, so a few loads stay in flight
+// without holding every neighbour row in registers).  Returns kGatherOk,
+// kGatherOvf when an input row lives in the overflow area (the row is then
+// gathered again by gather_slow), or kGatherWide when the row touches more
+// than kRowRegs layers.
+constexpr int kGatherOk = 0, kGatherOvf = 1, kGatherWide = 2;
+
+__device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n_in, int i,
+                                           const Ent* ops, const StepArgs& A) {
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   cnt = 0;
-  // own row and diagonal first: they do not wait for the slice descriptor
   const EllRow own = A.u_in[i];
   const float dg = A.ldiag[i];
   // entries of U_t in this row (for the counters)
@@ -252,13 +291,10 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& 
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k)
     le[k] = k < A.op_w ? ops[k * kSlice] : Ent{-1, 0.f};
-  // neighbour rows stream through a window of kWin rows: the row of
-  // neighbour k + kWin is requested before neighbour k is merged, so a few
-  // loads stay in flight without holding every neighbour row in registers
   EllRow win[kWin];
 #pragma unroll
   for (int k = 0; k < kWin; ++k) win[k] = A.u_in[le[k].col >= 0 ? le[k].col : i];
-  if (is_ovf(own.e[0])) return false;
+  if (is_ovf(own.e[0])) return kGatherOvf;
   // own row: slots 0..3 in layer order
 #pragma unroll
   for (int j = 0; j < kEll; ++j) {
@@ -269,7 +305,7 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& 
       cnt = j + 1;
     }
   }
-  bool ovf = false;
+  bool ovf = false, orow = false;
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k) {
     const EllRow u = win[k % kWin];
@@ -277,7 +313,7 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& 
       win[k % kWin] = A.u_in[le[k + kWin].col >= 0 ? le[k + kWin].col : i];
     if (le[k].col < 0) continue;
     if (is_ovf(u.e[0])) {
-      ovf = true;
+      orow = true;
       continue;
     }
 #pragma unroll
@@ -288,7 +324,7 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& 
     if (l.col < 0) return;
     const EllRow u = A.u_in[l.col];
     if (is_ovf(u.e[0])) {
-      ovf = true;
+      orow = true;
       return;
     }
 #pragma unroll
@@ -298,28 +334,58 @@ __device__ __forceinline__ bool gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& 
   for (int k = kNbPre; k < A.op_w; ++k) more(ops[k * kSlice]);
   if (A.op_w == kOpWidth && ops[(kOpWidth - 1) * kSlice].col >= 0)  // rows beyond the slices
     for (int q = A.lptr[i] + kOpWidth; q < A.lptr[i + 1]; ++q) more(A.lent[q]);
-  return !ovf;
+  return orow ? kGatherOvf : (ovf ? kGatherWide : kGatherOk);
+}
+
+// The same gather for a row that reads an overflow row (rare): plain loops,
+// overflow rows read from the overflow area, same terms in the same order.
+__device__ __forceinline__ int gather_slow(RowBuf<kRowRegs>& r, int& cnt, int i, const Ent* ops,
+                                        const StepArgs& A) {
+#pragma unroll
+  for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
+  cnt = 0;
+  bool ovf = false;
+  const float dg = A.ldiag[i];
+  const RowView o = row_view(&A, i);
+  if (o.n > kRowRegs) return kGatherWide;
+  for (int p = 0; p < o.n; ++p) {
+    const Ent e = o.p[p];
+    add_regs(r, cnt, ovf, e.col, dg, e.val);
+    put_phi(r, cnt - 1, e.val);
+  }
+  // neighbours in batches of kWin: the batch's operator entries, then its
+  // rows, are requested together (few dependent rounds for the wavefront
+  // that waits on this lane)
+  const int q0 = A.lptr[i], deg = A.lptr[i + 1] - q0;
+  for (int k0 = 0; k0 < deg; k0 += kWin) {
+    Ent le[kWin];
+    EllRow u[kWin];
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+      const int kk = k0 + k;
+      le[k] = kk >= deg ? Ent{-1, 0.f} : (kk < A.op_w ? ops[kk * kSlice] : A.lent[q0 + kk]);
+    }
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) u[k] = A.u_in[le[k].col >= 0 ? le[k].col : i];
+#pragma unroll
+    for (int k = 0; k < kWin; ++k) {
+      if (le[k].col < 0) continue;
+      const RowView v = is_ovf(u[k].e[0]) ? ovf_view(A, u[k]) : RowView{nullptr, 0};
+      if (v.p) {
+        for (int p = 0; p < v.n; ++p) add_regs(r, cnt, ovf, v.p[p].col, le[k].val, v.p[p].val);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kEll; ++j)
+          if (u[k].e[j].col >= 0) add_regs(r, cnt, ovf, u[k].e[j].col, le[k].val, u[k].e[j].val);
+      }
+    }
+  }
+  return ovf ? kGatherWide : kGatherOk;
 }
 
 // ---- wide path (many layers, or overflow rows) --------------------------------
 
-// entries of row u of U_t: inline, or in the overflow area (bounds-checked,
-// so that a row written by a failed step is read as empty)
-struct RowView {
-  const Ent* p;
-  int n;
-};
-__device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
-  const Ent* e = A->u_in[u].e;
-  if (is_ovf(e[0])) {
-    const long long o = e[1].col, n = e[2].col;
-    if (o < 0 || n < 0 || o + n > A->ovf_cap) return RowView{e, 0};
-    return RowView{A->ovf_in + o, (int)n};
-  }
-  int n = 0;
-  while (n < kEll && e[n].col >= 0) ++n;
-  return RowView{e, n};
-}
+
 
 // Same arithmetic in the same order as the register path, with kRowWide
 // slots in a global-memory workspace row.  Returns the number of kept
@@ -511,7 +577,11 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   bool in_regs = false;
   // this row's operator entries: column-major in the wavefront's slice
   const Ent* ops = A.lell + (int64_t)sl * A.op_w * kSlice + lane;
-  if (i < A.n_v) in_regs = gather_regs(r, cnt, n_in, i, ops, A);
+  if (i < A.n_v) {
+    int g = gather_regs(r, cnt, n_in, i, ops, A);
+    if (g == kGatherOvf) g = gather_slow(r, cnt, i, ops, A);
+    in_regs = g == kGatherOk;
+  }
   if (i < A.n_v) {
     if (in_regs) {
       row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);

@@ -63,7 +63,7 @@ def test_server_host_logic_without_gpu():
     with pytest.raises(lfb.LFError) as e:
         lfb.Server(0, 0, 1, 1)
     assert e.value.status == 1
-    S = lfb.Server(0, 3 << 20, 2, 8)
+    S = lfb.Server(0, 8 << 20, 2, 8)
     i = S.submit(mesh.V, mesh.F, seeds, steps=10)
     big = I.torus_grid(200, 200)
     with pytest.raises(lfb.LFError) as e:

@@ -111,7 +111,7 @@ def _jobs():
     return out
 
 
-@pytest.mark.parametrize("max_active,budget_mb,chunk", [(3, 5, 16), (8, 4096, 7), (1, 4096, 64)])
+@pytest.mark.parametrize("max_active,budget_mb,chunk", [(3, 12, 16), (8, 4096, 7), (1, 4096, 64)])
 def test_server_equals_solo(lf, max_active, budget_mb, chunk):
     lfb, ctx = lf
     jobs = _jobs()

@@ -131,3 +131,28 @@ def test_time_step_study(lf):
     assert all(res[dt][1] > 0 for dt in (1.0, 2.5, 5.0))
     assert res[5.0][1] < res[2.5][1] < res[1.0][1]
     assert agree[2.5] >= 0.95 and agree[5.0] >= 0.95
+
+
+def test_step_until_through_storage_growth(lf, orc):
+    """Chunks interrupted by overflow growth (replayed steps) are judged as
+    whole chunks: a one-entry overflow area gives the same steps, the same
+    convergence step and the same fields as an area large enough."""
+    lfb, ctx = lf
+    from tests.test_gpu_step import _three_layer_state
+    # three random layers of nine per vertex: rows of up to 7 entries (the
+    # overflow area) at first, converged after about 400 steps
+    mesh = I.torus_grid(24, 24)
+    n_s = 8
+    U = _three_layer_state(mesh, n_s, 4)
+    seeds = I.seeds_uniform(mesh.n_v, n_s, np.random.default_rng(8))
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    a = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=1))
+    b = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=1 << 22))
+    gpu_load(a, U)
+    gpu_load(b, U)
+    say("step_until with growth")
+    ra = a.step_until(3000, 1e-2, 32)
+    rb = b.step_until(3000, 1e-2, 32)
+    assert ra == rb and ra[1] > 0
+    assert a.stats()["grow_events"] > b.stats()["grow_events"]
+    assert all(np.array_equal(x, y) for x, y in zip(a.export(), b.export()))
