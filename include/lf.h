@@ -141,7 +141,9 @@ lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t che
                         int64_t* steps_done, int64_t* converged_at);
 /* Change made by the last completed step: rows it changed (label or layers
  * at or above tau) and max |U_{t+1} - U_t| over all (vertex, layer) pairs
- * (0 before any step). */
+ * (0 before any step).  The step kernel measures these on every step of
+ * lf_step_until and on the last step of every chunk of lf_step (at most 256
+ * steps; so always for the last step of a call). */
 lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta);
 lf_status lf_sync(lf_fields* f);
 

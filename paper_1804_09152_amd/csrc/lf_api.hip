@@ -84,7 +84,7 @@ static StepArgs make_args(lf_fields* f, int parity) {
   a.flags = f->flags;
   a.parts = nullptr;
   a.step_idx = 0;
-  a.pad2_ = 0;
+  a.measure = 0;
   return a;
 }
 
@@ -621,6 +621,7 @@ lf_status step_issue(lf_fields* f, int64_t n) {
     StepArgs a = make_args(f, (int)((f->cur + k) & 1));
     a.parts = f->parts + k * kParts;
     a.step_idx = (uint32_t)k;
+    a.measure = (f->measure_all || k == n - 1) ? 1u : 0u;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (f->timing) {
       t0 = pool_event(f->ev0, used);
@@ -719,6 +720,11 @@ lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t che
     return fail(LF_EINVAL, "invalid argument");
   int64_t done = 0, conv = 0;
   int grows = 0;
+  f->measure_all = true;
+  struct Restore {  // measures back to the last step of a chunk on every exit
+    lf_fields* f;
+    ~Restore() { f->measure_all = false; }
+  } restore{f};
   while (done < max_steps && !conv) {
     const int64_t m = std::min<int64_t>((int64_t)max_steps - done, check_every);
     int64_t ok = 0;  // the chunk, replaying what storage growth interrupted

@@ -105,7 +105,7 @@ struct StepArgs {
   StepFlags* flags;
   StepStats* parts;                // kParts partial sums of this step
   uint32_t step_idx;               // index of this step within the chunk
-  uint32_t pad2_;
+  uint32_t measure;                // compute the convergence measures of this step
 };
 
 // error handling -----------------------------------------------------------
@@ -276,6 +276,7 @@ struct lf_fields {
   unsigned long long skel_total, out_total, in_total, events_total;
   unsigned long long last_changed;  // change made by the last completed step
   float last_dmax;
+  bool measure_all;  // convergence measures on every step (else on the last of a chunk)
   // timing
   bool timing;
   std::vector<hipEvent_t> ev0, ev1;

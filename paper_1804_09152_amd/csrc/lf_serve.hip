@@ -101,6 +101,7 @@ lf_status admit(lf_server* s, Job* j) {
   if (!st) st = lf_mesh_create(j->ctx, j->V.data(), j->n_v, j->F.data(), j->n_f, j->op, &j->mesh);
   if (!st) st = lf_fields_create(j->mesh, j->seeds.data(), j->n_s, &j->P, &j->f);
   if (st) return st;
+  j->f->measure_all = j->conv_eps > 0;
   j->state = kActive;
   j->t_admit = now_ms();
   j->round = 0;

@@ -224,7 +224,7 @@ __device__ __forceinline__ void add_regs(RowBuf<kRowRegs>& r, int& cnt, bool& ov
 constexpr int kXcds = 8;   // accelerator dies of the MI355X, each with its own L2
 constexpr int kNbPre = 7;  // neighbours whose operator entries are prefetched
 #ifndef LF_WIN
-#define LF_WIN 4
+#define LF_WIN 3
 #endif
 constexpr int kWin = LF_WIN;  // neighbour rows in flight
 
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   if (i < A.n_v) {
     if (in_regs) {
       row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);
-      row_change(r, cnt, A.c, changed, dmax);
+      if (A.measure) row_change(r, cnt, A.c, changed, dmax);
     } else {
       const unsigned slot = atomicAdd(A.wide_ctr, 1u);
       if (slot < (unsigned)A.wide_cap) {
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
           step_failed(A, 2u);
           n_keep = 0;
         } else {
-          wide_change(A.wide + slot, A.c, changed, dmax);
+          if (A.measure) wide_change(A.wide + slot, A.c, changed, dmax);
         }
       } else {
         step_failed(A, 8u);  // the step is replayed with more slots
@@ -629,17 +629,19 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
       else if (!rowovf) wide_write(A.wide + wide, dst);
     }
   }
-  // counters of the slice, added into one of kParts slots
-  const int skel = wave_sum(n_skel), out = wave_sum(n_keep), in = wave_sum(n_in),
-            evs = wave_sum(ev), chg = wave_sum(changed);
-  const float dm = wave_max(dmax);
+  // counters of the slice, added into one of kParts slots; per row at most
+  // 64 rows of interest and kept entries, so a wavefront's sums fit 16 bits
+  // and travel packed
+  const int so = wave_sum(n_skel | (n_keep << 16)), in = wave_sum(n_in),
+            ec = wave_sum(ev | (changed << 16));
+  const float dm = A.measure ? wave_max(dmax) : 0.f;
   if (lane == 0) {
     StepStats* P = A.parts + (sl & (kParts - 1));
-    atomicAdd(&P->skel, (unsigned long long)skel);
-    atomicAdd(&P->out, (unsigned long long)out);
+    atomicAdd(&P->skel, (unsigned long long)(so & 0xffff));
+    atomicAdd(&P->out, (unsigned long long)(so >> 16));
     atomicAdd(&P->in, (unsigned long long)in);
-    if (evs) atomicAdd(&P->events, (unsigned long long)evs);
-    if (chg) atomicAdd(&P->changed, (unsigned long long)chg);
+    if (ec & 0xffff) atomicAdd(&P->events, (unsigned long long)(ec & 0xffff));
+    if (ec >> 16) atomicAdd(&P->changed, (unsigned long long)(ec >> 16));
     if (dm > 0.f) atomicMax(&P->dmax, (unsigned long long)__float_as_uint(dm));
   }
 }
