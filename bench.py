@@ -332,7 +332,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 10}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
