@@ -12,7 +12,10 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   init       pinned: definition.
   step       pinned: brute-force dense Algorithm 1 on tiny meshes, closed-form
              identity, constant-field invariance, flooding, mirror symmetry,
-             front speed, partition of unity, bounds.
+             front speed, partition of unity, bounds.  With per-pair
+             coefficients: brute-force dense Algorithm 1 with the typed
+             coefficient matrices, one type equal to the scalar step bit for
+             bit, invariance under relabelling the types.
   labels     pinned: definition on hand-built rows; Voronoi agreement.
   change     pinned: hand-computed two-step example (golden file), zero for a
              constant field and for a step onto itself.
@@ -35,6 +38,7 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -57,7 +61,8 @@ def build(force: bool = False) -> str:
 class Params(C.Structure):
     _fields_ = [("w", C.c_double), ("a", C.c_double), ("e", C.c_double), ("mu", C.c_double),
                 ("dt", C.c_double), ("theta", C.c_double), ("base_mode", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("n_types", C.c_int32), ("types", C.POINTER(C.c_int32)),
+                ("tab", C.POINTER(C.c_double))]
 
 
 class _Dual(C.Structure):
@@ -119,14 +124,28 @@ def _take(ptr, n, dtype):
 
 def default_params(**kw) -> dict:
     """Constants of the complete reading: w = 0.2 with a = w/5 (the paper's
-    ratio of 5), e = 1, mu = 0.1, dt = 5 (Section 7), theta = 1e-3."""
+    ratio of 5), e = 1, mu = 0.1, dt = 5 (Section 7), theta = 1e-3.
+    Optional per-pair coefficients: types (int, one per layer, the base
+    last) and table (n_types x n_types x 3: a, w, e of a pair of types)."""
     p = dict(w=0.2, a=0.04, e=1.0, mu=0.1, dt=5.0, theta=1e-3, base_mode=0)
     p.update(kw)
     return p
 
 
 def _params(p: dict) -> Params:
-    return Params(p["w"], p["a"], p["e"], p["mu"], p["dt"], p["theta"], int(p.get("base_mode", 0)), 0)
+    prm = Params(p["w"], p["a"], p["e"], p["mu"], p["dt"], p["theta"], int(p.get("base_mode", 0)), 0,
+                 None, None)
+    if p.get("types") is not None:
+        types = np.ascontiguousarray(p["types"], dtype=np.int32)
+        tab = np.ascontiguousarray(p["table"], dtype=np.float64)
+        n_t = int(round(math.sqrt(tab.size // 3)))
+        if tab.size != 3 * n_t * n_t:
+            raise ValueError("table must hold n_types x n_types x 3 values")
+        prm.n_types = n_t
+        prm.types = types.ctypes.data_as(C.POINTER(C.c_int32))
+        prm.tab = tab.ctypes.data_as(C.POINTER(C.c_double))
+        prm._keep = (types, tab)  # the arrays live as long as the struct
+    return prm
 
 
 def _mesh(V, F):

@@ -204,19 +204,24 @@ int orc_init(int32_t n_v, const int32_t* seeds, int32_t n_s, int64_t* ptr, int32
  * the base and -e for the base against a cell.  base_mode 1 instead treats
  * the base as an ordinary layer. */
 
+static double coef_tab(int32_t j, int32_t l, int q, const orc_params* P) {
+  return P->tab[3 * ((int64_t)P->types[j] * P->n_types + P->types[l]) + q];
+}
 static double coef_a(int32_t j, int32_t l, int32_t b, const orc_params* P) {
   (void)b;
-  return j == l ? 0.0 : P->a;
+  if (j == l) return 0.0;
+  return P->n_types > 0 ? coef_tab(j, l, 0, P) : P->a;
 }
 static double coef_w(int32_t j, int32_t l, int32_t b, const orc_params* P) {
   if (j == l) return 0.0;
   if (P->base_mode == 0 && (j == b || l == b)) return 0.0;
-  return P->w;
+  return P->n_types > 0 ? coef_tab(j, l, 1, P) : P->w;
 }
 static double coef_e(int32_t j, int32_t k, int32_t b, const orc_params* P) {
   if (j == k) return 0.0;
-  if (P->base_mode == 1 || (j != b && k != b)) return P->e;
-  return (j == b) ? -P->e : P->e;
+  const double e = P->n_types > 0 ? coef_tab(j, k, 2, P) : P->e;
+  if (P->base_mode == 1 || (j != b && k != b)) return e;
+  return (j == b) ? -e : e;
 }
 
 static void isort_i32(int32_t* a, int32_t n) {
@@ -249,6 +254,9 @@ int orc_step(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc, con
              int64_t* events) {
   if (n_v <= 0 || n_s < 0 || !P) return ORC_EINVAL;
   const int32_t n_r = n_s + 1, b = n_s;
+  if (P->n_types < 0 || (P->n_types > 0 && (!P->types || !P->tab))) return ORC_EINVAL;
+  for (int32_t l = 0; P->n_types > 0 && l < n_r; ++l)
+    if (P->types[l] < 0 || P->types[l] >= P->n_types) return ORC_EINVAL;
   double* lam = (double*)calloc((size_t)n_r, sizeof(double));
   double* phi = (double*)calloc((size_t)n_r, sizeof(double));
   char* touched = (char*)calloc((size_t)n_r, 1);

@@ -29,7 +29,16 @@
 typedef struct {
   double w, a, e, mu, dt, theta;
   int32_t base_mode;
-  int32_t pad_;
+  /* Per-pair coefficients (equation (2) carries a, w, e per pair of layers;
+   * the paper fixes one value each and foresees varying them, Section 3.1).
+   * n_types = 0: the scalars above.  n_types > 0: layer l has type
+   * types[l] (n_s + 1 entries, the base last) and a pair (j, l), j != l,
+   * takes a, w, e from tab[3 * (types[j] * n_types + types[l]) + 0, 1, 2].
+   * In base_mode 0 the pairs with the base keep the base reading: w = 0,
+   * and e is negated for the base against a cell. */
+  int32_t n_types;
+  const int32_t* types;
+  const double* tab;
 } orc_params;
 
 void orc_free(void* p);

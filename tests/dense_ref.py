@@ -37,17 +37,29 @@ def dense_operator(V, F, op):
 
 
 def coefficient_matrices(n_s, p):
-    """Dense a, w, e over n_s cells + base (last)."""
+    """Dense a, w, e over n_s cells + base (last).  With p["types"] and
+    p["table"] (n_types x n_types x 3), entry (j, l) comes from the table at
+    the pair of types; otherwise one scalar per matrix.  Zero diagonals; in
+    base_mode 0 no w against the base, and the base's e against a cell is the
+    negated table entry."""
     n_r = n_s + 1
     off = 1.0 - np.eye(n_r)
-    A = p["a"] * off
-    W = p["w"] * off
-    E = p["e"] * off
+    if p.get("types") is not None:
+        t = np.asarray(p["types"], dtype=np.int64)
+        tab = np.asarray(p["table"], dtype=float)
+        n_t = int(round((tab.size // 3) ** 0.5))
+        tab = tab.reshape(n_t, n_t, 3)
+        A = tab[t[:, None], t[None, :], 0] * off
+        W = tab[t[:, None], t[None, :], 1] * off
+        E = tab[t[:, None], t[None, :], 2] * off
+    else:
+        A = p["a"] * off
+        W = p["w"] * off
+        E = p["e"] * off
     if p.get("base_mode", 0) == 0:
         W[n_s, :] = 0.0
         W[:, n_s] = 0.0
-        E[n_s, :n_s] = -p["e"]
-        E[:n_s, n_s] = p["e"]
+        E[n_s, :n_s] = -E[n_s, :n_s]
     return A, W, E
 
 
