@@ -117,6 +117,23 @@ lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds);
 /* Current seeds, int32[n_s] host. */
 lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds);
 
+/* Per-pair coefficients (equation (2) carries a, w, e per pair of layers;
+ * Section 3.1 fixes one value each and foresees varying them, e.g. to model
+ * natural processes).  Layer l (cells 0..n_s-1, then the base) has type
+ * layer_types[l] in [0, n_types), host int32[n_s+1]; a pair of layers
+ * (j, l), j != l, takes a, w, e from host
+ * table[3 * (t_j * n_types + t_l) + 0, 1, 2] (double, finite, rounded to
+ * float32).  In base_mode 0 a pair with the base keeps the base reading:
+ * no w, and the base's e against a cell is the negated entry.  One type
+ * whose entry is (a, w, e) of the params is the scalar model.  n_types = 0
+ * (NULL arrays) returns to the scalars of the params.  The update then
+ * costs O(n^2) table reads per row of n active layers.  Applies from the
+ * next step; the fields are not touched.  LF_EINVAL for types out of range,
+ * non-finite entries or n_types above 65536; LF_ENOMEM when the table does
+ * not fit.  For a batch, the layers are those of lf_batch_fields. */
+lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_t* layer_types,
+                                     const double* table);
+
 /* n_steps explicit Euler steps of Algorithm 1 (Jacobi form): field
  * Laplacian L_t = Phi L^T (row form: L U), rows of interest, update with
  * clamping to [0,1], column normalisation, then the theta prune.  Runs on the

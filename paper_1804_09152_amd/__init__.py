@@ -51,7 +51,7 @@ class lf_job(C.Structure):
 EXPORTS = [
     "lf_last_error", "lf_params_default", "lf_ctx_create", "lf_ctx_destroy", "lf_mesh_create",
     "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
-    "lf_fields_reset", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_step", "lf_sync", "lf_fields_export",
+    "lf_fields_reset", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_fields_set_coefficients", "lf_step", "lf_sync", "lf_fields_export",
     "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_dual_mesh", "lf_dual_matrix",
     "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
     "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
@@ -101,6 +101,7 @@ def load(path: str | None = None):
         "lf_fields_create_regions": (C.c_int, [V, V, V, I32, C.POINTER(lf_params), PV]),
         "lf_fields_reset_regions": (C.c_int, [V, V, V]),
         "lf_fields_seeds": (C.c_int, [V, V]),
+        "lf_fields_set_coefficients": (C.c_int, [V, I32, V, V]),
         "lf_step": (C.c_int, [V, I32]),
         "lf_step_until": (C.c_int, [V, I32, D, I32, V, V]),
         "lf_last_change": (C.c_int, [V, V, V]),
@@ -233,6 +234,19 @@ def lf_fields_reset(f, seeds):
 
 def lf_fields_seeds(f, out: np.ndarray):
     _check(load().lf_fields_seeds(f, out.ctypes.data))
+
+
+def lf_fields_set_coefficients(f, layer_types=None, table=None):
+    """Per-pair coefficients: layer_types int32[n_s+1] (the base last),
+    table float64[n_types, n_types, 3] (a, w, e); None clears them."""
+    if layer_types is None:
+        _check(load().lf_fields_set_coefficients(f, 0, None, None))
+        return
+    types = np.ascontiguousarray(layer_types, dtype=np.int32)
+    tab = np.ascontiguousarray(table, dtype=np.float64)
+    if tab.ndim != 3 or tab.shape[0] != tab.shape[1] or tab.shape[2] != 3:
+        raise LFError(1, "table must have shape (n_types, n_types, 3)")
+    _check(load().lf_fields_set_coefficients(f, tab.shape[0], types.ctypes.data, tab.ctypes.data))
 
 
 def lf_step(f, n_steps: int):
@@ -489,6 +503,11 @@ class Batch:
         lf_batch_export(self.h, m, rp, col, val)
         return rp, col, val
 
+    def set_coefficients(self, layer_types=None, table=None):
+        """Per-pair coefficients over the batch's layers (cells of mesh 0,
+        mesh 1, ..., then the shared base)."""
+        lf_fields_set_coefficients(self.fh, layer_types, table)
+
     def labels(self, m: int):
         out = np.zeros(self.n_v[m], np.int32)
         lf_batch_labels(self.h, m, out)
@@ -597,6 +616,11 @@ class Fields:
 
     def reset_regions(self, region_ptr, region_vertices):
         lf_fields_reset_regions(self.h, region_ptr, region_vertices)
+
+    def set_coefficients(self, layer_types=None, table=None):
+        """Per-pair a, w, e from layer types and a type-pair table; None
+        returns to the scalar constants."""
+        lf_fields_set_coefficients(self.h, layer_types, table)
 
     def step(self, n: int = 1):
         lf_step(self.h, n)

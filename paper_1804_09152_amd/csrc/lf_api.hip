@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -75,7 +76,9 @@ static StepArgs make_args(lf_fields* f, int parity) {
   a.c.base_mode = f->P.base_mode;
   a.c.n_s = f->n_s;
   a.c.tau = (float)f->P.tau;
-  a.c.pad_ = 0;
+  a.c.n_types = f->n_types;
+  a.c.types = f->types;
+  a.c.tab = f->coef;
   a.wide = f->wide;
   a.wide_cap = f->wide_cap;
   a.pad_ = 0;
@@ -428,6 +431,8 @@ lf_status lf_fields_destroy(lf_fields* f) {
   (void)hipFree(f->uptr);
   (void)hipFree(f->uent);
   (void)hipFree(f->scan_tmp);
+  (void)hipFree(f->types);
+  (void)hipFree(f->coef);
   if (f->flags_host) (void)hipHostFree(f->flags_host);
   if (f->stats_pinned) (void)hipHostFree(f->stats_pinned);
   if (f->done_ev) (void)hipEventDestroy(f->done_ev);
@@ -706,6 +711,48 @@ bool chunk_quiet(const lf_fields* f, int64_t n, double eps) {
 }  // namespace lf
 
 extern "C" {
+
+lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_t* layer_types,
+                                     const double* table) {
+  if (!f) return fail(LF_EINVAL, "NULL argument");
+  if (n_types < 0 || n_types > 65536) return fail(LF_EINVAL, "n_types out of range");
+  if (n_types > 0 && (!layer_types || !table)) return fail(LF_EINVAL, "NULL argument");
+  const int64_t n_r = (int64_t)f->n_s + 1, n_pairs = (int64_t)n_types * n_types;
+  std::vector<float4> tab((size_t)n_pairs);
+  for (int64_t l = 0; n_types > 0 && l < n_r; ++l)
+    if (layer_types[l] < 0 || layer_types[l] >= n_types) return fail(LF_EINVAL, "layer type out of range");
+  for (int64_t q = 0; q < n_pairs; ++q) {
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(table[3 * q + k])) return fail(LF_EINVAL, "non-finite coefficient");
+    tab[(size_t)q] = make_float4((float)table[3 * q], (float)table[3 * q + 1], (float)table[3 * q + 2], 0.f);
+  }
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  hipStream_t s = f->mesh->ctx->stream;
+  // the steps already issued keep the old tables until they have run
+  LF_HIP(hipStreamSynchronize(s));
+  int32_t* types = nullptr;
+  float4* coef = nullptr;
+  if (n_types > 0) {
+    hipError_t e = dalloc(&types, n_r);
+    if (e == hipSuccess) e = dalloc(&coef, n_pairs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(types, layer_types, sizeof(int32_t) * n_r, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(coef, tab.data(), sizeof(float4) * n_pairs, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      (void)hipFree(types);
+      (void)hipFree(coef);
+      return hip_fail(e, "coefficient tables");
+    }
+  }
+  (void)hipFree(f->types);
+  (void)hipFree(f->coef);
+  f->types = types;
+  f->coef = coef;
+  f->n_types = n_types;
+  return LF_OK;
+}
 
 lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta) {
   if (!f) return fail(LF_EINVAL, "NULL argument");

@@ -66,7 +66,11 @@ struct StepConsts {
   int32_t base_mode;
   int32_t n_s;
   float tau;  // threshold of the rows' tau pattern (convergence measure)
-  int32_t pad_;
+  // per-pair coefficients (0: the scalars a, w, e): type of every layer and
+  // {a, w, e, 0} of every pair of types, row-major
+  int32_t n_types;
+  const int32_t* types;
+  const float4* tab;
 };
 
 // Workspace of one row touching more than kRowRegs layers, or reading a row
@@ -277,6 +281,10 @@ struct lf_fields {
   unsigned long long last_changed;  // change made by the last completed step
   float last_dmax;
   bool measure_all;  // convergence measures on every step (else on the last of a chunk)
+  // per-pair coefficients (n_types 0: the scalar constants)
+  int32_t n_types;
+  int32_t* types;    // n_s + 1
+  float4* coef;      // n_types * n_types
   // timing
   bool timing;
   std::vector<hipEvent_t> ev0, ev1;

@@ -65,11 +65,31 @@ struct MaskT<kRowRegs> {
   using type = unsigned int;
 };
 
-// Closed-form update of one row's active layers.  Slots s < cnt hold the
-// row's union of layers (col, phi = U(i,col), lam = field Laplacian).
-// out_of(r, s) receives the normalised kept value, or -1 (or 0 in register
-// slots beyond the wavefront's largest count).
-template <int K, bool UNROLL, class B>
+// Coefficients {a, w, e} of the ordered pair of layers (j, l), j != l, with
+// types tj, tl: the table entry; in base_mode 0 a pair with the base carries
+// no w, and the base's e against a cell is negated (the scalar reading of
+// the base, one table entry per pair of types).
+__device__ __forceinline__ float4 pair_coef(const StepConsts& c, int tj, int tl, bool jb,
+                                            bool lb) {
+  float4 k = c.tab[(int64_t)tj * c.n_types + tl];
+  if (c.base_mode == 0 && (jb || lb)) {
+    k.y = 0.f;
+    if (jb) k.z = -k.z;
+  }
+  return k;
+}
+
+// Update of one row's active layers.  Slots s < cnt hold the row's union of
+// layers (col, phi = U(i,col), lam = field Laplacian).  out_of(r, s)
+// receives the normalised kept value, or -1 (or 0 in register slots beyond
+// the wavefront's largest count).  TYPED = false: one value per coefficient
+// matrix, the sums over layers collapse to row totals (closed form above).
+// TYPED: per-pair coefficients from the layer types,
+//   Q_j = sum_{l != j} (a_jl lam_l / 2 + w_jl phi_l),
+//   G_j = sum_{k != j} e_jk sqrt(phi_k),
+//   d_j = -(mu/n) (n Q_j - sum_k Q_k - sqrt(phi_j) G_j),
+// the same sums of Algorithm 1 with the pairs spelled out (O(n^2) per row).
+template <int K, bool UNROLL, bool TYPED, class B>
 __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, int& n_keep,
                                            int& n_skel, int& ev) {
   using M = typename MaskT<K>::type;
@@ -155,7 +175,84 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
     out_of(r, s) = v;
     V += v;
   };
-  if constexpr (UNROLL) {
+  if constexpr (TYPED) {
+    // inner loops over the other active slots l
+#define LF_INNER                                                  \
+  _Pragma("unroll") for (int l = 0; l < (UNROLL ? K : 1); ++l)    \
+    if (!__any(l < cnt)) break;                                   \
+    else
+#define LF_INNER_RT for (int l = 0; l < cnt; ++l)
+    // Q_j per slot: registers in the register path, the workspace row's
+    // output slots (overwritten by the value below) in the wide path
+    float qbuf[UNROLL ? K : 1];
+    auto q_at = [&](int s) -> float& {
+      if constexpr (UNROLL) return qbuf[s];
+      else return out_of(r, s);
+    };
+    // the slots' types: loaded once into registers in the register path
+    int tbuf[UNROLL ? K : 1];
+    if constexpr (UNROLL) {
+      LF_SLOTS tbuf[s] = ((act >> s) & 1) ? c.types[r.col[s]] : 0;
+    }
+    auto type_of = [&](int s) {
+      if constexpr (UNROLL) return tbuf[s];
+      else return c.types[r.col[s]];
+    };
+    auto q_of = [&](int s) {
+      const int ts = type_of(s);
+      const bool sb = r.col[s] == c.n_s;
+      float Q = 0.f;
+      auto term = [&](int l) {
+        if (l == s || !((act >> l) & 1)) return;
+        const float4 k = pair_coef(c, ts, type_of(l), sb, r.col[l] == c.n_s);
+        Q += 0.5f * k.x * r.lam[l] + k.y * r.phi[l];
+      };
+      if constexpr (UNROLL) {
+        LF_INNER term(l);
+      } else {
+        LF_INNER_RT term(l);
+      }
+      return Q;
+    };
+    auto d_of = [&](int s, float sumQ_) {
+      const int ts = type_of(s);
+      const bool sb = r.col[s] == c.n_s;
+      float G = 0.f;
+      auto term = [&](int l) {
+        if (l == s || !((act >> l) & 1)) return;
+        const float4 k = pair_coef(c, ts, type_of(l), sb, r.col[l] == c.n_s);
+        G += k.z * root(r.phi[l]);
+      };
+      if constexpr (UNROLL) {
+        LF_INNER term(l);
+      } else {
+        LF_INNER_RT term(l);
+      }
+      return -mun * (fn * q_at(s) - sumQ_ - root(r.phi[s]) * G);
+    };
+#undef LF_INNER
+#undef LF_INNER_RT
+    float sQ = 0.f;
+    auto pass_q = [&](int s) {
+      const float q = q_of(s);
+      q_at(s) = q;
+      sQ += q;
+    };
+    auto pass_v = [&](int s) {
+      float v = r.phi[s] + c.dt * d_of(s, sQ);
+      if (v > 1.f) v = 1.f;
+      if (v <= 0.f) v = 0.f;
+      out_of(r, s) = v;
+      V += v;
+    };
+    if constexpr (UNROLL) {
+      LF_SLOTS if ((act >> s) & 1) pass_q(s);
+      LF_SLOTS if ((act >> s) & 1) pass_v(s); else out_of(r, s) = -1.f;
+    } else {
+      LF_SLOTS_RT if ((act >> s) & 1) pass_q(s);
+      LF_SLOTS_RT if ((act >> s) & 1) pass_v(s); else out_of(r, s) = -1.f;
+    }
+  } else if constexpr (UNROLL) {
     LF_SLOTS if ((act >> s) & 1) upd(s); else out_of(r, s) = -1.f;
   } else {
     LF_SLOTS_RT if ((act >> s) & 1) upd(s); else out_of(r, s) = -1.f;
@@ -390,6 +487,7 @@ __device__ __forceinline__ int gather_slow(RowBuf<kRowRegs>& r, int& cnt, int i,
 // Same arithmetic in the same order as the register path, with kRowWide
 // slots in a global-memory workspace row.  Returns the number of kept
 // entries (0 and *ovf set when the row touches more than kRowWide layers).
+template <bool TYPED>
 __device__ __forceinline__ int wide_row(int i, const Ent* ops, const StepArgs* A, WideRow* r,
                                         int* n_skel, int* ev, int* ovf) {
   int cnt = 0;
@@ -427,7 +525,7 @@ __device__ __forceinline__ int wide_row(int i, const Ent* ops, const StepArgs* A
   }
   for (int s = cnt; s < kRowWide; ++s) { r->col[s] = -1; r->phi[s] = 0.f; r->lam[s] = 0.f; }
   int n_keep = 0;
-  row_update<kRowWide, false>(*r, cnt, A->c, n_keep, *n_skel, *ev);
+  row_update<kRowWide, false, TYPED>(*r, cnt, A->c, n_keep, *n_skel, *ev);
   r->cnt = cnt;
   r->n_keep = n_keep;
   return n_keep;
@@ -547,6 +645,9 @@ __device__ __forceinline__ EllRow row_regs(const RowBuf<kRowRegs>& r, int cnt) {
   return o;
 }
 
+// TYPED: per-pair coefficients (a separate instance, so that the scalar
+// step keeps its registers)
+template <bool TYPED>
 __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
     StepArgs A) {
   const int lane = threadIdx.x;
@@ -584,13 +685,13 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   }
   if (i < A.n_v) {
     if (in_regs) {
-      row_update<kRowRegs, true>(r, cnt, A.c, n_keep, n_skel, ev);
+      row_update<kRowRegs, true, TYPED>(r, cnt, A.c, n_keep, n_skel, ev);
       if (A.measure) row_change(r, cnt, A.c, changed, dmax);
     } else {
       const unsigned slot = atomicAdd(A.wide_ctr, 1u);
       if (slot < (unsigned)A.wide_cap) {
         wide = (int)slot;
-        n_keep = wide_row(i, ops, &A, A.wide + slot, &n_skel, &ev, &rowovf);
+        n_keep = wide_row<TYPED>(i, ops, &A, A.wide + slot, &n_skel, &ev, &rowovf);
         if (rowovf) {
           step_failed(A, 2u);
           n_keep = 0;
@@ -690,9 +791,11 @@ __global__ __launch_bounds__(kParts) void k_reduce_parts(const StepStats* parts,
 hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   const dim3 grid((unsigned)(kXcds * ((a.n_slices + kXcds - 1) / kXcds)));
   if (t0 && t1) {
-    hipExtLaunchKernelGGL(k_step, grid, dim3(kSlice), 0, s, t0, t1, 0, a);
+    if (a.c.n_types > 0) hipExtLaunchKernelGGL(k_step<true>, grid, dim3(kSlice), 0, s, t0, t1, 0, a);
+    else hipExtLaunchKernelGGL(k_step<false>, grid, dim3(kSlice), 0, s, t0, t1, 0, a);
   } else {
-    hipLaunchKernelGGL(k_step, grid, dim3(kSlice), 0, s, a);
+    if (a.c.n_types > 0) hipLaunchKernelGGL(k_step<true>, grid, dim3(kSlice), 0, s, a);
+    else hipLaunchKernelGGL(k_step<false>, grid, dim3(kSlice), 0, s, a);
   }
   return hipGetLastError();
 }

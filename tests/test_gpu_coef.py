@@ -1,0 +1,213 @@
+"""GPU parity of the step with per-pair coefficients (layer types and a
+table over pairs of types, equation (2) with a, w, e per pair) against the
+FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_1804_09152_amd import inputs as I
+from tests.gpu_common import as_oracle, check_step, f32, gpu_load, row_compare, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_09152_amd as lfb
+    lfb.load()
+    ctx = lfb.Context(0)
+    yield lfb, ctx
+
+
+def _table(rng, n_t, symmetric=True):
+    t = np.empty((n_t, n_t, 3))
+    t[..., 0] = rng.uniform(0.02, 0.06, (n_t, n_t))
+    t[..., 1] = rng.uniform(0.1, 0.3, (n_t, n_t))
+    t[..., 2] = rng.uniform(0.5, 1.5, (n_t, n_t))
+    if symmetric:
+        t = 0.5 * (t + t.transpose(1, 0, 2))
+    return t
+
+
+def _gparams(lfb, P):
+    return lfb.default_params(w=P["w"], a=P["a"], e=P["e"], mu=P["mu"], dt=P["dt"],
+                              theta=P["theta"], base_mode=P.get("base_mode", 0))
+
+
+MESHES = {
+    "c1_torus64_graph": (lambda: I.config_c1(), 0),
+    "ico4_jit_cotan": (lambda: I.config_c2(level=4, n_seeds=48, seed=1), 1),
+    "ico5_jit_cotan": (lambda: I.config_c2(level=5, n_seeds=64, seed=2), 1),
+}
+
+TF_CASES = [
+    ("c1_torus64_graph", 0, True, [0, 1, 5, 20, 60, 120]),
+    ("ico5_jit_cotan", 0, False, [0, 1, 3, 10, 40, 100]),
+    ("ico4_jit_cotan", 1, True, [0, 1, 5, 20, 60]),
+]
+
+
+@pytest.mark.parametrize("name,base_mode,symmetric,ts", TF_CASES)
+def test_typed_step_teacher_forced(lf, orc, name, base_mode, symmetric, ts):
+    """The oracle's typed state at step t (rounded to float32) goes into the
+    GPU; one GPU step against one oracle step from the same input."""
+    lfb, ctx = lf
+    (mesh, seeds), op = MESHES[name][0](), MESHES[name][1]
+    k = seeds.size
+    rng = np.random.default_rng(k + base_mode)
+    n_t = 4
+    types = rng.integers(0, n_t, k + 1).astype(np.int32)
+    tab = _table(rng, n_t, symmetric)
+    P = orc.default_params(base_mode=base_mode, types=types, table=tab)
+    L = orc.operator(mesh.V, mesh.F, op)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, op)
+    f = lfb.Fields(m, seeds, _gparams(lfb, P))
+    f.set_coefficients(types, tab)
+    U = orc.init(mesh.n_v, seeds)
+    t = 0
+    for target in ts:
+        while t < target:
+            U = orc.step(L, U, k, P)
+            t += 1
+        Uf = f32(U)
+        say("typed teacher-forced", name, base_mode, symmetric, "t", t)
+        gpu_load(f, Uf)
+        f.step(1)
+        G = as_oracle(f.export())
+        O, info = orc.step(L, Uf, k, P, want_info=True)
+        check_step(G, O, info["margin"], what=f"typed {name} t={t}")
+
+
+def test_typed_free_running_c1(lf, orc):
+    """100 float32 GPU steps against 100 float64 oracle steps with three
+    types: identical patterns, fields within 1e-5."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c1()
+    rng = np.random.default_rng(4)
+    types = rng.integers(0, 3, seeds.size + 1).astype(np.int32)
+    tab = _table(rng, 3)
+    P = orc.default_params(types=types, table=tab)
+    L = orc.operator(mesh.V, mesh.F, 0)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, seeds)
+    f.set_coefficients(types, tab)
+    U = orc.init(mesh.n_v, seeds)
+    for chunk in range(5):
+        say("typed free-running c1 chunk", chunk)
+        f.step(20)
+        for _ in range(20):
+            U = orc.step(L, U, seeds.size, P)
+        G = as_oracle(f.export())
+        pat, diff = row_compare(G, U)
+        assert pat.all(), f"pattern differs at step {20 * (chunk + 1)} on {(~pat).sum()} rows"
+        assert diff.max() <= 1e-5
+
+
+def test_one_type_and_clearing(lf, orc):
+    """One type holding the scalars follows the scalar step (same patterns,
+    values within 1e-5: the sums run in another order); clearing the table
+    runs the scalar kernel again, bit for bit."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c2(level=4, n_seeds=48, seed=1)
+    P = orc.default_params()
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    fs = lfb.Fields(m, seeds)
+    ft = lfb.Fields(m, seeds)
+    ft.set_coefficients(np.zeros(seeds.size + 1, np.int32), np.array([[[P["a"], P["w"], P["e"]]]]))
+    say("one type vs scalar")
+    for _ in range(5):
+        fs.step(20)
+        ft.step(20)
+        pat, diff = row_compare(as_oracle(ft.export()), as_oracle(fs.export()))
+        assert pat.all() and diff.max() <= 1e-5
+    fc = lfb.Fields(m, seeds)
+    fc.set_coefficients(np.zeros(seeds.size + 1, np.int32), np.array([[[0.05, 0.4, 0.3]]]))
+    fc.set_coefficients(None)
+    fc.step(100)
+    for x, y in zip(fc.export(), fs.export()):
+        assert np.array_equal(x, y)
+
+
+def test_typed_wide_rows(lf, orc):
+    """A vertex whose neighbourhood holds 13 layers takes the 64-slot path
+    with per-pair coefficients."""
+    lfb, ctx = lf
+    nx = 16
+    mesh = I.torus_grid(nx, nx)
+    L = orc.operator(mesh.V, mesh.F, 0)
+    nb = [int(c) for c in L[1][L[0][0]:L[0][1]] if c != 0]
+    n_s = 14
+    rows = [{n_s: 1.0} for _ in range(mesh.n_v)]
+    rows[0] = {0: 1.0}
+    for j, u in enumerate(nb):
+        rows[u] = {1 + 2 * j: 0.5, 2 + 2 * j: 0.5}
+    ptr = np.zeros(mesh.n_v + 1, np.int64)
+    col, val = [], []
+    for i, r in enumerate(rows):
+        for c in sorted(r):
+            col.append(c)
+            val.append(r[c])
+        ptr[i + 1] = len(col)
+    U = (ptr, np.array(col, np.int32), np.array(val))
+    rng = np.random.default_rng(8)
+    types = rng.integers(0, 5, n_s + 1).astype(np.int32)
+    tab = _table(rng, 5, symmetric=False)
+    P = orc.default_params(types=types, table=tab)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, np.arange(n_s, dtype=np.int32) + 100)
+    f.set_coefficients(types, tab)
+    say("typed wide rows")
+    for t in range(3):
+        gpu_load(f, f32(U))
+        f.step(1)
+        G = as_oracle(f.export())
+        O, info = orc.step(L, f32(U), n_s, P, want_info=True)
+        check_step(G, O, info["margin"], what=f"typed wide t={t}", max_guarded_frac=0.05)
+        U = O
+
+
+def test_typed_batch_equals_solo(lf):
+    """A batch with per-pair coefficients equals solo runs bit for bit (the
+    batch's layers are the meshes' cells in order, then the shared base)."""
+    lfb, ctx = lf
+    items = I.batch_tori(4, seed=5, nv_lo=200, nv_hi=3000, s_lo=4, s_hi=40)
+    rng = np.random.default_rng(12)
+    n_t = 3
+    tab = _table(rng, n_t)
+    base_t = 2
+    per = [np.append(rng.integers(0, n_t, s.size), base_t).astype(np.int32) for _, s in items]
+    B = lfb.Batch(ctx, [(m.V, m.F) for m, _ in items], 0, [s for _, s in items])
+    B.set_coefficients(np.concatenate([t[:-1] for t in per] + [[base_t]]).astype(np.int32), tab)
+    say("typed batch", [m.n_v for m, _ in items])
+    B.step(40)
+    for k, (mesh, seeds) in enumerate(items):
+        M = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+        f = lfb.Fields(M, seeds)
+        f.set_coefficients(per[k], tab)
+        f.step(40)
+        for x, y in zip(B.export(k), f.export()):
+            assert np.array_equal(x, y), f"mesh {k}"
+
+
+def test_invalid_coefficients(lf):
+    lfb, ctx = lf
+    mesh, seeds = I.config_c1()
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, seeds)
+    n_r = seeds.size + 1
+    with pytest.raises(lfb.LFError):
+        f.set_coefficients(np.full(n_r, 2, np.int32), np.zeros((2, 2, 3)))
+    bad = np.zeros((2, 2, 3))
+    bad[1, 0, 2] = np.nan
+    with pytest.raises(lfb.LFError):
+        f.set_coefficients(np.zeros(n_r, np.int32), bad)
+    with pytest.raises(lfb.LFError):
+        f.set_coefficients(np.zeros(n_r, np.int32), np.zeros((2, 3, 3)))
+    # a failed call leaves the scalar model in place
+    g = lfb.Fields(m, seeds)
+    f.step(10)
+    g.step(10)
+    for x, y in zip(f.export(), g.export()):
+        assert np.array_equal(x, y)
