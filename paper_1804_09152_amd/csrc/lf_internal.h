@@ -239,6 +239,9 @@ struct lf_mesh {
   int32_t n_slices;
   std::vector<double> Vh;  // host copies for small host-side geometry needs
   std::vector<int32_t> Fh;
+  // largest face area and largest |coordinate| (the Lloyd sums' fixed-point
+  // scale); measured on the first re-seeding, < 0 before
+  double amax = -1.0, xmax = -1.0;
 };
 
 struct DualState;  // defined with the dual-mesh kernels

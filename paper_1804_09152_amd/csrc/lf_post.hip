@@ -47,15 +47,54 @@ __global__ void k_bitonic(unsigned long long* a, int64_t n, int64_t k, int64_t j
   }
 }
 
+// The stages of the same network whose partners lie within one chunk of C
+// keys (C a power of two, at most kSortChunk), run by one block in LDS:
+// with k = 0 every stage of k = 2..C (the chunk sorted in the direction
+// the network gives it), otherwise the steps j = C/2..1 of stage k > C.
+// Same compare-exchanges in the same order as the one-stage kernel.
+constexpr int kSortChunk = 2048;
+// rounds of an iteration to a fixed point launched per read of its flag
+constexpr int kCheckEvery = 16;
+__global__ __launch_bounds__(1024) void k_bitonic_local(unsigned long long* a, int64_t C, int64_t k) {
+  __shared__ unsigned long long sh[kSortChunk];
+  const int64_t base = (int64_t)blockIdx.x * C;
+  for (int64_t t = threadIdx.x; t < C; t += blockDim.x) sh[t] = a[base + t];
+  __syncthreads();
+  auto stage = [&](int64_t kk, int64_t j) {
+    for (int64_t t = threadIdx.x; t < C / 2; t += blockDim.x) {
+      const int64_t i = 2 * j * (t / j) + (t % j), l = i + j;
+      const bool up = ((base + i) & kk) == 0;
+      const unsigned long long x = sh[i], y = sh[l];
+      if (up ? (x > y) : (x < y)) {
+        sh[i] = y;
+        sh[l] = x;
+      }
+    }
+    __syncthreads();
+  };
+  if (k == 0) {
+    for (int64_t kk = 2; kk <= C; kk <<= 1)
+      for (int64_t j = kk >> 1; j > 0; j >>= 1) stage(kk, j);
+  } else {
+    for (int64_t j = C >> 1; j > 0; j >>= 1) stage(k, j);
+  }
+  for (int64_t t = threadIdx.x; t < C; t += blockDim.x) a[base + t] = sh[t];
+}
+
 // sorts keys[0..n) ascending in place; keys has room for next_pow2(n)
 hipError_t sort_u64(unsigned long long* keys, int64_t n, hipStream_t s) {
   if (n <= 1) return hipSuccess;
   int64_t N = 1;
   while (N < n) N <<= 1;
   if (N > n) hipLaunchKernelGGL(k_fill64, dim3(nblk(N - n)), dim3(kT), 0, s, keys + n, N - n, kEmpty);
-  for (int64_t k = 2; k <= N; k <<= 1)
-    for (int64_t j = k >> 1; j > 0; j >>= 1)
+  const int64_t C = std::min<int64_t>(N, kSortChunk);
+  const dim3 lg((unsigned)(N / C)), lb((unsigned)std::min<int64_t>(C / 2, 1024));
+  hipLaunchKernelGGL(k_bitonic_local, lg, lb, 0, s, keys, C, (int64_t)0);
+  for (int64_t k = 2 * C; k <= N; k <<= 1) {
+    for (int64_t j = k >> 1; j >= C; j >>= 1)
       hipLaunchKernelGGL(k_bitonic, dim3(nblk(N)), dim3(kT), 0, s, keys, N, k, j);
+    hipLaunchKernelGGL(k_bitonic_local, lg, lb, 0, s, keys, C, k);
+  }
   return hipGetLastError();
 }
 
@@ -660,6 +699,9 @@ __global__ void k_comp_step(const int32_t* across, int32_t* label, int64_t nt, i
     const int32_t g = across[3 * t + e];
     if (g >= 0) m = min(m, label[g]);
   }
+  // a label is a triangle of the same component with a label no larger:
+  // following it once shortens the chains (labels never grow)
+  m = min(m, label[m]);
   if (m < label[t]) {
     atomicMin(&label[t], m);
     *changed = 1;
@@ -871,18 +913,20 @@ lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out)
   LF_HIP(status.alloc(n_s));
   LF_HIP(owner.alloc(m->n_v));
   LF_HIP(changed.alloc(1));
-  LF_HIP(hipMemsetAsync(bounds.p, 0, 2 * sizeof(unsigned long long), s));
   LF_HIP(hipMemsetAsync(acc.p, 0, sizeof(CellSums) * n_s, s));
   LF_HIP(hipMemcpyAsync(old.p, f->seeds.data(), sizeof(int32_t) * n_s, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_bounds, dim3(nblk(n_f)), dim3(kT), 0, s, m->V, m->F, n_f, bounds.p,
-                     bounds.p + 1);
-  LF_HIP(hipGetLastError());
-  unsigned long long hb[2] = {0, 0};
-  LF_HIP(hipMemcpyAsync(hb, bounds.p, sizeof(hb), hipMemcpyDeviceToHost, s));
-  LF_HIP(hipStreamSynchronize(s));
-  double amax, xmax;
-  memcpy(&amax, &hb[0], sizeof(double));
-  memcpy(&xmax, &hb[1], sizeof(double));
+  if (m->amax < 0.0) {  // a property of the mesh: measured once
+    LF_HIP(hipMemsetAsync(bounds.p, 0, 2 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_bounds, dim3(nblk(n_f)), dim3(kT), 0, s, m->V, m->F, n_f, bounds.p,
+                       bounds.p + 1);
+    LF_HIP(hipGetLastError());
+    unsigned long long hb[2] = {0, 0};
+    LF_HIP(hipMemcpyAsync(hb, bounds.p, sizeof(hb), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipStreamSynchronize(s));
+    memcpy(&m->amax, &hb[0], sizeof(double));
+    memcpy(&m->xmax, &hb[1], sizeof(double));
+  }
+  const double amax = m->amax, xmax = m->xmax;
   // fixed-point scale: the largest possible per-cell sum stays below 2^62
   const double bound = std::max(1e-300, (double)n_f * amax * (xmax + 1.0));
   const double scale = std::ldexp(1.0, 62 - (int)std::ceil(std::log2(bound)));
@@ -1077,9 +1121,12 @@ lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, 
     hipLaunchKernelGGL(k_edge_links, dim3(nblk(3 * T)), dim3(kT), 0, s, ek.p, 3 * T, T, n_s, tri2.p,
                        across.p, nonman.p);
     hipLaunchKernelGGL(k_comp_init, dim3(nblk(T)), dim3(kT), 0, s, label.p, T);
-    for (int64_t it = 0; it <= T; ++it) {
+    // label propagation to a fixed point; extra rounds change nothing, so the
+    // host reads the change flag once per kCheckEvery rounds
+    for (int64_t it = 0; it <= T; it += kCheckEvery) {
       LF_HIP(hipMemsetAsync(chg.p, 0, sizeof(int32_t), s));
-      hipLaunchKernelGGL(k_comp_step, dim3(nblk(T)), dim3(kT), 0, s, across.p, label.p, T, chg.p);
+      for (int q = 0; q < kCheckEvery; ++q)
+        hipLaunchKernelGGL(k_comp_step, dim3(nblk(T)), dim3(kT), 0, s, across.p, label.p, T, chg.p);
       int32_t h = 0;
       LF_HIP(hipMemcpyAsync(&h, chg.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       LF_HIP(hipStreamSynchronize(s));
@@ -1092,10 +1139,13 @@ lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, 
                        n_s, vn.p);
     hipLaunchKernelGGL(k_orient_roots, dim3(nblk(T)), dim3(kT), 0, s, tri2.p, label.p, T, m->V,
                        f->d_seeds, vn.p, otri.p, level.p);
-    for (int32_t lev = 1; lev <= T; ++lev) {
+    // breadth-first levels; a level past the last one assigns nothing, so the
+    // host reads the flag once per kCheckEvery levels
+    for (int32_t lev = 1; lev <= T; lev += kCheckEvery) {
       LF_HIP(hipMemsetAsync(chg.p, 0, sizeof(int32_t), s));
-      hipLaunchKernelGGL(k_orient_level, dim3(nblk(T)), dim3(kT), 0, s, tri2.p, across.p, T, lev,
-                         otri.p, level.p, chg.p);
+      for (int32_t q = 0; q < kCheckEvery; ++q)
+        hipLaunchKernelGGL(k_orient_level, dim3(nblk(T)), dim3(kT), 0, s, tri2.p, across.p, T,
+                           lev + q, otri.p, level.p, chg.p);
       int32_t h = 0;
       LF_HIP(hipMemcpyAsync(&h, chg.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       LF_HIP(hipStreamSynchronize(s));
