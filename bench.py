@@ -332,8 +332,9 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 10}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "the step would shard by vertex rows with a one-ring halo exchange",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
