@@ -274,7 +274,9 @@ typedef struct {
   double conv_eps;     /* > 0: a phase ends at convergence (lf_step_until's rule */
   int32_t conv_every;  /*      with eps = conv_eps, check_every = conv_every); steps
                         *      is then the cap */
-  int32_t pad2_;
+  int32_t n_types;     /* > 0: per-pair coefficients, as lf_fields_set_coefficients */
+  const int32_t* layer_types;  /* int32[n_s+1] (NULL when n_types = 0) */
+  const double* table;         /* double[n_types*n_types*3] */
 } lf_job;
 /* hbm_budget: bytes the active jobs may hold (estimated per job from its
  * size); max_active: concurrent jobs; chunk: steps issued per job per poll. */

@@ -45,7 +45,8 @@ class lf_job(C.Structure):
                 ("n_v", C.c_int32), ("n_f", C.c_int32), ("n_s", C.c_int32), ("op", C.c_int32),
                 ("steps", C.c_int32), ("lloyd_rounds", C.c_int32), ("dual_mesh", C.c_int32),
                 ("pad_", C.c_int32), ("params", lf_params), ("conv_eps", C.c_double),
-                ("conv_every", C.c_int32), ("pad2_", C.c_int32)]
+                ("conv_every", C.c_int32), ("n_types", C.c_int32),
+                ("layer_types", C.c_void_p), ("table", C.c_void_p)]
 
 
 EXPORTS = [
@@ -543,7 +544,7 @@ class Server:
 
     def submit(self, V, F, seeds, steps: int, lloyd_rounds: int = 0, dual_mesh: bool = False,
                op: int = LF_OP_GRAPH, params: lf_params | None = None, conv_eps: float = 0.0,
-               conv_every: int = 16) -> int:
+               conv_every: int = 16, layer_types=None, table=None) -> int:
         V = np.ascontiguousarray(V, np.float64)
         F = np.ascontiguousarray(F, np.int32)
         S = np.ascontiguousarray(seeds, np.int32)
@@ -553,6 +554,12 @@ class Server:
         j.steps, j.lloyd_rounds, j.dual_mesh = steps, lloyd_rounds, int(bool(dual_mesh))
         j.params = params if params is not None else default_params()
         j.conv_eps, j.conv_every = conv_eps, conv_every
+        if layer_types is not None:  # copied by the server during submit
+            T = np.ascontiguousarray(layer_types, np.int32)
+            tab = np.ascontiguousarray(table, np.float64)
+            if tab.ndim != 3 or tab.shape[0] != tab.shape[1] or tab.shape[2] != 3 or T.size != S.size + 1:
+                raise LFError(1, "layer_types must hold n_s + 1 types, table (n_types, n_types, 3)")
+            j.n_types, j.layer_types, j.table = tab.shape[0], T.ctypes.data, tab.ctypes.data
         i = lf_server_submit(self.h, j)
         self.shape[i] = (V.shape[0], S.size)
         return i

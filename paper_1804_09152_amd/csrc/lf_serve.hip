@@ -30,6 +30,9 @@ struct Job {
   lf_params P;
   double conv_eps = 0;  // > 0: phases end at convergence
   int32_t conv_every = 0;
+  int32_t n_types = 0;  // per-pair coefficients
+  std::vector<int32_t> layer_types;
+  std::vector<double> table;
   bool chunk_quiet = true;  // the current chunk has been quiet so far
   int64_t chunk_pos = 0;     // steps of the current chunk done
   int64_t bytes = 0;
@@ -100,6 +103,8 @@ lf_status admit(lf_server* s, Job* j) {
   lf_status st = lf_ctx_create(s->device, nullptr, &j->ctx);
   if (!st) st = lf_mesh_create(j->ctx, j->V.data(), j->n_v, j->F.data(), j->n_f, j->op, &j->mesh);
   if (!st) st = lf_fields_create(j->mesh, j->seeds.data(), j->n_s, &j->P, &j->f);
+  if (!st && j->n_types > 0)
+    st = lf_fields_set_coefficients(j->f, j->n_types, j->layer_types.data(), j->table.data());
   if (st) return st;
   j->f->measure_all = j->conv_eps > 0;
   j->state = kActive;
@@ -182,10 +187,13 @@ lf_status lf_server_destroy(lf_server* s) {
 lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id) {
   if (!s || !job || !id || !job->V || !job->F || !job->seeds || job->n_v < 3 || job->n_f < 1 ||
       job->n_s < 1 || job->steps < 0 || job->lloyd_rounds < 0 || job->conv_eps < 0 ||
-      (job->conv_eps > 0 && job->conv_every < 1))
+      (job->conv_eps > 0 && job->conv_every < 1) || job->n_types < 0 || job->n_types > 65536 ||
+      (job->n_types > 0 && (!job->layer_types || !job->table)))
     return sfail(LF_EINVAL, "invalid job");
   Job* j = new Job();
   j->bytes = job_bytes(job->n_v, job->n_f);
+  if (job->n_types > 0)  // the coefficient table and the layer types on the device
+    j->bytes += 16ll * job->n_types * job->n_types + 4ll * (job->n_s + 1);
   if (j->bytes > s->budget) {
     delete j;
     return sfail(LF_ENOMEM, "the job alone exceeds the HBM budget");
@@ -204,6 +212,11 @@ lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id) {
   j->P = job->params;
   j->conv_eps = job->conv_eps;
   j->conv_every = job->conv_every;
+  j->n_types = job->n_types;
+  if (job->n_types > 0) {  // checked when the job is admitted
+    j->layer_types.assign(job->layer_types, job->layer_types + job->n_s + 1);
+    j->table.assign(job->table, job->table + 3ll * job->n_types * job->n_types);
+  }
   j->t_submit = now_ms();
   s->queue.push_back(j);
   s->jobs[j->id] = j;

@@ -78,5 +78,8 @@ def test_server_host_logic_without_gpu():
     with pytest.raises(lfb.LFError) as e:
         lfb.lf_server_result(S.h, 12345)
     assert e.value.status == 1
+    with pytest.raises(lfb.LFError):  # layer types for n_s + 1 layers, a square table
+        S.submit(mesh.V, mesh.F, seeds, steps=10, layer_types=np.zeros(3, np.int32),
+                 table=np.zeros((2, 2, 3)))
     assert S.memory() == (0, 0)
     S.close()  # queued jobs are dropped

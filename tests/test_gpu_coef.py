@@ -211,3 +211,37 @@ def test_invalid_coefficients(lf):
     g.step(10)
     for x, y in zip(f.export(), g.export()):
         assert np.array_equal(x, y)
+
+
+def test_typed_server_job_equals_solo(lf):
+    """A served job with per-pair coefficients computes what the same calls
+    compute alone; a job whose types are out of range fails on its own."""
+    lfb, ctx = lf
+    rng = np.random.default_rng(21)
+    jobs = []
+    for k, (nx, ny, n_s) in enumerate([(24, 24, 6), (30, 20, 9), (16, 40, 5)]):
+        mesh = I.torus_grid(nx, ny)
+        seeds = I.seeds_uniform(mesh.n_v, n_s, rng)
+        types = rng.integers(0, 3, n_s + 1).astype(np.int32)
+        jobs.append((mesh, seeds, types, _table(rng, 3)))
+    S = lfb.Server(0, 4096 << 20, 2, 16)
+    ids = [S.submit(m.V, m.F, s, 40, 1, True, 0, layer_types=t, table=tab) for m, s, t, tab in jobs]
+    m0, s0, t0, tab0 = jobs[0]
+    bad = S.submit(m0.V, m0.F, s0, 10, layer_types=np.full(t0.size, 7, np.int32), table=tab0)
+    say("typed server jobs")
+    S.run()
+    with pytest.raises(lfb.LFError):
+        S.result(bad)
+    for i, (mesh, seeds, types, tab) in zip(ids, jobs):
+        M = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+        f = lfb.Fields(M, seeds)
+        f.set_coefficients(types, tab)
+        f.step(40)
+        s, _ = f.lloyd_reseed()
+        f.reset(s)
+        f.step(40)
+        r = S.result(i)
+        assert np.array_equal(r["seeds"], f.seeds())
+        assert np.array_equal(r["labels"], f.labels())
+        assert np.array_equal(r["tris"], f.dual_mesh(0.25)[0])
+    S.close()
