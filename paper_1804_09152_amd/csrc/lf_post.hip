@@ -125,12 +125,25 @@ __device__ __forceinline__ void set_insert(unsigned long long* tab, int64_t cap,
   atomicOr(overflow, 1);
 }
 
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// the keys of a hash set, in any order (they are sorted next): one atomic
+// per wavefront reserves the wavefront's run of the output
 __global__ void k_set_extract(const unsigned long long* tab, int64_t cap, unsigned long long* out,
                               unsigned long long* count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cap) return;
-  const unsigned long long k = tab[i];
-  if (k != kEmpty) out[atomicAdd(count, 1ull)] = k;
+  const unsigned long long k = i < cap ? tab[i] : kEmpty;
+  const bool has = k != kEmpty;
+  const unsigned long long mask = __ballot(has);
+  const int lane = (int)(threadIdx.x & 63);
+  unsigned long long base = 0;
+  if (lane == 0 && mask) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+  base = __shfl(base, 0, 64);
+  if (has) out[base + __popcll(mask & ((1ull << lane) - 1ull))] = k;
 }
 
 __device__ __forceinline__ bool bsearch_u64(const unsigned long long* a, int64_t n,
@@ -396,16 +409,24 @@ __global__ void k_dual_count(const int32_t* F, int32_t n_f, int32_t n_v, const i
                              const Ent* uent, int32_t n_s, float tau,
                              unsigned long long* counts /* [2] */) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long cv = 0, ct = 0;
   if (t < n_v) {
     long long k = 0;
     for (int32_t p = uptr[t]; p < uptr[t + 1]; ++p)
       k += (uent[p].col < n_s && uent[p].val >= tau) ? 1 : 0;
-    if (k > 1) atomicAdd(&counts[0], (unsigned long long)(k * (k - 1) / 2));
+    if (k > 1) cv = (unsigned long long)(k * (k - 1) / 2);
   }
   if (t < n_f) {
     long long k = 0;
     face_cells(F, t, uptr, uent, n_s, tau, true, [&](int32_t) { ++k; });
-    if (k > 1) atomicAdd(&counts[1], (unsigned long long)(k * (k - 1) / 2));
+    if (k > 1) ct = (unsigned long long)(k * (k - 1) / 2);
+  }
+  // one atomic per wavefront and counter
+  cv = wave_sum_u64(cv);
+  ct = wave_sum_u64(ct);
+  if ((threadIdx.x & 63) == 0) {
+    if (cv) atomicAdd(&counts[0], cv);
+    if (ct) atomicAdd(&counts[1], ct);
   }
 }
 
