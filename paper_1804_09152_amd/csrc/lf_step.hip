@@ -327,6 +327,15 @@ constexpr int kWin = LF_WIN;  // neighbour rows in flight
 
 __device__ __forceinline__ bool is_ovf(const Ent& e) { return e.col == kOvfMark; }
 
+// row v of U_t: a 32-bit byte offset from the buffer's base (rows are 32
+// bytes and a field buffer stays far below 4 GiB), so that the load adds
+// the offset to the base in the address unit instead of in 64-bit vector
+// arithmetic
+__device__ __forceinline__ EllRow row_at(const EllRow* base, int v) {
+  return *reinterpret_cast<const EllRow*>(reinterpret_cast<const char*>(base) +
+                                          (uint32_t)v * (uint32_t)sizeof(EllRow));
+}
+
 // entries of a row of U_t
 struct RowView {
   const Ent* p;
@@ -377,8 +386,9 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   cnt = 0;
-  const EllRow own = A.u_in[i];
-  const float dg = A.ldiag[i];
+  const EllRow own = row_at(A.u_in, i);
+  const float dg = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.ldiag) +
+                                                   (uint32_t)i * 4u);
   // entries of U_t in this row (for the counters)
   n_in = 0;
 #pragma unroll
@@ -390,7 +400,7 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n
     le[k] = k < A.op_w ? ops[k * kSlice] : Ent{-1, 0.f};
   EllRow win[kWin];
 #pragma unroll
-  for (int k = 0; k < kWin; ++k) win[k] = A.u_in[le[k].col >= 0 ? le[k].col : i];
+  for (int k = 0; k < kWin; ++k) win[k] = row_at(A.u_in, le[k].col >= 0 ? le[k].col : i);
   if (is_ovf(own.e[0])) return kGatherOvf;
   // own row: slots 0..3 in layer order
 #pragma unroll
@@ -407,7 +417,7 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n
   for (int k = 0; k < kNbPre; ++k) {
     const EllRow u = win[k % kWin];
     if (k + kWin < kNbPre)
-      win[k % kWin] = A.u_in[le[k + kWin].col >= 0 ? le[k + kWin].col : i];
+      win[k % kWin] = row_at(A.u_in, le[k + kWin].col >= 0 ? le[k + kWin].col : i);
     if (le[k].col < 0) continue;
     if (is_ovf(u.e[0])) {
       orow = true;
@@ -419,7 +429,7 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n
   }
   auto more = [&](const Ent& l) {  // neighbours beyond the prefetched ones
     if (l.col < 0) return;
-    const EllRow u = A.u_in[l.col];
+    const EllRow u = row_at(A.u_in, l.col);
     if (is_ovf(u.e[0])) {
       orow = true;
       return;
@@ -720,7 +730,8 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
     } else if (wide < 0) {
       // the whole row from registers: two 16-byte stores, contiguous across
       // the wavefront
-      A.u_out[i] = row_regs(r, cnt);
+      *reinterpret_cast<EllRow*>(reinterpret_cast<char*>(A.u_out) +
+                                 (uint32_t)i * (uint32_t)sizeof(EllRow)) = row_regs(r, cnt);
       dst = nullptr;
     } else {
       for (int p = n_keep; p < kEll; ++p) row[p] = Ent{-1, 0.f};
