@@ -222,8 +222,10 @@ lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skeleton_total, int64_
 lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out);
 
 /* Device time of the step kernels, measured with HIP events on the
- * context stream around every step launch while enabled; total in ms and
- * number of launches timed since the last enable. */
+ * context stream around step launches while enabled: enable = 1 times every
+ * launch, enable = k > 1 every k-th (the events cost a few microseconds of
+ * wall time per timed launch), 0 stops, -1 only reads.  Total in ms and
+ * number of launches timed since timing was last switched on. */
 lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t* launches);
 
 /* ---- batches: many independent meshes advanced by the same launches ------

@@ -628,7 +628,7 @@ lf_status step_issue(lf_fields* f, int64_t n) {
     a.step_idx = (uint32_t)k;
     a.measure = (f->measure_all || k == n - 1) ? 1u : 0u;
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (f->timing) {
+    if (f->timing > 0 && f->timing_ctr++ % f->timing == 0) {
       t0 = pool_event(f->ev0, used);
       t1 = pool_event(f->ev1, used);
       if (t0 && t1) ++used;
@@ -964,8 +964,9 @@ lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t
     if (enable && !f->timing) {
       f->timed_ms = 0.0;
       f->timed_launches = 0;
+      f->timing_ctr = 0;
     }
-    f->timing = enable != 0;
+    f->timing = enable;
   }
   return LF_OK;
 }

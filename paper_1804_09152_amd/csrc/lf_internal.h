@@ -289,7 +289,8 @@ struct lf_fields {
   int32_t* types;    // n_s + 1
   float4* coef;      // n_types * n_types
   // timing
-  bool timing;
+  int32_t timing;             // time every timing-th step launch (0: off)
+  int64_t timing_ctr;         // step launches issued while timing
   std::vector<hipEvent_t> ev0, ev1;
   double timed_ms;
   long long timed_launches;
