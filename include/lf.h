@@ -190,6 +190,13 @@ lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_device_ptr);
  * seeds_out int32[n_s] and status int32[n_s] (0 hit, 1 miss, 2 collision;
  * may be NULL), host.  Does not re-initialise the fields. */
 lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status);
+/* Lloyd-like iterations (Section 5, Figure 11): `rounds` times, re-seed
+ * (lf_lloyd_reseed), re-initialise the fields from the new seeds
+ * (lf_fields_reset) and run steps_per_round steps (lf_step).  Writes the
+ * final seeds to host seeds_out int32[n_s] (may be NULL); with rounds = 0 it
+ * only copies the current seeds.  Errors as the calls it makes; the fields
+ * are those of the last completed call. */
+lf_status lf_lloyd(lf_fields* f, int32_t rounds, int32_t steps_per_round, int32_t* seeds_out);
 
 /* Dual mesh (Sections 5.1-5.2) from the current fields with threshold tau:
  * A_v = Phibar Phibar^T, A_t = (Phibar Mbar)(Phibar Mbar)^T, candidates

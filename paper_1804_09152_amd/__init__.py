@@ -53,7 +53,7 @@ EXPORTS = [
     "lf_last_error", "lf_params_default", "lf_ctx_create", "lf_ctx_destroy", "lf_mesh_create",
     "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
     "lf_fields_reset", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_fields_set_coefficients", "lf_step", "lf_sync", "lf_fields_export",
-    "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_dual_mesh", "lf_dual_matrix",
+    "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_lloyd", "lf_dual_mesh", "lf_dual_matrix",
     "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
     "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
     "lf_server_create", "lf_server_destroy", "lf_server_submit", "lf_server_poll",
@@ -111,6 +111,7 @@ def load(path: str | None = None):
         "lf_fields_import": (C.c_int, [V, I64, V, V, V, I32]),
         "lf_labels": (C.c_int, [V, V, I32]),
         "lf_lloyd_reseed": (C.c_int, [V, V, V]),
+        "lf_lloyd": (C.c_int, [V, I32, I32, V]),
         "lf_dual_mesh": (C.c_int, [V, D, V, V, V, V, V]),
         "lf_dual_matrix": (C.c_int, [V, I32, V, V, V]),
         "lf_dual_candidates": (C.c_int, [V, V, V, V]),
@@ -674,6 +675,13 @@ class Fields:
         out = np.zeros(self.mesh.n_v, np.int32)
         lf_labels(self.h, out)
         return out
+
+    def lloyd(self, rounds: int, steps_per_round: int):
+        """rounds x (re-seed, re-initialise, steps_per_round steps); the
+        final seeds."""
+        seeds = np.zeros(self.n_s, np.int32)
+        _check(load().lf_lloyd(self.h, rounds, steps_per_round, seeds.ctypes.data))
+        return seeds
 
     def lloyd_reseed(self):
         seeds = np.zeros(self.n_s, np.int32)

@@ -980,6 +980,19 @@ lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out)
   return LF_OK;
 }
 
+lf_status lf_lloyd(lf_fields* f, int32_t rounds, int32_t steps_per_round, int32_t* seeds_out) {
+  if (!f || rounds < 0 || steps_per_round < 0) return fail(LF_EINVAL, "invalid argument");
+  std::vector<int32_t> seeds((size_t)f->n_s);
+  for (int32_t r = 0; r < rounds; ++r) {
+    lf_status st = lf_lloyd_reseed(f, seeds.data(), nullptr);
+    if (!st) st = lf_fields_reset(f, seeds.data());
+    if (!st) st = lf_step(f, steps_per_round);
+    if (st) return st;
+  }
+  if (seeds_out) return lf_fields_seeds(f, seeds_out);
+  return LF_OK;
+}
+
 lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, int64_t* adj_nnz,
                        int32_t* adj_rowptr, int32_t* adj_col) {
   if (!f || !n_tri || !adj_nnz) return fail(LF_EINVAL, "NULL argument");

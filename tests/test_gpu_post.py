@@ -160,3 +160,26 @@ def test_full_size_c3_post(lf, orc):
     assert np.array_equal(pairs, d["cand"])
     clear = d["cand_margin"] > 1e-12
     assert np.array_equal(state[clear], d["cand_state"][clear])
+
+
+def test_lloyd_rounds_entry_point(lf):
+    """lf_lloyd(rounds, steps) is rounds x (re-seed, re-initialise, steps)."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c2(level=4, n_seeds=48, seed=1)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    a = lfb.Fields(m, seeds)
+    b = lfb.Fields(m, seeds)
+    say("lloyd rounds entry point")
+    a.step(60)
+    b.step(60)
+    assert np.array_equal(a.lloyd(0, 10), seeds)  # no round: the current seeds
+    got = a.lloyd(3, 60)
+    for _ in range(3):
+        s, _ = b.lloyd_reseed()
+        b.reset(s)
+        b.step(60)
+    assert np.array_equal(got, b.seeds())
+    for x, y in zip(a.export(), b.export()):
+        assert np.array_equal(x, y)
+    with pytest.raises(lfb.LFError):
+        a.lloyd(-1, 10)
