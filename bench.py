@@ -15,6 +15,9 @@ bytes per launch over its event-timed duration, against 8 TB/s), and the
 FP64 CPU oracle timed on a bounded sample of the same job.  More objects
 in the same line:
 
+* "copy_roof": a measured 1 GiB device-to-device copy (read + write bytes
+  over time), the practical HBM roof, and the step's achieved bandwidth as a
+  fraction of it.
 * "c2": jittered icosphere level 7 (163,842 vertices), 1,024 seeds,
   cotangent operator, 1,000 steps + 5 Lloyd rounds + labels + dual mesh.
 * "batch": 256 torus grids of uneven size (vertex counts log-uniform in
@@ -125,9 +128,37 @@ def cpu_baseline(mesh, seeds, seconds: float, max_steps: int = 200):
             break
     dt = time.perf_counter() - t0
     log(f"cpu baseline: {n} steps in {dt:.1f} s")
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": skel / dt, "unit": "nnz-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} Euler steps of the same job from its seeds, FP64 C oracle, "
-                      f"one thread, operator build excluded ({dt:.1f} s)"}
+                      f"one thread, operator build excluded ({dt:.1f} s)",
+            "host_cpu": model, "host_threads": os.cpu_count()}
+
+
+def copy_roof(mib: int = 1024, reps: int = 10):
+    """Measured device-to-device copy bandwidth (read + write bytes / time),
+    the practical HBM roof next to the vendor peak."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    b.synchronize()
+    gbs = 2 * n * 4 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    return gbs
 
 
 def run_c2(lfb, I, steps: int, rounds: int, jobs: int):
@@ -442,6 +473,11 @@ def main():
     }
     f.close()
     m.close()
+    roof = copy_roof()
+    out["copy_roof"] = {"unit": "GB/s", "measured": roof, "frac_of_peak": roof / HBM_PEAK_GBS,
+                        "step_achieved_frac": achieved / roof,
+                        "what": "1 GiB device-to-device copy, read + write bytes"}
+    log(f"copy roof: {roof:.0f} GB/s")
     if not args.no_c2:
         out["c2"] = run_c2(lfb, I, 1000, 5, 3)
     if not args.no_batch:
