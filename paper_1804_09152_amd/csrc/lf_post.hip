@@ -708,25 +708,55 @@ __global__ void k_edge_links(const unsigned long long* keys, int64_t nk, int64_t
 }
 
 // components of the edge-adjacency graph by minimum-label propagation
+// Components of the dual triangles across manifold edges, by union-find:
+// every hook puts the larger root under the smaller one with a
+// compare-and-swap, so parents only decrease, every walk up a tree ends,
+// and the root of a component is its lowest triangle id.  One pass hooks
+// every edge, a second one points every triangle at its root.
+__device__ __forceinline__ int32_t cc_root(int32_t* parent, int32_t v) {
+  int32_t cur = parent[v];
+  if (cur != v) {
+    int32_t prev = v, next;
+    while (cur > (next = parent[cur])) {  // path halving; next < cur < prev
+      parent[prev] = next;
+      prev = cur;
+      cur = next;
+    }
+  }
+  return cur;
+}
+
+__global__ void k_cc_hook(const int32_t* across, int32_t* parent, int64_t nt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  int32_t a = cc_root(parent, (int32_t)t);
+  for (int e = 0; e < 3; ++e) {
+    const int32_t g = across[3 * t + e];
+    if (g < 0) continue;
+    int32_t b = cc_root(parent, g);
+    while (a != b) {
+      // a failed swap returns the node's new, lower parent: climb to it
+      if (a < b) {
+        const int32_t r = atomicCAS(&parent[b], b, a);
+        if (r == b) break;
+        b = r;
+      } else {
+        const int32_t r = atomicCAS(&parent[a], a, b);
+        if (r == a) break;
+        a = r;
+      }
+    }
+  }
+}
+
+__global__ void k_cc_final(int32_t* parent, int64_t nt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nt) parent[t] = cc_root(parent, (int32_t)t);
+}
+
 __global__ void k_comp_init(int32_t* label, int64_t nt) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nt) label[t] = (int32_t)t;
-}
-__global__ void k_comp_step(const int32_t* across, int32_t* label, int64_t nt, int32_t* changed) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nt) return;
-  int32_t m = label[t];
-  for (int e = 0; e < 3; ++e) {
-    const int32_t g = across[3 * t + e];
-    if (g >= 0) m = min(m, label[g]);
-  }
-  // a label is a triangle of the same component with a label no larger:
-  // following it once shortens the chains (labels never grow)
-  m = min(m, label[m]);
-  if (m < label[t]) {
-    atomicMin(&label[t], m);
-    *changed = 1;
-  }
 }
 
 // area-weighted normals at seed vertices (faces touching a seed)
@@ -1154,18 +1184,10 @@ lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, 
     LF_HIP(sort_u64(ek.p, 3 * T, s));
     hipLaunchKernelGGL(k_edge_links, dim3(nblk(3 * T)), dim3(kT), 0, s, ek.p, 3 * T, T, n_s, tri2.p,
                        across.p, nonman.p);
+    // component labels: the lowest triangle id of each component
     hipLaunchKernelGGL(k_comp_init, dim3(nblk(T)), dim3(kT), 0, s, label.p, T);
-    // label propagation to a fixed point; extra rounds change nothing, so the
-    // host reads the change flag once per kCheckEvery rounds
-    for (int64_t it = 0; it <= T; it += kCheckEvery) {
-      LF_HIP(hipMemsetAsync(chg.p, 0, sizeof(int32_t), s));
-      for (int q = 0; q < kCheckEvery; ++q)
-        hipLaunchKernelGGL(k_comp_step, dim3(nblk(T)), dim3(kT), 0, s, across.p, label.p, T, chg.p);
-      int32_t h = 0;
-      LF_HIP(hipMemcpyAsync(&h, chg.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      LF_HIP(hipStreamSynchronize(s));
-      if (!h) break;
-    }
+    hipLaunchKernelGGL(k_cc_hook, dim3(nblk(T)), dim3(kT), 0, s, across.p, label.p, T);
+    hipLaunchKernelGGL(k_cc_final, dim3(nblk(T)), dim3(kT), 0, s, label.p, T);
     LF_HIP(launch_fill_i32(f->owner, n_v, n_s, s));
     LF_HIP(hipMemcpyAsync(f->d_seeds, f->seeds.data(), sizeof(int32_t) * n_s, hipMemcpyHostToDevice, s));
     LF_HIP(launch_scatter_owner(f->d_seeds, n_s, f->owner, s));
