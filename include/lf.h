@@ -129,8 +129,8 @@ lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds);
  * (NULL arrays) returns to the scalars of the params.  The update then
  * costs O(n^2) table reads per row of n active layers.  Applies from the
  * next step; the fields are not touched.  LF_EINVAL for types out of range,
- * non-finite entries or n_types above 65536; LF_ENOMEM when the table does
- * not fit.  For a batch, the layers are those of lf_batch_fields. */
+ * entries that are not finite in float32 or n_types above 65536; LF_ENOMEM
+ * when the table does not fit.  For a batch, the layers are those of lf_batch_fields. */
 lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_t* layer_types,
                                      const double* table);
 

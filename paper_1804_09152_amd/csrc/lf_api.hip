@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,11 @@ void set_error(const std::string& msg) { g_err = msg; }
 lf_status hip_fail(hipError_t e, const char* what) {
   g_err = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
   return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? LF_ENOMEM : LF_EDEVICE;
+}
+
+lf_status host_oom() {
+  g_err = "out of host memory";
+  return LF_ENOMEM;
 }
 
 static lf_status fail(lf_status st, const std::string& msg) {
@@ -184,7 +190,7 @@ void lf_params_default(lf_params* p) {
   p->capacity_hint = 0;
 }
 
-lf_status lf_ctx_create(int32_t device, void* hip_stream, lf_ctx** out) {
+lf_status lf_ctx_create(int32_t device, void* hip_stream, lf_ctx** out) try {
   if (!out) return fail(LF_EINVAL, "out is NULL");
   *out = nullptr;
   int n = 0;
@@ -205,14 +211,18 @@ lf_status lf_ctx_create(int32_t device, void* hip_stream, lf_ctx** out) {
   }
   *out = c;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_ctx_destroy(lf_ctx* c) {
+lf_status lf_ctx_destroy(lf_ctx* c) try {
   if (!c) return LF_OK;
   hipSetDevice(c->device);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 }  // extern "C"
@@ -329,12 +339,14 @@ lf_status mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* 
 extern "C" {
 
 lf_status lf_mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* F, int32_t n_f,
-                         int32_t op, lf_mesh** out) {
+                         int32_t op, lf_mesh** out) try {
   const int32_t part[2] = {0, n_v};
   return mesh_create(ctx, V, n_v, F, n_f, op, part, 1, out);
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_mesh_destroy(lf_mesh* m) {
+lf_status lf_mesh_destroy(lf_mesh* m) try {
   if (!m) return LF_OK;
   hipSetDevice(m->ctx->device);
   (void)hipFree(m->V);
@@ -350,10 +362,12 @@ lf_status lf_mesh_destroy(lf_mesh* m) {
   (void)hipFree(m->sldiag);
   delete m;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_mesh_operator(lf_mesh* m, int64_t* nnz, int32_t* rowptr, int32_t* col, float* val,
-                           int32_t is_dev) {
+                           int32_t is_dev) try {
   if (!m || !nnz) return fail(LF_EINVAL, "NULL argument");
   const int64_t total = m->nnz_off + m->n_v;
   *nnz = total;
@@ -377,6 +391,8 @@ lf_status lf_mesh_operator(lf_mesh* m, int64_t* nnz, int32_t* rowptr, int32_t* c
   LF_HIP(hipMemcpyAsync(val, dv.p, sizeof(float) * total, hipMemcpyDeviceToHost, s));
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 static lf_status check_seeds(const int32_t* seeds, int32_t n_s, int32_t n_v) {
@@ -414,7 +430,7 @@ static lf_status init_fields(lf_fields* f) {
   return LF_OK;
 }
 
-lf_status lf_fields_destroy(lf_fields* f) {
+lf_status lf_fields_destroy(lf_fields* f) try {
   if (!f) return LF_OK;
   (void)hipSetDevice(f->mesh->ctx->device);
   for (int k = 0; k < 2; ++k) {
@@ -441,6 +457,8 @@ lf_status lf_fields_destroy(lf_fields* f) {
   dual_release(f);
   delete f;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 // owner of every vertex (region id, n_s outside all regions) and the first
@@ -472,27 +490,31 @@ static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const
                             std::vector<int32_t>&& region_owner, lf_fields** out);
 
 lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const lf_params* P,
-                           lf_fields** out) {
+                           lf_fields** out) try {
   if (!m || !out) return fail(LF_EINVAL, "NULL argument");
   *out = nullptr;
   lf_status st = check_seeds(seeds, n_s, m->n_v);
   if (st) return st;
   return fields_new(m, seeds, n_s, P, std::vector<int32_t>(), out);
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_fields_create_regions(lf_mesh* m, const int32_t* region_ptr,
                                    const int32_t* region_vertices, int32_t n_s, const lf_params* P,
-                                   lf_fields** out) {
+                                   lf_fields** out) try {
   if (!m || !out) return fail(LF_EINVAL, "NULL argument");
   *out = nullptr;
   std::vector<int32_t> owner, first;
   lf_status st = check_regions(region_ptr, region_vertices, n_s, m->n_v, owner, first);
   if (st) return st;
   return fields_new(m, first.data(), n_s, P, std::move(owner), out);
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_fields_reset_regions(lf_fields* f, const int32_t* region_ptr,
-                                  const int32_t* region_vertices) {
+                                  const int32_t* region_vertices) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   std::vector<int32_t> owner, first;
   lf_status st = check_regions(region_ptr, region_vertices, f->n_s, f->mesh->n_v, owner, first);
@@ -501,6 +523,8 @@ lf_status lf_fields_reset_regions(lf_fields* f, const int32_t* region_ptr,
   f->seeds = std::move(first);
   f->region_owner = std::move(owner);
   return init_fields(f);
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 }  // extern "C"
@@ -561,7 +585,7 @@ static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const
 
 extern "C" {
 
-lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds) {
+lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   lf_status st = check_seeds(seeds, f->n_s, f->mesh->n_v);
   if (st) return st;
@@ -569,12 +593,16 @@ lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds) {
   f->seeds.assign(seeds, seeds + f->n_s);
   f->region_owner.clear();
   return init_fields(f);
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds) {
+lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds) try {
   if (!f || !seeds) return fail(LF_EINVAL, "NULL argument");
   memcpy(seeds, f->seeds.data(), sizeof(int32_t) * f->n_s);
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 static hipEvent_t pool_event(std::vector<hipEvent_t>& pool, size_t k) {
@@ -713,18 +741,26 @@ bool chunk_quiet(const lf_fields* f, int64_t n, double eps) {
 extern "C" {
 
 lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_t* layer_types,
-                                     const double* table) {
+                                     const double* table) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   if (n_types < 0 || n_types > 65536) return fail(LF_EINVAL, "n_types out of range");
   if (n_types > 0 && (!layer_types || !table)) return fail(LF_EINVAL, "NULL argument");
   const int64_t n_r = (int64_t)f->n_s + 1, n_pairs = (int64_t)n_types * n_types;
-  std::vector<float4> tab((size_t)n_pairs);
   for (int64_t l = 0; n_types > 0 && l < n_r; ++l)
     if (layer_types[l] < 0 || layer_types[l] >= n_types) return fail(LF_EINVAL, "layer type out of range");
+  std::vector<float4> tab;
+  try {
+    tab.resize((size_t)n_pairs);
+  } catch (const std::bad_alloc&) {
+    return fail(LF_ENOMEM, "coefficient table does not fit in host memory");
+  }
   for (int64_t q = 0; q < n_pairs; ++q) {
-    for (int k = 0; k < 3; ++k)
-      if (!std::isfinite(table[3 * q + k])) return fail(LF_EINVAL, "non-finite coefficient");
-    tab[(size_t)q] = make_float4((float)table[3 * q], (float)table[3 * q + 1], (float)table[3 * q + 2], 0.f);
+    float v[3];
+    for (int k = 0; k < 3; ++k) {
+      v[k] = (float)table[3 * q + k];
+      if (!std::isfinite(v[k])) return fail(LF_EINVAL, "coefficient not finite in float32");
+    }
+    tab[(size_t)q] = make_float4(v[0], v[1], v[2], 0.f);
   }
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   hipStream_t s = f->mesh->ctx->stream;
@@ -752,17 +788,21 @@ lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_
   f->coef = coef;
   f->n_types = n_types;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta) {
+lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   if (changed_rows) *changed_rows = (int64_t)f->last_changed;
   if (max_delta) *max_delta = (double)f->last_dmax;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t check_every,
-                        int64_t* steps_done, int64_t* converged_at) {
+                        int64_t* steps_done, int64_t* converged_at) try {
   if (!f || max_steps < 0 || check_every < 1 || check_every > kMaxChunk || !(eps >= 0))
     return fail(LF_EINVAL, "invalid argument");
   int64_t done = 0, conv = 0;
@@ -793,9 +833,11 @@ lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t che
   if (steps_done) *steps_done = done;
   if (converged_at) *converged_at = conv;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_step(lf_fields* f, int32_t n) {
+lf_status lf_step(lf_fields* f, int32_t n) try {
   if (!f || n < 0) return fail(LF_EINVAL, "invalid argument");
   int64_t left = n;
   int grows = 0;
@@ -812,16 +854,20 @@ lf_status lf_step(lf_fields* f, int32_t n) {
     if (rem > 0 && ++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
   }
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_sync(lf_fields* f) {
+lf_status lf_sync(lf_fields* f) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   LF_HIP(hipStreamSynchronize(f->mesh->ctx->stream));
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_fields_export(lf_fields* f, int64_t* nnz, int32_t* rowptr, int32_t* col, float* val,
-                           int32_t is_dev) {
+                           int32_t is_dev) try {
   if (!f || !nnz) return fail(LF_EINVAL, "NULL argument");
   *nnz = f->nnz;
   if (!rowptr && !col && !val) return LF_OK;
@@ -850,10 +896,12 @@ lf_status lf_fields_export(lf_fields* f, int64_t* nnz, int32_t* rowptr, int32_t*
   }
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, const int32_t* col,
-                           const float* val, int32_t is_dev) {
+                           const float* val, int32_t is_dev) try {
   if (!f || !rowptr || (nnz > 0 && (!col || !val)) || nnz < 0)
     return fail(LF_EINVAL, "invalid argument");
   if (nnz > (1ll << 31) - 1) return fail(LF_EINVAL, "more than 2^31 entries");
@@ -912,9 +960,11 @@ lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, con
   if (st) return st;
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_dev) {
+lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_dev) try {
   if (!f || !labels) return fail(LF_EINVAL, "NULL argument");
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   hipStream_t s = f->mesh->ctx->stream;
@@ -935,10 +985,12 @@ lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_dev) {
   }
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skel, int64_t* steps, int64_t* empty,
-                   int64_t* grows) {
+                   int64_t* grows) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   if (nnz_u) *nnz_u = f->nnz;
@@ -947,16 +999,20 @@ lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skel, int64_t* steps, 
   if (empty) *empty = (int64_t)f->events_total;
   if (grows) *grows = f->grow_events;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out) {
+lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   if (entries_in) *entries_in = (int64_t)f->in_total;
   if (entries_out) *entries_out = (int64_t)f->out_total;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t* launches) {
+lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t* launches) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
   if (total_ms) *total_ms = f->timed_ms;
   if (launches) *launches = f->timed_launches;
@@ -969,6 +1025,8 @@ lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t
     f->timing = enable;
   }
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 }  // extern "C"

@@ -3,6 +3,7 @@
 // shared base layer (see lf.h).
 #include <string.h>
 
+#include <new>
 #include <string>
 #include <vector>
 
@@ -70,7 +71,7 @@ extern "C" {
 lf_status lf_batch_create(lf_ctx* ctx, int32_t n, const double* const* V, const int32_t* n_v,
                           const int32_t* const* F, const int32_t* n_f, int32_t op,
                           const int32_t* const* seeds, const int32_t* n_s, const lf_params* P,
-                          lf_batch** out) {
+                          lf_batch** out) try {
   if (!ctx || n < 1 || !V || !n_v || !F || !n_f || !seeds || !n_s || !out)
     return bfail(LF_EINVAL, "invalid argument");
   *out = nullptr;
@@ -132,24 +133,30 @@ lf_status lf_batch_create(lf_ctx* ctx, int32_t n, const double* const* V, const 
   }
   *out = b;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_batch_destroy(lf_batch* b) {
+lf_status lf_batch_destroy(lf_batch* b) try {
   if (!b) return LF_OK;
   lf_fields_destroy(b->fields);
   lf_mesh_destroy(b->mesh);
   delete b;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_batch_fields(lf_batch* b, lf_fields** f) {
+lf_status lf_batch_fields(lf_batch* b, lf_fields** f) try {
   if (!b || !f) return bfail(LF_EINVAL, "NULL argument");
   *f = b->fields;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_batch_export(lf_batch* b, int32_t m, int64_t* nnz, int32_t* rowptr, int32_t* col,
-                          float* val) {
+                          float* val) try {
   if (!b || !nnz || m < 0 || m >= b->n) return bfail(LF_EINVAL, "invalid argument");
   lf_fields* f = b->fields;
   LF_HIP(hipSetDevice(b->ctx->device));
@@ -180,9 +187,11 @@ lf_status lf_batch_export(lf_batch* b, int32_t m, int64_t* nnz, int32_t* rowptr,
   }
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_batch_labels(lf_batch* b, int32_t m, int32_t* labels) {
+lf_status lf_batch_labels(lf_batch* b, int32_t m, int32_t* labels) try {
   if (!b || !labels || m < 0 || m >= b->n) return bfail(LF_EINVAL, "invalid argument");
   lf_fields* f = b->fields;
   LF_HIP(hipSetDevice(b->ctx->device));
@@ -202,6 +211,8 @@ lf_status lf_batch_labels(lf_batch* b, int32_t m, int32_t* labels) {
   LF_HIP(hipMemcpyAsync(labels, part.p, sizeof(int32_t) * nr, hipMemcpyDeviceToHost, s));
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 }  // extern "C"

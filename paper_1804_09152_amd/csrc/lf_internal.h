@@ -115,6 +115,9 @@ struct StepArgs {
 // error handling -----------------------------------------------------------
 void set_error(const std::string& msg);
 lf_status hip_fail(hipError_t e, const char* what);
+// a host allocation failed inside an entry point: LF_ENOMEM, nothing thrown
+// across the C ABI
+lf_status host_oom();
 #define LF_HIP(call)                                       \
   do {                                                     \
     hipError_t e_ = (call);                                \

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -938,7 +939,7 @@ using namespace lf;
 
 extern "C" {
 
-lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out) {
+lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out) try {
   if (!f || !seeds_out) return fail(LF_EINVAL, "NULL argument");
   lf_mesh* m = f->mesh;
   LF_HIP(hipSetDevice(m->ctx->device));
@@ -1008,9 +1009,11 @@ lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out)
     LF_HIP(hipMemcpyAsync(status_out, status.p, sizeof(int32_t) * n_s, hipMemcpyDeviceToHost, s));
   LF_HIP(hipStreamSynchronize(s));
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_lloyd(lf_fields* f, int32_t rounds, int32_t steps_per_round, int32_t* seeds_out) {
+lf_status lf_lloyd(lf_fields* f, int32_t rounds, int32_t steps_per_round, int32_t* seeds_out) try {
   if (!f || rounds < 0 || steps_per_round < 0) return fail(LF_EINVAL, "invalid argument");
   std::vector<int32_t> seeds((size_t)f->n_s);
   for (int32_t r = 0; r < rounds; ++r) {
@@ -1021,10 +1024,12 @@ lf_status lf_lloyd(lf_fields* f, int32_t rounds, int32_t steps_per_round, int32_
   }
   if (seeds_out) return lf_fields_seeds(f, seeds_out);
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, int64_t* adj_nnz,
-                       int32_t* adj_rowptr, int32_t* adj_col) {
+                       int32_t* adj_rowptr, int32_t* adj_col) try {
   if (!f || !n_tri || !adj_nnz) return fail(LF_EINVAL, "NULL argument");
   if (!(tau > 0.0 && tau <= 1.0)) return fail(LF_EINVAL, "tau must be in (0, 1]");
   lf_mesh* m = f->mesh;
@@ -1246,9 +1251,11 @@ lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, 
   if (adj_rowptr) memcpy(adj_rowptr, d->ad_rp.data(), sizeof(int32_t) * d->ad_rp.size());
   if (adj_col) memcpy(adj_col, d->ad_col.data(), sizeof(int32_t) * d->ad_col.size());
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_dual_matrix(lf_fields* f, int32_t which, int64_t* nnz, int32_t* rowptr, int32_t* col) {
+lf_status lf_dual_matrix(lf_fields* f, int32_t which, int64_t* nnz, int32_t* rowptr, int32_t* col) try {
   if (!f || !nnz || (which != 0 && which != 1)) return fail(LF_EINVAL, "invalid argument");
   if (!f->dual) return fail(LF_EINVAL, "no dual mesh computed yet");
   const std::vector<int32_t>& rp = which == 0 ? f->dual->av_rp : f->dual->at_rp;
@@ -1257,15 +1264,19 @@ lf_status lf_dual_matrix(lf_fields* f, int32_t which, int64_t* nnz, int32_t* row
   if (rowptr) memcpy(rowptr, rp.data(), sizeof(int32_t) * rp.size());
   if (col) memcpy(col, c.data(), sizeof(int32_t) * c.size());
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_dual_candidates(lf_fields* f, int64_t* n_cand, int32_t* pairs, int32_t* state) {
+lf_status lf_dual_candidates(lf_fields* f, int64_t* n_cand, int32_t* pairs, int32_t* state) try {
   if (!f || !n_cand) return fail(LF_EINVAL, "invalid argument");
   if (!f->dual) return fail(LF_EINVAL, "no dual mesh computed yet");
   *n_cand = (int64_t)f->dual->cand_state.size();
   if (pairs) memcpy(pairs, f->dual->cand.data(), sizeof(int32_t) * f->dual->cand.size());
   if (state) memcpy(state, f->dual->cand_state.data(), sizeof(int32_t) * f->dual->cand_state.size());
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 }  // extern "C"

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <deque>
 #include <map>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -158,7 +159,7 @@ lf_status next_phase(lf_server* s, Job* j, bool* finished) {
 extern "C" {
 
 lf_status lf_server_create(int32_t device, int64_t budget, int32_t max_active, int32_t chunk,
-                           lf_server** out) {
+                           lf_server** out) try {
   if (!out || budget <= 0 || max_active < 1 || chunk < 1) return sfail(LF_EINVAL, "invalid argument");
   lf_server* s = new lf_server();
   s->device = device;
@@ -167,9 +168,11 @@ lf_status lf_server_create(int32_t device, int64_t budget, int32_t max_active, i
   s->chunk = chunk;
   *out = s;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_server_destroy(lf_server* s) {
+lf_status lf_server_destroy(lf_server* s) try {
   if (!s) return LF_OK;
   for (auto& kv : s->jobs) {
     Job* j = kv.second;
@@ -182,9 +185,11 @@ lf_status lf_server_destroy(lf_server* s) {
   }
   delete s;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id) {
+lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id) try {
   if (!s || !job || !id || !job->V || !job->F || !job->seeds || job->n_v < 3 || job->n_f < 1 ||
       job->n_s < 1 || job->steps < 0 || job->lloyd_rounds < 0 || job->conv_eps < 0 ||
       (job->conv_eps > 0 && job->conv_every < 1) || job->n_types < 0 || job->n_types > 65536 ||
@@ -198,10 +203,19 @@ lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id) {
     delete j;
     return sfail(LF_ENOMEM, "the job alone exceeds the HBM budget");
   }
+  try {
+    j->V.assign(job->V, job->V + 3ll * job->n_v);
+    j->F.assign(job->F, job->F + 3ll * job->n_f);
+    j->seeds.assign(job->seeds, job->seeds + job->n_s);
+    if (job->n_types > 0) {  // checked when the job is admitted
+      j->layer_types.assign(job->layer_types, job->layer_types + job->n_s + 1);
+      j->table.assign(job->table, job->table + 3ll * job->n_types * job->n_types);
+    }
+  } catch (const std::bad_alloc&) {
+    delete j;
+    return sfail(LF_ENOMEM, "the job's inputs do not fit in host memory");
+  }
   j->id = s->next_id++;
-  j->V.assign(job->V, job->V + 3ll * job->n_v);
-  j->F.assign(job->F, job->F + 3ll * job->n_f);
-  j->seeds.assign(job->seeds, job->seeds + job->n_s);
   j->n_v = job->n_v;
   j->n_f = job->n_f;
   j->n_s = job->n_s;
@@ -213,18 +227,16 @@ lf_status lf_server_submit(lf_server* s, const lf_job* job, int64_t* id) {
   j->conv_eps = job->conv_eps;
   j->conv_every = job->conv_every;
   j->n_types = job->n_types;
-  if (job->n_types > 0) {  // checked when the job is admitted
-    j->layer_types.assign(job->layer_types, job->layer_types + job->n_s + 1);
-    j->table.assign(job->table, job->table + 3ll * job->n_types * job->n_types);
-  }
   j->t_submit = now_ms();
   s->queue.push_back(j);
   s->jobs[j->id] = j;
   *id = j->id;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_server_poll(lf_server* s, int32_t* n_queued, int32_t* n_active, int32_t* n_done) {
+lf_status lf_server_poll(lf_server* s, int32_t* n_queued, int32_t* n_active, int32_t* n_done) try {
   if (!s) return sfail(LF_EINVAL, "NULL argument");
   // admission, in arrival order, while memory and slots allow
   while (!s->queue.empty() && (int32_t)s->active.size() < s->max_active &&
@@ -283,11 +295,13 @@ lf_status lf_server_poll(lf_server* s, int32_t* n_queued, int32_t* n_active, int
   if (n_active) *n_active = (int32_t)s->active.size();
   if (n_done) *n_done = s->n_done;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 lf_status lf_server_result(lf_server* s, int64_t id, int32_t* seeds, int32_t* labels,
                            int64_t* n_tri, int32_t* tris, double* latency_ms, double* queue_ms,
-                           int64_t* steps) {
+                           int64_t* steps) try {
   if (!s) return sfail(LF_EINVAL, "NULL argument");
   auto it = s->jobs.find(id);
   if (it == s->jobs.end()) return sfail(LF_EINVAL, "unknown job");
@@ -302,9 +316,11 @@ lf_status lf_server_result(lf_server* s, int64_t id, int32_t* seeds, int32_t* la
   if (queue_ms) *queue_ms = j->t_admit - j->t_submit;
   if (steps) *steps = j->steps_run;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_server_release(lf_server* s, int64_t id) {
+lf_status lf_server_release(lf_server* s, int64_t id) try {
   if (!s) return sfail(LF_EINVAL, "NULL argument");
   auto it = s->jobs.find(id);
   if (it == s->jobs.end()) return sfail(LF_EINVAL, "unknown job");
@@ -313,13 +329,17 @@ lf_status lf_server_release(lf_server* s, int64_t id) {
   delete j;
   s->jobs.erase(it);
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
-lf_status lf_server_memory(lf_server* s, int64_t* in_use, int64_t* peak) {
+lf_status lf_server_memory(lf_server* s, int64_t* in_use, int64_t* peak) try {
   if (!s) return sfail(LF_EINVAL, "NULL argument");
   if (in_use) *in_use = s->in_use;
   if (peak) *peak = s->peak;
   return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
 }
 
 }  // extern "C"

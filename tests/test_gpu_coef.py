@@ -205,6 +205,10 @@ def test_invalid_coefficients(lf):
         f.set_coefficients(np.zeros(n_r, np.int32), bad)
     with pytest.raises(lfb.LFError):
         f.set_coefficients(np.zeros(n_r, np.int32), np.zeros((2, 3, 3)))
+    huge = np.zeros((1, 1, 3))
+    huge[0, 0, 1] = 1e300  # finite in float64, not in float32
+    with pytest.raises(lfb.LFError):
+        f.set_coefficients(np.zeros(n_r, np.int32), huge)
     # a failed call leaves the scalar model in place
     g = lfb.Fields(m, seeds)
     f.step(10)
