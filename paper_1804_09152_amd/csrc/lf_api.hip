@@ -230,47 +230,20 @@ lf_status lf_ctx_destroy(lf_ctx* c) try {
 namespace lf {
 
 // spreads the low 21 bits of x to every third bit
-static uint64_t spread3(uint64_t x) {
-  x &= 0x1fffffull;
-  x = (x | (x << 32)) & 0x1f00000000ffffull;
-  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
-  x = (x | (x << 8)) & 0x100f00f00f00f00full;
-  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x << 2)) & 0x1249249249249249ull;
-  return x;
-}
-
-// Vertex order of the step: within each part [part_off[p], part_off[p+1]),
-// vertices sorted along a Morton (Z-order) curve of their positions, so
-// that a vertex's neighbours are mostly close to it in memory.
-static std::vector<int32_t> locality_order(const double* V, const int32_t* part_off,
-                                           int32_t n_parts) {
-  std::vector<int32_t> perm((size_t)part_off[n_parts]);
-  std::vector<std::pair<uint64_t, int32_t>> key;
+// bounding box of every part's vertices: box[6 p .. 6 p + 5] = lo xyz, hi xyz
+static std::vector<double> part_boxes(const double* V, const int32_t* part_off, int32_t n_parts) {
+  std::vector<double> box(6 * (size_t)n_parts);
   for (int32_t p = 0; p < n_parts; ++p) {
     const int32_t a = part_off[p], b = part_off[p + 1];
-    double lo[3] = {V[3ll * a], V[3ll * a + 1], V[3ll * a + 2]}, hi[3] = {lo[0], lo[1], lo[2]};
+    double* bx = box.data() + 6 * (size_t)p;
+    for (int d = 0; d < 3; ++d) bx[d] = bx[3 + d] = V[3ll * a + d];
     for (int32_t v = a; v < b; ++v)
       for (int d = 0; d < 3; ++d) {
-        lo[d] = std::min(lo[d], V[3ll * v + d]);
-        hi[d] = std::max(hi[d], V[3ll * v + d]);
+        bx[d] = std::min(bx[d], V[3ll * v + d]);
+        bx[3 + d] = std::max(bx[3 + d], V[3ll * v + d]);
       }
-    key.resize((size_t)(b - a));
-    for (int32_t v = a; v < b; ++v) {
-      uint64_t c = 0;
-      for (int d = 0; d < 3; ++d) {
-        const double span = hi[d] - lo[d];
-        double t = span > 0 ? (V[3ll * v + d] - lo[d]) / span : 0.0;
-        if (!(t >= 0.0)) t = 0.0;  // also NaN
-        if (t > 1.0) t = 1.0;
-        c |= spread3((uint64_t)(t * 2097151.0)) << d;
-      }
-      key[(size_t)(v - a)] = {c, v};
-    }
-    std::sort(key.begin(), key.end());
-    for (int32_t v = a; v < b; ++v) perm[(size_t)v] = key[(size_t)(v - a)].second;
   }
-  return perm;
+  return box;
 }
 
 lf_status mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* F, int32_t n_f,
@@ -313,23 +286,17 @@ lf_status mesh_create(lf_ctx* ctx, const double* V, int32_t n_v, const int32_t* 
     lf_mesh_destroy(m);
     return fail(LF_EINVAL, "zero-area face: cotangent weights undefined");
   }
-  // the step's vertex order and its copy of the operator
-  const std::vector<int32_t> perm = locality_order(V, part_off, n_parts);
-  std::vector<int32_t> inv((size_t)n_v);
-  for (int32_t k = 0; k < n_v; ++k) inv[(size_t)perm[(size_t)k]] = k;
+  // the step's vertex order (a Morton curve per part, sorted on the GPU) and
+  // its copy of the operator
+  const std::vector<double> box = part_boxes(V, part_off, n_parts);
   e = dalloc(&m->perm, n_v);
   if (e == hipSuccess) e = dalloc(&m->inv, n_v);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(m->perm, perm.data(), sizeof(int32_t) * n_v, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(m->inv, inv.data(), sizeof(int32_t) * n_v, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = locality_order(m->V, n_v, part_off, n_parts, box.data(), m->perm, m->inv, s);
   if (e == hipSuccess)
     e = permute_operator(m->lptr, m->lent, m->ldiag, m->perm, m->inv, n_v, m->nnz_off, &m->slptr,
                          &m->slent, &m->sldiag, s);
   if (e == hipSuccess) e = build_slices(m->slptr, m->slent, n_v, &m->lell, &m->op_w, s);
   if (e != hipSuccess) return bail(e, "operator in step order");
-  m->Vh.assign(V, V + 3ll * n_v);
-  m->Fh.assign(F, F + 3ll * n_f);
   *out = m;
   return LF_OK;
 }

@@ -166,6 +166,16 @@ hipError_t ell_to_csr_fill(const EllRow* u, const Ent* ovf, const int32_t* inv, 
 // entries)
 hipError_t csr_to_ell(const int32_t* uptr, const Ent* uent, const int32_t* inv, int32_t n_v,
                       EllRow* u, Ent* ovf, hipStream_t s);
+// sorts keys[0..n) ascending in place (bitonic network; keys has room for
+// the next power of two of n, padded with ~0)
+hipError_t sort_keys_u64(unsigned long long* keys, int64_t n, hipStream_t s);
+// The step's vertex order: within each part [part_off[p], part_off[p+1])
+// (host array), vertices sorted along a Morton curve of their positions in
+// the part's bounding box (host box[6 p .. 6 p + 5]: lo xyz, hi xyz), ties by
+// vertex id.  V is the device copy of the positions; perm (row -> vertex)
+// and inv (vertex -> row) are device arrays of n_v.
+hipError_t locality_order(const double* V, int32_t n_v, const int32_t* part_off, int32_t n_parts,
+                          const double* box, int32_t* perm, int32_t* inv, hipStream_t s);
 // the operator in the step's order (rows permuted, columns renumbered,
 // entries of a row in their original order)
 hipError_t permute_operator(const int32_t* lptr, const Ent* lent, const float* ldiag,
@@ -240,8 +250,6 @@ struct lf_mesh {
   lf::Ent* lell;    // the same off-diagonal entries in slices of kSlice rows
   int32_t op_w;     // their width
   int32_t n_slices;
-  std::vector<double> Vh;  // host copies for small host-side geometry needs
-  std::vector<int32_t> Fh;
   // largest face area and largest |coordinate| (the Lloyd sums' fixed-point
   // scale); measured on the first re-seeding, < 0 before
   double amax = -1.0, xmax = -1.0;

@@ -860,6 +860,10 @@ __global__ void k_orient_conflicts(const int32_t* otri, const int32_t* across, i
 
 }  // namespace
 
+hipError_t sort_keys_u64(unsigned long long* keys, int64_t n, hipStream_t s) {
+  return sort_u64(keys, n, s);
+}
+
 }  // namespace lf
 
 // ---- state kept for inspection ---------------------------------------------------

@@ -1,5 +1,7 @@
 // Setup-time kernels: mesh operator and its slices, field initialisation,
 // scans, conversions between the fixed-width field rows and CSR, labels.
+#include <algorithm>
+
 #include "lf_internal.h"
 
 namespace lf {
@@ -350,7 +352,92 @@ __global__ void k_labels(const int32_t* uptr, const Ent* uent, int32_t n_v, int3
   labels[i] = best;
 }
 
+// spreads the low 21 bits of x to every third bit
+__device__ __forceinline__ unsigned long long spread3(unsigned long long x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+constexpr int kIdBits = 25;  // vertex ids below 2^25
+
+// key of vertex v: its part (top part_bits bits), the interleaved positions
+// quantised to axis_bits bits per axis in the part's box, then v
+__global__ void k_morton_keys(const double* V, int32_t n_v, const int32_t* part_off,
+                              int32_t n_parts, const double* box, int part_bits, int axis_bits,
+                              unsigned long long* keys) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_v) return;
+  int32_t lo = 0, hi = n_parts;  // the part holding v: part_off[lo] <= v < part_off[lo + 1]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (part_off[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  const double* b = box + 6 * (int64_t)lo;
+  const double top = (double)((1u << axis_bits) - 1u);
+  unsigned long long code = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double ext = b[3 + k] - b[k];
+    double t = ext > 0.0 ? (V[3 * (int64_t)v + k] - b[k]) / ext : 0.0;
+    if (!(t >= 0.0)) t = 0.0;  // also NaN
+    if (t > 1.0) t = 1.0;
+    code |= spread3((unsigned long long)(t * top)) << k;
+  }
+  const unsigned long long part = part_bits ? (unsigned long long)lo << (64 - part_bits) : 0ull;
+  keys[v] = part | (code << kIdBits) | (unsigned long long)v;
+}
+
+__global__ void k_order_from_keys(const unsigned long long* keys, int32_t n_v, int32_t* perm,
+                                  int32_t* inv) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_v) return;
+  const int32_t v = (int32_t)(keys[k] & ((1ull << kIdBits) - 1ull));
+  perm[k] = v;
+  inv[v] = k;
+}
+
 }  // namespace
+
+hipError_t locality_order(const double* V, int32_t n_v, const int32_t* part_off, int32_t n_parts,
+                          const double* box, int32_t* perm, int32_t* inv, hipStream_t s) {
+  // 64 bits: part, 3 axes, vertex id
+  int part_bits = 0;
+  while ((1ll << part_bits) < n_parts) ++part_bits;
+  const int axis_bits = std::max(1, std::min(21, (64 - kIdBits - part_bits) / 3));
+  int64_t N = 1;
+  while (N < n_v) N <<= 1;
+  unsigned long long* keys = nullptr;
+  int32_t* d_off = nullptr;
+  double* d_box = nullptr;
+  hipError_t e = dalloc(&keys, N);
+  if (e == hipSuccess) e = dalloc(&d_off, (int64_t)n_parts + 1);
+  if (e == hipSuccess) e = dalloc(&d_box, 6ll * n_parts);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_off, part_off, sizeof(int32_t) * (n_parts + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_box, box, sizeof(double) * 6 * n_parts, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_morton_keys, dim3(blocks_for(n_v)), dim3(kT), 0, s, V, n_v, d_off, n_parts,
+                       d_box, part_bits, axis_bits, keys);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = sort_keys_u64(keys, n_v, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_order_from_keys, dim3(blocks_for(n_v)), dim3(kT), 0, s, keys, n_v, perm,
+                       inv);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // before the buffers are freed
+  (void)hipFree(keys);
+  (void)hipFree(d_off);
+  (void)hipFree(d_box);
+  return e;
+}
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n)), dim3(kT), 0, s, p, n, v);
