@@ -236,6 +236,7 @@ static std::vector<double> part_boxes(const double* V, const int32_t* part_off, 
   for (int32_t p = 0; p < n_parts; ++p) {
     const int32_t a = part_off[p], b = part_off[p + 1];
     double* bx = box.data() + 6 * (size_t)p;
+    if (a >= b) continue;  // an empty part keeps a zero box
     for (int d = 0; d < 3; ++d) bx[d] = bx[3 + d] = V[3ll * a + d];
     for (int32_t v = a; v < b; ++v)
       for (int d = 0; d < 3; ++d) {
