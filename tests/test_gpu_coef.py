@@ -249,3 +249,27 @@ def test_typed_server_job_equals_solo(lf):
         assert np.array_equal(r["labels"], f.labels())
         assert np.array_equal(r["tris"], f.dual_mesh(0.25)[0])
     S.close()
+
+
+def test_typed_full_size_c3_one_step(lf, orc):
+    """Per-pair coefficients at the roofline workload's full size (icosphere
+    level 9, 2,621,442 vertices, 16,384 cells, 16 types): one step from a
+    synthetic mid-run state, every row against the oracle."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c3()
+    rng = np.random.default_rng(16)
+    types = rng.integers(0, 16, seeds.size + 1).astype(np.int32)
+    tab = _table(rng, 16)
+    P = orc.default_params(types=types, table=tab)
+    say("typed c3")
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    L = orc.operator(mesh.V, mesh.F, 1)
+    U = f32(I.synthetic_state(mesh, seeds, np.random.default_rng(0), k=3))
+    f = lfb.Fields(m, seeds)
+    f.set_coefficients(types, tab)
+    gpu_load(f, U)
+    f.step(1)
+    G = as_oracle(f.export())
+    O, info = orc.step(L, U, seeds.size, P, want_info=True)
+    r = check_step(G, O, info["margin"], what="typed c3")
+    say("typed c3", r)
