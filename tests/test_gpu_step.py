@@ -369,3 +369,29 @@ def test_invalid_inputs(lf):
     after = f.export()
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
+
+
+def test_full_size_c3_invariants(lf):
+    """Properties of the update that hold at any size, on the roofline
+    workload after 500 free steps: values in (0, 1], at least theta; every
+    row's sum within n theta of 1 (normalised, then entries below theta
+    dropped); no empty row; layers ascending; counters consistent."""
+    lfb, ctx = lf
+    mesh, seeds = I.config_c3()
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    f = lfb.Fields(m, seeds)
+    say("c3 500 steps")
+    f.step(500)
+    rp, col, val = f.export()
+    theta = 1e-3
+    n = np.diff(rp)
+    assert n.min() >= 1
+    assert val.min() >= np.float32(theta) and val.max() <= 1.0
+    sums = np.add.reduceat(val.astype(np.float64), rp[:-1])
+    assert np.all(sums <= 1.0 + 1e-5) and np.all(sums >= 1.0 - n * theta - 1e-5)
+    d = np.diff(col.astype(np.int64))
+    row_start = np.zeros(col.size, bool)
+    row_start[rp[:-1]] = True
+    assert np.all(d[~row_start[1:]] > 0)  # ascending within every row
+    st = f.stats()
+    assert st["steps"] == 500 and st["empty_columns"] == 0 and st["nnz"] == col.size
