@@ -374,8 +374,9 @@ def test_invalid_inputs(lf):
 def test_full_size_c3_invariants(lf):
     """Properties of the update that hold at any size, on the roofline
     workload after 500 free steps: values in (0, 1], at least theta; every
-    row's sum within n theta of 1 (normalised, then entries below theta
-    dropped); no empty row; layers ascending; counters consistent."""
+    row's sum at most 1 and above 1 - 64 theta (normalised, then fewer than
+    64 entries below theta dropped); no empty row; layers ascending; counters
+    consistent."""
     lfb, ctx = lf
     mesh, seeds = I.config_c3()
     m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
@@ -388,7 +389,7 @@ def test_full_size_c3_invariants(lf):
     assert n.min() >= 1
     assert val.min() >= np.float32(theta) and val.max() <= 1.0
     sums = np.add.reduceat(val.astype(np.float64), rp[:-1])
-    assert np.all(sums <= 1.0 + 1e-5) and np.all(sums >= 1.0 - n * theta - 1e-5)
+    assert np.all(sums <= 1.0 + 1e-5) and np.all(sums > 1.0 - 64 * theta - 1e-5)
     d = np.diff(col.astype(np.int64))
     row_start = np.zeros(col.size, bool)
     row_start[rp[:-1]] = True
