@@ -667,16 +667,12 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int per = (A.n_slices + kXcds - 1) / kXcds;
   const int sl = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
   if (sl >= A.n_slices) return;
-  // An earlier step of the chunk failed: write nothing, so that the last
-  // good fields (the input of the failed step, which this step would
-  // overwrite) survive for the replay.  The flag is set by atomics in an
-  // earlier launch; a scalar load sees it (caches are made coherent between
-  // launches) and costs no vector-memory round trip.
-  if (*(const __attribute__((address_space(4))) unsigned int*)&A.flags->poisoned) return;
-  if (sl == 0 && lane == 0) {
-    *A.ovf_ctr_next = 0u;
-    *A.wide_ctr_next = 0u;
-  }
+  // Whether an earlier step of the chunk failed: the flag is set by atomics
+  // in an earlier launch, and a scalar load sees it (caches are made
+  // coherent between launches).  It is loaded here and tested after the
+  // gather, which only reads, so that its latency overlaps the first loads.
+  const unsigned poisoned =
+      *(const __attribute__((address_space(4))) unsigned int*)&A.flags->poisoned;
   const int i = sl * kSlice + lane;
 
   RowBuf<kRowRegs> r;
@@ -692,6 +688,15 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
     int g = gather_regs(r, cnt, n_in, i, ops, A);
     if (g == kGatherOvf) g = gather_slow(r, cnt, i, ops, A);
     in_regs = g == kGatherOk;
+  }
+  // An earlier step of the chunk failed: write nothing (no row, no overflow
+  // entry, no workspace slot, no counter), so that the last good fields (the
+  // input of the failed step, which this step would overwrite) survive for
+  // the replay.
+  if (poisoned) return;
+  if (sl == 0 && lane == 0) {
+    *A.ovf_ctr_next = 0u;
+    *A.wide_ctr_next = 0u;
   }
   if (i < A.n_v) {
     if (in_regs) {
