@@ -132,3 +132,24 @@ def test_server_equals_solo(lf, max_active, budget_mb, chunk):
         assert r["latency_ms"] >= r["queue_ms"] >= 0
         S.release(i)
     S.close()
+
+
+def test_full_size_c4_batch_equals_solo(lf):
+    """The benchmark's batch at full size (256 torus grids, 6.1 M vertices,
+    graph operator, 500 steps): eight meshes spread over the batch, from the
+    smallest to the largest, are bit-identical to their solo runs."""
+    lfb, ctx = lf
+    items = I.batch_tori(256)
+    say("c4 batch", sum(m.n_v for m, _ in items), "vertices")
+    B = lfb.Batch(ctx, [(m.V, m.F) for m, _ in items], 0, [s for _, s in items])
+    B.step(500)
+    order = np.argsort([m.n_v for m, _ in items])
+    pick = sorted(set(int(order[k]) for k in np.linspace(0, len(items) - 1, 8).round().astype(int)))
+    for k in pick:
+        mesh, seeds = items[k]
+        M, f = _solo_fields(lfb, ctx, mesh, seeds, 0, None, 500)
+        assert _same_csr(B.export(k), f.export()), f"mesh {k} ({mesh.n_v} vertices) differs"
+        assert np.array_equal(B.labels(k), f.labels())
+        f.close()
+        M.close()
+    B.close()
