@@ -894,7 +894,11 @@ struct Buf {
   ~Buf() {
     if (p) hipFree(p);
   }
-  hipError_t alloc(int64_t n) { return dalloc(&p, n); }
+  hipError_t alloc(int64_t n) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    return dalloc(&p, n);
+  }
 };
 
 template <class T>
@@ -1059,32 +1063,40 @@ lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, 
   }
   const int64_t nmax = std::max<int64_t>(n_v, n_f);
 
-  // A_v and A_t as hash sets of cell pairs
+  // A_v and A_t as hash sets of cell pairs.  A cell meets a handful of
+  // others, so the tables start at 16 slots per cell (a low load for any
+  // ordinary partition); a table that fills up (bit 1) is sized again from
+  // the exact number of pair incidences, which always suffices.
   Buf<unsigned long long> counts, tv, tt, kv, kt;
   Buf<int> ovf;
-  LF_HIP(counts.alloc(2));
   LF_HIP(ovf.alloc(1));
-  LF_HIP(hipMemsetAsync(counts.p, 0, 2 * sizeof(unsigned long long), s));
-  LF_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_dual_count, dim3(nblk(nmax)), dim3(kT), 0, s, m->F, n_f, n_v, uptr, uent, n_s,
-                     ftau, counts.p);
-  LF_HIP(hipGetLastError());
-  unsigned long long hc[2];
-  LF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
-  LF_HIP(hipStreamSynchronize(s));
-  const int64_t cap_v = pow2_at_least(std::max<int64_t>(1024, 2 * (int64_t)hc[0]));
-  const int64_t cap_t = pow2_at_least(std::max<int64_t>(1024, 2 * (int64_t)hc[1]));
-  LF_HIP(tv.alloc(cap_v));
-  LF_HIP(tt.alloc(cap_t));
-  hipLaunchKernelGGL(k_fill64, dim3(nblk(cap_v)), dim3(kT), 0, s, tv.p, cap_v, kEmpty);
-  hipLaunchKernelGGL(k_fill64, dim3(nblk(cap_t)), dim3(kT), 0, s, tt.p, cap_t, kEmpty);
-  hipLaunchKernelGGL(k_dual_pairs, dim3(nblk(nmax)), dim3(kT), 0, s, m->F, n_f, n_v, uptr, uent, n_s,
-                     ftau, tv.p, cap_v, tt.p, cap_t, ovf.p);
-  LF_HIP(hipGetLastError());
-  int hov = 0;
-  LF_HIP(hipMemcpyAsync(&hov, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  LF_HIP(hipStreamSynchronize(s));
-  if (hov) return fail(LF_ECAPACITY, "more than 32 cells above tau on one face");
+  int64_t cap_v = pow2_at_least(std::max<int64_t>(1024, 16ll * n_s)), cap_t = cap_v;
+  for (int attempt = 0;; ++attempt) {
+    LF_HIP(tv.alloc(cap_v));
+    LF_HIP(tt.alloc(cap_t));
+    LF_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_fill64, dim3(nblk(cap_v)), dim3(kT), 0, s, tv.p, cap_v, kEmpty);
+    hipLaunchKernelGGL(k_fill64, dim3(nblk(cap_t)), dim3(kT), 0, s, tt.p, cap_t, kEmpty);
+    hipLaunchKernelGGL(k_dual_pairs, dim3(nblk(nmax)), dim3(kT), 0, s, m->F, n_f, n_v, uptr, uent,
+                       n_s, ftau, tv.p, cap_v, tt.p, cap_t, ovf.p);
+    LF_HIP(hipGetLastError());
+    int hov = 0;
+    LF_HIP(hipMemcpyAsync(&hov, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipStreamSynchronize(s));
+    if (hov & 2) return fail(LF_ECAPACITY, "more than 32 cells above tau on one face");
+    if (!(hov & 1)) break;
+    if (attempt > 0) return fail(LF_ECAPACITY, "cell-pair tables overflowed");
+    LF_HIP(counts.alloc(2));
+    LF_HIP(hipMemsetAsync(counts.p, 0, 2 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_dual_count, dim3(nblk(nmax)), dim3(kT), 0, s, m->F, n_f, n_v, uptr, uent,
+                       n_s, ftau, counts.p);
+    LF_HIP(hipGetLastError());
+    unsigned long long hc[2];
+    LF_HIP(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+    LF_HIP(hipStreamSynchronize(s));
+    cap_v = pow2_at_least(std::max<int64_t>(1024, 2 * (int64_t)hc[0]));
+    cap_t = pow2_at_least(std::max<int64_t>(1024, 2 * (int64_t)hc[1]));
+  }
   int64_t nv = 0, nt = 0;
   lf_status st = set_to_sorted(tv.p, cap_v, kv, &nv, s);
   if (st) return st;
