@@ -325,12 +325,22 @@ __device__ __forceinline__ bool line_hit(Vec3 o, Vec3 d, Vec3 p0, Vec3 p1, Vec3 
   return u >= 0.0 && v >= 0.0 && 1.0 - u - v >= 0.0;
 }
 
-// pass 0: smallest |s| per cell; pass 1: lowest face id among the hits at it
+// a hit of a cell's line on one of its faces
+struct HitRec {
+  unsigned long long key;  // |s| as bits (non-negative doubles order like their bits)
+  int32_t cell, face;
+};
+
+// pass 0: smallest |s| per cell, and every hit appended to `hits` (while it
+// has room); pass 1: lowest face id among the hits at the smallest |s|, by a
+// second walk over all faces, needed only when the list overflowed
 __global__ void k_lloyd_hits(const double* V, const int32_t* F, int32_t n_f, const int32_t* uptr,
                              const Ent* uent, int32_t n_s, const CellLine* lines,
-                             unsigned long long* best_s, int32_t* best_f, int pass) {
+                             unsigned long long* best_s, int32_t* best_f, int pass, HitRec* hits,
+                             unsigned int* n_hits, int64_t hit_cap) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= n_f) return;
+  if (pass == 1 && (int64_t)*n_hits <= hit_cap) return;  // the list holds every hit
   const Vec3 p0 = vload(V, F[3 * (int64_t)f]), p1 = vload(V, F[3 * (int64_t)f + 1]),
              p2 = vload(V, F[3 * (int64_t)f + 2]);
   face_cells(F, f, uptr, uent, n_s, 0.f, false, [&](int32_t cell) {
@@ -339,9 +349,24 @@ __global__ void k_lloyd_hits(const double* V, const int32_t* F, int32_t n_f, con
     double s = 0.0;
     if (!line_hit(L.ctr, L.dir, p0, p1, p2, &s)) return;
     const unsigned long long key = (unsigned long long)__double_as_longlong(fabs(s));
-    if (pass == 0) atomicMin(&best_s[cell], key);
-    else if (key == best_s[cell]) atomicMin(&best_f[cell], f);
+    if (pass == 0) {
+      atomicMin(&best_s[cell], key);
+      const unsigned int at = atomicAdd(n_hits, 1u);
+      if ((int64_t)at < hit_cap) hits[at] = HitRec{key, cell, f};
+    } else if (key == best_s[cell]) {
+      atomicMin(&best_f[cell], f);
+    }
   });
+}
+
+// pass 1 from the list of hits (when it holds them all)
+__global__ void k_lloyd_hit_faces(const HitRec* hits, const unsigned int* n_hits, int64_t hit_cap,
+                                  const unsigned long long* best_s, int32_t* best_f) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)*n_hits;
+  if (n > hit_cap || k >= n) return;
+  const HitRec h = hits[k];
+  if (h.key == best_s[h.cell]) atomicMin(&best_f[h.cell], h.face);
 }
 
 // the hit face's vertex nearest the hit point becomes the candidate seed
@@ -994,9 +1019,21 @@ lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out)
                      scale, acc.p);
   hipLaunchKernelGGL(k_lloyd_lines, dim3(nblk(n_s)), dim3(kT), 0, s, acc.p, n_s, scale, lines.p,
                      best_s.p, best_f.p);
-  for (int pass = 0; pass < 2; ++pass)
+  // hits are few (a handful per cell): the second pass walks their list,
+  // and the walk over all faces runs only if the list overflowed
+  const int64_t hit_cap = 8ll * n_s + 4096;
+  Buf<HitRec> hits;
+  Buf<unsigned int> n_hits;
+  LF_HIP(hits.alloc(hit_cap));
+  LF_HIP(n_hits.alloc(1));
+  LF_HIP(hipMemsetAsync(n_hits.p, 0, sizeof(unsigned int), s));
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1)
+      hipLaunchKernelGGL(k_lloyd_hit_faces, dim3(nblk(hit_cap)), dim3(kT), 0, s, hits.p, n_hits.p,
+                         hit_cap, best_s.p, best_f.p);
     hipLaunchKernelGGL(k_lloyd_hits, dim3(nblk(n_f)), dim3(kT), 0, s, m->V, m->F, n_f, uptr, uent,
-                       n_s, lines.p, best_s.p, best_f.p, pass);
+                       n_s, lines.p, best_s.p, best_f.p, pass, hits.p, n_hits.p, hit_cap);
+  }
   hipLaunchKernelGGL(k_lloyd_pick, dim3(nblk(n_s)), dim3(kT), 0, s, m->V, m->F, n_s, lines.p,
                      best_f.p, old.p, cand.p, status.p);
   LF_HIP(hipGetLastError());
