@@ -5,6 +5,7 @@
 // fixed point (integer atomics are order independent), minima use integer
 // atomics on order-preserving keys, and sets of cell pairs are built in hash
 // tables and then sorted.
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -926,6 +927,14 @@ struct Buf {
   }
 };
 
+// LF_TEST_SMALL_TABLES=1 starts the growable tables of the post-processing
+// (cell-pair sets, the list of line hits) with tiny capacities, so that a
+// test can run their fallback paths on ordinary inputs
+bool small_tables() {
+  const char* e = getenv("LF_TEST_SMALL_TABLES");
+  return e && e[0] == '1';
+}
+
 template <class T>
 hipError_t to_host(std::vector<T>& v, const T* d, int64_t n, hipStream_t s) {
   v.resize((size_t)std::max<int64_t>(n, 0));
@@ -1021,7 +1030,7 @@ lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out)
                      best_s.p, best_f.p);
   // hits are few (a handful per cell): the second pass walks their list,
   // and the walk over all faces runs only if the list overflowed
-  const int64_t hit_cap = 8ll * n_s + 4096;
+  const int64_t hit_cap = small_tables() ? 1 : 8ll * n_s + 4096;
   Buf<HitRec> hits;
   Buf<unsigned int> n_hits;
   LF_HIP(hits.alloc(hit_cap));
@@ -1107,7 +1116,8 @@ lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, 
   Buf<unsigned long long> counts, tv, tt, kv, kt;
   Buf<int> ovf;
   LF_HIP(ovf.alloc(1));
-  int64_t cap_v = pow2_at_least(std::max<int64_t>(1024, 16ll * n_s)), cap_t = cap_v;
+  int64_t cap_v = small_tables() ? 16 : pow2_at_least(std::max<int64_t>(1024, 16ll * n_s));
+  int64_t cap_t = cap_v;
   for (int attempt = 0;; ++attempt) {
     LF_HIP(tv.alloc(cap_v));
     LF_HIP(tt.alloc(cap_t));

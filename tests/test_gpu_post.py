@@ -206,3 +206,29 @@ def test_lloyd_rounds_even_out_cells(lf):
     s5 = spread()
     say(f"cell size spread {s0:.3f} -> {s5:.3f}")
     assert s5 < 0.7 * s0, (s0, s5)
+
+
+def test_small_table_fallbacks_match(lf):
+    """The post-processing's growable tables (cell-pair sets of the dual mesh,
+    the list of line hits of the re-seeding) start with tiny capacities under
+    LF_TEST_SMALL_TABLES=1, which runs their fallback paths (exact-count
+    resizing, the walk over every face); results must not change."""
+    import os
+    lfb, ctx = lf
+    mesh, seeds = I.config_c2(level=5, n_seeds=64, seed=3)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    say("small-table fallbacks")
+    out = []
+    for small in (False, True):
+        os.environ["LF_TEST_SMALL_TABLES"] = "1" if small else "0"
+        try:
+            f = lfb.Fields(m, seeds)
+            f.step(200)
+            s, st = f.lloyd_reseed()
+            tris, (rp, col) = f.dual_mesh(0.25)
+            out.append((s, st, tris, rp, col))
+            f.close()
+        finally:
+            os.environ.pop("LF_TEST_SMALL_TABLES", None)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
