@@ -303,6 +303,12 @@ lf_status lf_server_poll(lf_server* s, int32_t* n_queued, int32_t* n_active, int
  * (size query with tris NULL; 0 without dual mesh), latency_ms from
  * submission to completion, queue_ms spent waiting for admission, steps run.
  * Host buffers. */
+/* Cancels a queued or active job: a queued job leaves the queue; an active
+ * job's chunk in flight completes, then its memory is released at once.  A
+ * cancelled job counts as done for lf_server_poll, its lf_server_result
+ * fails with LF_EINVAL, and lf_server_release frees it.  LF_EINVAL for an
+ * unknown or finished job. */
+lf_status lf_server_cancel(lf_server* s, int64_t id);
 lf_status lf_server_result(lf_server* s, int64_t id, int32_t* seeds, int32_t* labels,
                            int64_t* n_tri, int32_t* tris, double* latency_ms, double* queue_ms,
                            int64_t* steps);

@@ -56,7 +56,7 @@ EXPORTS = [
     "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_lloyd", "lf_dual_mesh", "lf_dual_matrix",
     "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
     "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
-    "lf_server_create", "lf_server_destroy", "lf_server_submit", "lf_server_poll",
+    "lf_server_create", "lf_server_destroy", "lf_server_submit", "lf_server_poll", "lf_server_cancel",
     "lf_server_result", "lf_server_release", "lf_server_memory",
 ]
 
@@ -127,6 +127,7 @@ def load(path: str | None = None):
         "lf_server_destroy": (C.c_int, [V]),
         "lf_server_submit": (C.c_int, [V, C.POINTER(lf_job), V]),
         "lf_server_poll": (C.c_int, [V, V, V, V]),
+        "lf_server_cancel": (C.c_int, [V, I64]),
         "lf_server_result": (C.c_int, [V, I64, V, V, V, V, V, V, V]),
         "lf_server_release": (C.c_int, [V, I64]),
         "lf_server_memory": (C.c_int, [V, V, V]),
@@ -587,6 +588,9 @@ class Server:
         tris = np.zeros((nt, 3), np.int32)
         nt, lat, qu, st = lf_server_result(self.h, job_id, seeds, labels, tris)
         return dict(seeds=seeds, labels=labels, tris=tris, latency_ms=lat, queue_ms=qu, steps=st)
+
+    def cancel(self, job_id: int):
+        _check(load().lf_server_cancel(self.h, job_id))
 
     def release(self, job_id: int):
         lf_server_release(self.h, job_id)

@@ -21,7 +21,7 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-enum JobState { kQueued, kActive, kDone, kFailed };
+enum JobState { kQueued, kActive, kDone, kFailed, kCancelled };
 
 struct Job {
   int64_t id = 0;
@@ -299,6 +299,34 @@ lf_status lf_server_poll(lf_server* s, int32_t* n_queued, int32_t* n_active, int
   return lf::host_oom();
 }
 
+lf_status lf_server_cancel(lf_server* s, int64_t id) try {
+  if (!s) return sfail(LF_EINVAL, "NULL argument");
+  auto it = s->jobs.find(id);
+  if (it == s->jobs.end()) return sfail(LF_EINVAL, "unknown job");
+  Job* j = it->second;
+  if (j->state == kQueued) {
+    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), j));
+  } else if (j->state == kActive) {
+    // the chunk in flight finishes first; then the job's memory is released
+    if (j->in_flight) {
+      int64_t rem = 0;
+      lf::step_complete(j->f, &rem);
+      j->in_flight = false;
+    }
+    release(j);
+    s->in_use -= j->bytes;
+    s->active.erase(std::find(s->active.begin(), s->active.end(), j));
+  } else {
+    return sfail(LF_EINVAL, "job already finished");
+  }
+  j->state = kCancelled;
+  j->t_done = now_ms();
+  ++s->n_done;
+  return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
+}
+
 lf_status lf_server_result(lf_server* s, int64_t id, int32_t* seeds, int32_t* labels,
                            int64_t* n_tri, int32_t* tris, double* latency_ms, double* queue_ms,
                            int64_t* steps) try {
@@ -307,6 +335,7 @@ lf_status lf_server_result(lf_server* s, int64_t id, int32_t* seeds, int32_t* la
   if (it == s->jobs.end()) return sfail(LF_EINVAL, "unknown job");
   Job* j = it->second;
   if (j->state == kFailed) return sfail(j->err, "job failed: " + j->err_msg);
+  if (j->state == kCancelled) return sfail(LF_EINVAL, "job cancelled");
   if (j->state != kDone) return sfail(LF_EBUSY, "job not finished");
   if (seeds) memcpy(seeds, j->out_seeds.data(), sizeof(int32_t) * j->out_seeds.size());
   if (labels) memcpy(labels, j->labels.data(), sizeof(int32_t) * j->labels.size());
@@ -325,7 +354,8 @@ lf_status lf_server_release(lf_server* s, int64_t id) try {
   auto it = s->jobs.find(id);
   if (it == s->jobs.end()) return sfail(LF_EINVAL, "unknown job");
   Job* j = it->second;
-  if (j->state != kDone && j->state != kFailed) return sfail(LF_EBUSY, "job not finished");
+  if (j->state != kDone && j->state != kFailed && j->state != kCancelled)
+    return sfail(LF_EBUSY, "job not finished");
   delete j;
   s->jobs.erase(it);
   return LF_OK;

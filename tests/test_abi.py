@@ -78,6 +78,14 @@ def test_server_host_logic_without_gpu():
     with pytest.raises(lfb.LFError) as e:
         lfb.lf_server_result(S.h, 12345)
     assert e.value.status == 1
+    j = S.submit(mesh.V, mesh.F, seeds, steps=10)
+    S.cancel(j)  # a queued job leaves the queue; no GPU needed
+    with pytest.raises(lfb.LFError) as e:
+        S.result(j)
+    assert e.value.status == 1
+    S.release(j)
+    with pytest.raises(lfb.LFError):
+        S.cancel(j)  # unknown now
     with pytest.raises(lfb.LFError):  # layer types for n_s + 1 layers, a square table
         S.submit(mesh.V, mesh.F, seeds, steps=10, layer_types=np.zeros(3, np.int32),
                  table=np.zeros((2, 2, 3)))

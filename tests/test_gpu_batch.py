@@ -153,3 +153,33 @@ def test_full_size_c4_batch_equals_solo(lf):
         f.close()
         M.close()
     B.close()
+
+
+def test_server_cancel(lf):
+    """Cancelling an active job (after its first chunk is in flight) and a
+    queued one: their memory is released, their results fail, and the other
+    jobs compute exactly what they compute alone."""
+    lfb, ctx = lf
+    jobs = _jobs()[:3]
+    S = lfb.Server(0, 4096 << 20, 1, 8)
+    ids = [S.submit(m.V, m.F, s, steps, rounds, dual, op) for m, s, op, steps, rounds, dual in jobs]
+    say("server cancel")
+    S.poll()  # admits the first job and issues its first chunk
+    S.cancel(ids[0])
+    S.cancel(ids[2])
+    assert S.memory()[0] == 0
+    S.run()
+    for i in (ids[0], ids[2]):
+        with pytest.raises(lfb.LFError):
+            S.result(i)
+        S.release(i)
+    m, s, op, steps, rounds, dual = jobs[1]
+    r = S.result(ids[1])
+    ref = _solo_job(lfb, ctx, m, s, op, steps, rounds, dual, None)
+    assert np.array_equal(r["labels"], ref["labels"]) and np.array_equal(r["seeds"], ref["seeds"])
+    assert np.array_equal(r["tris"], ref["tris"])
+    with pytest.raises(lfb.LFError):
+        S.cancel(ids[1])  # finished
+    S.release(ids[1])
+    assert S.memory()[0] == 0
+    S.close()
