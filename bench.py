@@ -107,7 +107,97 @@ def summarize_counters(fetch_dir, write_dir, copyf_dir, copyw_dir, probe_mib, ou
          "hbm_bytes_per_launch": fetch + write}
     with open(out_path, "w") as fh:
         json.dump(d, fh, indent=1)
+    md = os.path.splitext(out_path)[0] + ".md"
+    if os.path.exists(md):  # the per-launch table of the summary next to it
+        text = open(md).read()
+        i, j = text.index("Calibration:"), text.index("| algorithmic bytes")
+        table = (f"Calibration: a {probe_mib // 1024} GiB device-to-device copy reads FETCH_SIZE = "
+                 f"{cf['FETCH_SIZE']:,.0f} KiB and WRITE_SIZE =\n{cw['WRITE_SIZE']:,.0f} KiB per "
+                 f"dispatch, so FETCH_SIZE is scaled by {f_scale:.1f} and WRITE_SIZE by "
+                 f"{w_scale:.1f}.\n\n"
+                 "| per launch (mean of 2,000 steps of one job) | value |\n|---|---|\n"
+                 f"| FETCH_SIZE | {d['fetch_size_kib_per_launch']:,.0f} KiB → "
+                 f"{d['hbm_read_bytes_per_launch'] / 1e6:.0f} MB read |\n"
+                 f"| WRITE_SIZE | {d['write_size_kib_per_launch']:,.0f} KiB → "
+                 f"{d['hbm_write_bytes_per_launch'] / 1e6:.0f} MB written |\n"
+                 f"| HBM traffic | {d['hbm_bytes_per_launch'] / 1e6:.0f} MB |\n")
+        with open(md, "w") as fh:
+            fh.write(text[:i] + table + text[j:])
     print(json.dumps(d))
+
+
+def _kname(name: str) -> str:
+    import re
+    m = re.search(r"(k_[A-Za-z0-9_]+(<[a-z]+>)?|__amd_rocclr_[A-Za-z]+)", name)
+    return m.group(1) if m else name.split("(")[0][:40]
+
+
+def summarize_trace(trace_dir: str, plain_json: str, traced_json: str, out_dir: str):
+    """Writes the kernel-trace summaries of the C3 job (step kernel and the
+    post-processing of the last job) from a rocprofv3 --kernel-trace --stats
+    run of `bench.py --no-c2 --no-batch --no-serve --no-cpu-baseline`, next
+    to the bench lines of that run and of a plain run."""
+    import collections
+    import csv
+    stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
+    plain = json.loads(open(plain_json).read().strip().splitlines()[-1])
+    traced = json.loads(open(traced_json).read().strip().splitlines()[-1])
+    cmd = ["```", "cd /tmp && export TMPDIR=/tmp",
+           "rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- \\",
+           "    python3 <repo>/bench.py --no-c2 --no-batch --no-serve --no-cpu-baseline",
+           "python3 <repo>/bench.py --trace-summary <out> <plain bench line> <traced bench line>",
+           "```"]
+    lines = ["# Kernel trace: C3 job (bench.py C3 section)", "",
+             "Commands (on one MI355X, from the repository root):", "", *cmd, "",
+             "Workload: icosphere level 9 (2,621,442 vertices) displaced by 8 spherical harmonics, "
+             "cotangent", "operator, 16,384 seeds; 1 warm-up + 3 timed jobs of 2,000 steps + "
+             "labels + Lloyd + dual mesh.", "",
+             "| kernel | calls | avg (us) | min (us) | max (us) | share |",
+             "|---|---|---|---|---|---|"]
+    for r in stats[:14]:
+        lines.append(f"| {_kname(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f}% |")
+    step = next(r for r in stats if "k_step" in r["Name"])
+    lines += ["", f"The step kernel's mean ({float(step['AverageNs']) / 1e3:.1f} us over "
+              f"{step['Calls']} launches) agrees with the event-timed",
+              f"`config.step_kernel_us` of the bench line of the same run "
+              f"({traced['config']['step_kernel_us']:.1f} us under the",
+              f"profiler) and of the plain bench run ({plain['config']['step_kernel_us']:.1f} us)."]
+    with open(os.path.join(out_dir, "k_step_c3_trace.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    # the post-processing of the last timed job: from its Lloyd accumulation
+    # to the last kernel of its dual mesh (before the copy-roof probe)
+    rows = sorted(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv"))),
+                  key=lambda r: int(r["Start_Timestamp"]))
+    first = max(i for i, r in enumerate(rows) if _kname(r["Kernel_Name"]) == "k_lloyd_accum")
+    seg = rows[first:]
+    stop = next((i for i, r in enumerate(seg) if "at::native" in r["Kernel_Name"]), len(seg))
+    seg = seg[:stop]
+    while seg and not _kname(seg[-1]["Kernel_Name"]).startswith("k_"):
+        seg.pop()
+    d0 = next(i for i, r in enumerate(seg) if _kname(r["Kernel_Name"]) == "k_dual_pairs")
+    while d0 > 0 and _kname(seg[d0 - 1]["Kernel_Name"]) in ("k_fill64",
+                                                            "__amd_rocclr_fillBufferAligned"):
+        d0 -= 1
+    lines = ["# Kernel trace: post-processing of one C3 job (Lloyd re-seed, dual mesh)", "",
+             "From the same run as `k_step_c3_trace.md` (commands there): the kernels after the "
+             "last", "job's 2,000 steps, split at the first dual-mesh kernel; GPU kernel times.", ""]
+    for title, part in (("Lloyd re-seed", seg[:d0]), ("dual mesh", seg[d0:])):
+        busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in part)
+        lines += [f"## {title}: {len(part)} launches, {busy / 1e6:.2f} ms of kernel time", "",
+                  "| kernel | calls | total (us) |", "|---|---|---|"]
+        agg = collections.defaultdict(lambda: [0, 0])
+        for r in part:
+            a = agg[_kname(r["Kernel_Name"])]
+            a[0] += 1
+            a[1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        for n, (c, t) in sorted(agg.items(), key=lambda x: -x[1][1])[:14]:
+            lines.append(f"| {n} | {c} | {t / 1e3:.1f} |")
+        lines.append("")
+    with open(os.path.join(out_dir, "post_c3_trace.md"), "w") as fh:
+        fh.write("\n".join(lines))
 
 
 def cpu_baseline(mesh, seeds, seconds: float, max_steps: int = 200):
@@ -349,10 +439,16 @@ def main():
     ap.add_argument("--counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
                     help="only summarize rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the step "
                          "kernel and of the copy probe into profiles/k_step_c3_counters.json")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_DIR", "PLAIN_JSON", "TRACE_JSON"),
+                    help="only summarize a rocprofv3 kernel trace of the C3 section into "
+                         "profiles/k_step_c3_trace.md and profiles/post_c3_trace.md")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB ten times (calibrates "
                          "the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        summarize_trace(*args.trace_summary, out_dir=os.path.join(ROOT, "profiles"))
+        return
     if args.counters:
         summarize_counters(*args.counters, probe_mib=1024,
                            out_path=os.path.join(ROOT, "profiles", "k_step_c3_counters.json"))
