@@ -182,64 +182,61 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
     if (!__any(l < cnt)) break;                                   \
     else
 #define LF_INNER_RT for (int l = 0; l < cnt; ++l)
-    // Q_j per slot: registers in the register path, the workspace row's
+    // n Q_j - sqrt(phi_j) G_j per slot: registers in the register path, the workspace row's
     // output slots (overwritten by the value below) in the wide path
     float qbuf[UNROLL ? K : 1];
     auto q_at = [&](int s) -> float& {
       if constexpr (UNROLL) return qbuf[s];
       else return out_of(r, s);
     };
-    // the slots' types: loaded once into registers in the register path
+    // the slots' types and square roots: computed once into registers in
+    // the register path
     int tbuf[UNROLL ? K : 1];
+    float sbuf[UNROLL ? K : 1];
     if constexpr (UNROLL) {
-      LF_SLOTS tbuf[s] = ((act >> s) & 1) ? c.types[r.col[s]] : 0;
+      LF_SLOTS {
+        tbuf[s] = ((act >> s) & 1) ? c.types[r.col[s]] : 0;
+        sbuf[s] = root(r.phi[s]);
+      }
     }
     auto type_of = [&](int s) {
       if constexpr (UNROLL) return tbuf[s];
       else return c.types[r.col[s]];
     };
-    auto q_of = [&](int s) {
+    auto sqrt_of = [&](int s) {
+      if constexpr (UNROLL) return sbuf[s];
+      else return root(r.phi[s]);
+    };
+    // Q_s and G_s in one pass over the other active slots (one table read
+    // per ordered pair); what d_s needs besides the sum of all Q is kept
+    // per slot: n Q_s - sqrt(phi_s) G_s
+    auto qg_of = [&](int s) {
       const int ts = type_of(s);
       const bool sb = r.col[s] == c.n_s;
-      float Q = 0.f;
+      float Q = 0.f, G = 0.f;
       auto term = [&](int l) {
         if (l == s || !((act >> l) & 1)) return;
         const float4 k = pair_coef(c, ts, type_of(l), sb, r.col[l] == c.n_s);
         Q += 0.5f * k.x * r.lam[l] + k.y * r.phi[l];
+        G += k.z * sqrt_of(l);
       };
       if constexpr (UNROLL) {
         LF_INNER term(l);
       } else {
         LF_INNER_RT term(l);
       }
-      return Q;
-    };
-    auto d_of = [&](int s, float sumQ_) {
-      const int ts = type_of(s);
-      const bool sb = r.col[s] == c.n_s;
-      float G = 0.f;
-      auto term = [&](int l) {
-        if (l == s || !((act >> l) & 1)) return;
-        const float4 k = pair_coef(c, ts, type_of(l), sb, r.col[l] == c.n_s);
-        G += k.z * root(r.phi[l]);
-      };
-      if constexpr (UNROLL) {
-        LF_INNER term(l);
-      } else {
-        LF_INNER_RT term(l);
-      }
-      return -mun * (fn * q_at(s) - sumQ_ - root(r.phi[s]) * G);
+      return float2{Q, G};
     };
 #undef LF_INNER
 #undef LF_INNER_RT
     float sQ = 0.f;
     auto pass_q = [&](int s) {
-      const float q = q_of(s);
-      q_at(s) = q;
-      sQ += q;
+      const float2 qg = qg_of(s);
+      q_at(s) = fn * qg.x - sqrt_of(s) * qg.y;
+      sQ += qg.x;
     };
     auto pass_v = [&](int s) {
-      float v = r.phi[s] + c.dt * d_of(s, sQ);
+      float v = r.phi[s] + c.dt * (-mun * (q_at(s) - sQ));
       if (v > 1.f) v = 1.f;
       if (v <= 0.f) v = 0.f;
       out_of(r, s) = v;
