@@ -20,6 +20,8 @@ in the same line:
   fraction of it.
 * "c2": jittered icosphere level 7 (163,842 vertices), 1,024 seeds,
   cotangent operator, 1,000 steps + 5 Lloyd rounds + labels + dual mesh.
+* "typed": the same mesh and seeds with per-pair coefficients over 1, 8 and
+  64 layer types; mean step-kernel time of each against the scalar step.
 * "batch": 256 torus grids of uneven size (vertex counts log-uniform in
   [1e3, 1e5], seed counts log-uniform in [8, 512]), graph operator, 500 steps
   + labels each, advanced as one batch and, on the same GPU, one mesh at a
@@ -93,8 +95,8 @@ def summarize_counters(fetch_dir, write_dir, copyf_dir, copyw_dir, probe_mib, ou
     probe = probe_mib * (1 << 20)
     cf, _ = _counter_means(copyf_dir, "copyBuffer")
     cw, _ = _counter_means(copyw_dir, "copyBuffer")
-    kf, nf = _counter_means(fetch_dir, "k_step")
-    kw, nw = _counter_means(write_dir, "k_step")
+    kf, nf = _counter_means(fetch_dir, "k_step<false>")
+    kw, nw = _counter_means(write_dir, "k_step<false>")
     f_scale = probe / (cf["FETCH_SIZE"] * 1024)
     w_scale = probe / (cw["WRITE_SIZE"] * 1024)
     fetch = kf["FETCH_SIZE"] * 1024 * f_scale
@@ -135,7 +137,7 @@ def _kname(name: str) -> str:
 def summarize_trace(trace_dir: str, plain_json: str, traced_json: str, out_dir: str):
     """Writes the kernel-trace summaries of the C3 job (step kernel and the
     post-processing of the last job) from a rocprofv3 --kernel-trace --stats
-    run of `bench.py --no-c2 --no-batch --no-serve --no-cpu-baseline`, next
+    run of `bench.py --no-c2 --no-batch --no-serve --no-typed --no-cpu-baseline`, next
     to the bench lines of that run and of a plain run."""
     import collections
     import csv
@@ -144,7 +146,7 @@ def summarize_trace(trace_dir: str, plain_json: str, traced_json: str, out_dir: 
     traced = json.loads(open(traced_json).read().strip().splitlines()[-1])
     cmd = ["```", "cd /tmp && export TMPDIR=/tmp",
            "rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- \\",
-           "    python3 <repo>/bench.py --no-c2 --no-batch --no-serve --no-cpu-baseline",
+           "    python3 <repo>/bench.py --no-c2 --no-batch --no-serve --no-typed --no-cpu-baseline",
            "python3 <repo>/bench.py --trace-summary <out> <plain bench line> <traced bench line>",
            "```"]
     lines = ["# Kernel trace: C3 job (bench.py C3 section)", "",
@@ -158,7 +160,7 @@ def summarize_trace(trace_dir: str, plain_json: str, traced_json: str, out_dir: 
         lines.append(f"| {_kname(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f}% |")
-    step = next(r for r in stats if "k_step" in r["Name"])
+    step = next(r for r in stats if "k_step<false>" in r["Name"])
     lines += ["", f"The step kernel's mean ({float(step['AverageNs']) / 1e3:.1f} us over "
               f"{step['Calls']} launches) agrees with the event-timed",
               f"`config.step_kernel_us` of the bench line of the same run "
@@ -291,6 +293,37 @@ def run_c2(lfb, I, steps: int, rounds: int, jobs: int):
                          f"operator, {steps} steps + {rounds} Lloyd rounds + labels + dual mesh"),
             "value": skel / wall, "unit": "nnz-updates/s", "ms_per_job": wall / jobs * 1e3,
             "jobs": jobs, "step_kernel_us": ms / max(n, 1) * 1e3}
+
+
+def run_typed(lfb, m, seeds, type_counts=(1, 8, 64), warm: int = 200, timed: int = 400):
+    """Per-pair coefficients on the C3 mesh: each layer draws one of T types
+    (seeded), the T x T table is symmetric around the scalar defaults (a =
+    0.04, w uniform in [0.15, 0.25], e = 1).  Mean step-kernel time (every
+    launch event-timed) over `timed` steps after `warm` steps from the seeds,
+    for the scalar step and each T."""
+    import numpy as np
+    res = {}
+    for n_t in (0,) + tuple(type_counts):
+        f = lfb.Fields(m, seeds)
+        if n_t:
+            rng = np.random.default_rng(n_t)
+            tab = np.empty((n_t, n_t, 3))
+            tab[..., 0] = 0.04
+            tab[..., 1] = rng.uniform(0.15, 0.25, (n_t, n_t))
+            tab[..., 2] = 1.0
+            tab = 0.5 * (tab + tab.transpose(1, 0, 2))
+            f.set_coefficients(rng.integers(0, n_t, seeds.size + 1).astype(np.int32), tab)
+        f.step(warm)
+        f.timing(1)
+        f.step(timed)
+        ms, n = f.timing(0)
+        res[n_t] = ms / max(n, 1) * 1e3
+        f.close()
+    log("per-pair coefficients: " + ", ".join(f"T={t}: {v:.1f} us" for t, v in res.items()))
+    return {"workload": (f"the C3 mesh and seeds, per-pair coefficients over T layer types, "
+                         f"steps {warm}-{warm + timed} from the seeds"),
+            "scalar_step_kernel_us": res[0],
+            "step_kernel_us_by_types": {str(t): res[t] for t in type_counts}}
 
 
 def run_batch(lfb, I, n_meshes: int, steps: int):
@@ -436,6 +469,7 @@ def main():
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-typed", action="store_true", help="skip the per-pair coefficient steps")
     ap.add_argument("--counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
                     help="only summarize rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the step "
                          "kernel and of the copy probe into profiles/k_step_c3_counters.json")
@@ -568,12 +602,14 @@ def main():
         },
     }
     f.close()
-    m.close()
     roof = copy_roof()
     out["copy_roof"] = {"unit": "GB/s", "measured": roof, "frac_of_peak": roof / HBM_PEAK_GBS,
                         "step_achieved_frac": achieved / roof,
                         "what": "1 GiB device-to-device copy, read + write bytes"}
     log(f"copy roof: {roof:.0f} GB/s")
+    if not args.no_typed:
+        out["typed"] = run_typed(lfb, m, seeds)
+    m.close()
     if not args.no_c2:
         out["c2"] = run_c2(lfb, I, 1000, 5, 3)
     if not args.no_batch:
