@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 from paper_1804_09152_amd import inputs as I
+from tests.dense_ref import torus_graph_operator
 from tests.gpu_common import as_oracle, check_step, f32, gpu_load, row_compare, say
 
 pytestmark = pytest.mark.gpu
@@ -169,6 +170,41 @@ def test_full_size_c3_one_step(lf, orc):
         U4 = orc.step(L, U4, seeds.size, orc.default_params())
     pat, diff = row_compare(G4, U4)
     assert pat.all() and diff.max() <= 1e-5
+
+
+def test_max_size_mesh(lf, orc):
+    """The largest mesh the library takes (vertex ids below 2^25): a
+    5792 x 5792 torus grid (33,547,264 vertices, 67,094,528 triangles,
+    16,384 seeds, graph operator), 3 steps from the seeds, every row against
+    the oracle run on the grid's closed-form operator (pinned to the
+    oracle's own operator on small grids); one vertex more than the limit
+    is rejected."""
+    lfb, ctx = lf
+    nx = 5792
+    mesh = I.torus_grid(nx, nx)
+    assert mesh.n_v < (1 << 25)
+    seeds = I.seeds_uniform(mesh.n_v, 16384, np.random.default_rng(5))
+    say("max-size mesh", mesh.n_v)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    L = torus_graph_operator(nx, nx)
+    rp, col, val = m.operator()
+    assert np.array_equal(rp, L[0]) and np.array_equal(col, L[1]) and np.array_equal(val, L[2])
+    del rp, col, val
+    f = lfb.Fields(m, seeds)
+    f.step(3)
+    G = as_oracle(f.export())
+    U = orc.init(mesh.n_v, seeds)
+    for _ in range(3):
+        U = orc.step(L, U, seeds.size, orc.default_params())
+    pat, diff = row_compare(G, U)
+    assert pat.all() and diff.max() <= 1e-5
+    f.close()
+    m.close()
+    del G, U, L
+    say("one vertex over the limit")
+    V = np.zeros((1 << 25, 3))
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        lfb.Mesh(ctx, V, mesh.F[:1], 0)
 
 
 def _three_layer_state(mesh, n_s, seed):
@@ -352,6 +388,13 @@ def test_invalid_inputs(lf):
         lfb.Fields(m, np.array([1, 2, 1], np.int32))
     with pytest.raises(lfb.LFError, match="EINVAL"):
         lfb.Fields(m, np.array([1, mesh.n_v], np.int32))
+    # degenerate seed counts: none, or every vertex (no base anywhere)
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        lfb.Fields(m, np.zeros(0, np.int32))
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        lfb.Fields(m, np.arange(mesh.n_v, dtype=np.int32))
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        lfb.Mesh(ctx, mesh.V[:0], mesh.F[:0], 0)
     bad = mesh.F.copy()
     bad[3, 2] = bad[3, 0]
     with pytest.raises(lfb.LFError, match="EINVAL"):
@@ -359,6 +402,11 @@ def test_invalid_inputs(lf):
     f = lfb.Fields(m, seeds)
     f.step(3)
     before = f.export()
+    f.step(0)  # no steps: nothing changes
+    with pytest.raises(lfb.LFError, match="EINVAL"):
+        f.step(-1)
+    for x, y in zip(before, f.export()):
+        assert np.array_equal(x, y)
     P, C, V = [x.copy() for x in before]
     if P[1] - P[0] >= 2:
         C[0], C[1] = C[1], C[0]

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_1804_09152_amd import inputs as I
-from tests.dense_ref import dense_operator
+from tests.dense_ref import dense_operator, torus_graph_operator
 
 
 def _dense(orc, L, n):
@@ -48,6 +48,16 @@ def test_graph_degrees(orc):
     assert np.all(np.diff(ptr) == 7)  # 6 neighbours + diagonal
     D = _dense(orc, (ptr, col, val), m.n_v)
     assert np.all(np.diag(D) == -6)
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (9, 7), (64, 33)])
+def test_torus_graph_operator_closed_form(orc, nx, ny):
+    """The graph operator of a torus grid equals its closed form (six
+    neighbours of weight 1, diagonal -6), entry for entry."""
+    m = I.torus_grid(nx, ny)
+    ptr, col, val = orc.operator(m.V, m.F, 0)
+    cp, cc, cv = torus_graph_operator(nx, ny)
+    assert np.array_equal(ptr, cp) and np.array_equal(col, cc) and np.array_equal(val, cv)
 
 
 @pytest.mark.parametrize("op", [0, 1])
