@@ -356,27 +356,16 @@ __device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
   return RowView{e, n};
 }
 
-// sets phi of slot s (s from 0 to kRowRegs - 1)
-__device__ __forceinline__ void put_phi(RowBuf<kRowRegs>& r, int s, float ph) {
-#pragma unroll
-  for (int t = 0; t < kRowRegs; ++t) r.phi[t] = t == s ? ph : r.phi[t];
-}
-
-// Gathers row i: its own layers (lam starts at L_ii * phi) and then, in the
-// operator's column order, every neighbour row scaled by L(i,u).  The loads
-// come in two rounds (own row, diagonal and the slice's operator entries;
-// then the neighbours' rows).  Returns false when the row needs the wide
-// path: more than kRowRegs layers, or an overflow row among its inputs.
 // Row i's gather into register slots: its own layers (lam starts at L_ii *
-// phi) and then, in the operator's column order, every neighbour row scaled
-// by L(i,u), each row in layer order.  The fast path streams the neighbour
-// rows through a window of kWin rows (the row of neighbour k + kWin is
-// requested before neighbour k is merged, so a few loads stay in flight
-// without holding every neighbour row in registers).  Returns kGatherOk,
-// kGatherOvf when an input row lives in the overflow area (the row is then
-// gathered again by gather_slow), or kGatherWide when the row touches more
-// than kRowRegs layers.
-constexpr int kGatherOk = 0, kGatherOvf = 1, kGatherWide = 2;
+// phi) and then every neighbour row scaled by L(i,u), each row in layer
+// order.  The neighbour rows stream through a window of kWin rows (the row
+// of neighbour k + kWin is requested before neighbour k is merged, so a few
+// loads stay in flight without holding every neighbour row in registers),
+// in the operator's column order; a neighbour row kept in the overflow area
+// is merged after the others, from there, so that only the lanes that meet
+// one wait for the extra load round.  Returns kGatherOk, or kGatherWide
+// when the row touches more than kRowRegs layers.
+constexpr int kGatherOk = 0, kGatherWide = 2;
 
 __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n_in, int i,
                                            const Ent* ops, const StepArgs& A) {
@@ -398,18 +387,24 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n
   EllRow win[kWin];
 #pragma unroll
   for (int k = 0; k < kWin; ++k) win[k] = row_at(A.u_in, le[k].col >= 0 ? le[k].col : i);
-  if (is_ovf(own.e[0])) return kGatherOvf;
-  // own row: slots 0..3 in layer order
+  bool ovf = false;
+  // the entries of an overflow row, scaled by w
+  auto merge_ovf = [&](const EllRow& u, float w) {
+    const RowView v = ovf_view(A, u);
+    for (int p = 0; p < v.n; ++p) add_regs(r, cnt, ovf, v.p[p].col, w, v.p[p].val);
+  };
+  // own row: slots 0..3 in layer order (an overflow row is merged last)
+  const bool own_ovf = is_ovf(own.e[0]);
 #pragma unroll
   for (int j = 0; j < kEll; ++j) {
-    if (own.e[j].col >= 0) {
+    if (!own_ovf && own.e[j].col >= 0) {
       r.col[j] = own.e[j].col;
       r.phi[j] = own.e[j].val;
       r.lam[j] = dg * own.e[j].val;
       cnt = j + 1;
     }
   }
-  bool ovf = false, orow = false;
+  unsigned onb = 0;  // prefetched neighbours whose rows are overflow rows
 #pragma unroll
   for (int k = 0; k < kNbPre; ++k) {
     const EllRow u = win[k % kWin];
@@ -417,7 +412,7 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n
       win[k % kWin] = row_at(A.u_in, le[k + kWin].col >= 0 ? le[k + kWin].col : i);
     if (le[k].col < 0) continue;
     if (is_ovf(u.e[0])) {
-      orow = true;
+      onb |= 1u << k;
       continue;
     }
 #pragma unroll
@@ -428,7 +423,7 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n
     if (l.col < 0) return;
     const EllRow u = row_at(A.u_in, l.col);
     if (is_ovf(u.e[0])) {
-      orow = true;
+      merge_ovf(u, l.val);
       return;
     }
 #pragma unroll
@@ -438,50 +433,19 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n
   for (int k = kNbPre; k < A.op_w; ++k) more(ops[k * kSlice]);
   if (A.op_w == kOpWidth && ops[(kOpWidth - 1) * kSlice].col >= 0)  // rows beyond the slices
     for (int q = A.lptr[i] + kOpWidth; q < A.lptr[i + 1]; ++q) more(A.lent[q]);
-  return orow ? kGatherOvf : (ovf ? kGatherWide : kGatherOk);
-}
-
-// The same gather for a row that reads an overflow row (rare): plain loops,
-// overflow rows read from the overflow area, same terms in the same order.
-__device__ __forceinline__ int gather_slow(RowBuf<kRowRegs>& r, int& cnt, int i, const Ent* ops,
-                                        const StepArgs& A) {
-#pragma unroll
-  for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
-  cnt = 0;
-  bool ovf = false;
-  const float dg = A.ldiag[i];
-  const RowView o = row_view(&A, i);
-  if (o.n > kRowRegs) return kGatherWide;
-  for (int p = 0; p < o.n; ++p) {
-    const Ent e = o.p[p];
-    add_regs(r, cnt, ovf, e.col, dg, e.val);
-    put_phi(r, cnt - 1, e.val);
+  while (onb) {  // the overflow rows among the prefetched neighbours
+    const int k = __builtin_ctz(onb);
+    onb &= onb - 1u;
+    const Ent l = ops[k * kSlice];
+    merge_ovf(row_at(A.u_in, l.col), l.val);
   }
-  // neighbours in batches of kWin: the batch's operator entries, then its
-  // rows, are requested together (few dependent rounds for the wavefront
-  // that waits on this lane)
-  const int q0 = A.lptr[i], deg = A.lptr[i + 1] - q0;
-  for (int k0 = 0; k0 < deg; k0 += kWin) {
-    Ent le[kWin];
-    EllRow u[kWin];
+  if (own_ovf) {  // own entries: add L_ii * phi and set phi of their slots
+    const RowView o = ovf_view(A, row_at(A.u_in, i));
+    for (int p = 0; p < o.n; ++p) {
+      const Ent e = o.p[p];
+      add_regs(r, cnt, ovf, e.col, dg, e.val);
 #pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      const int kk = k0 + k;
-      le[k] = kk >= deg ? Ent{-1, 0.f} : (kk < A.op_w ? ops[kk * kSlice] : A.lent[q0 + kk]);
-    }
-#pragma unroll
-    for (int k = 0; k < kWin; ++k) u[k] = A.u_in[le[k].col >= 0 ? le[k].col : i];
-#pragma unroll
-    for (int k = 0; k < kWin; ++k) {
-      if (le[k].col < 0) continue;
-      const RowView v = is_ovf(u[k].e[0]) ? ovf_view(A, u[k]) : RowView{nullptr, 0};
-      if (v.p) {
-        for (int p = 0; p < v.n; ++p) add_regs(r, cnt, ovf, v.p[p].col, le[k].val, v.p[p].val);
-      } else {
-#pragma unroll
-        for (int j = 0; j < kEll; ++j)
-          if (u[k].e[j].col >= 0) add_regs(r, cnt, ovf, u[k].e[j].col, le[k].val, u[k].e[j].val);
-      }
+      for (int t = 0; t < kRowRegs; ++t) r.phi[t] = r.col[t] == e.col ? e.val : r.phi[t];
     }
   }
   return ovf ? kGatherWide : kGatherOk;
@@ -682,9 +646,7 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   // this row's operator entries: column-major in the wavefront's slice
   const Ent* ops = A.lell + (int64_t)sl * A.op_w * kSlice + lane;
   if (i < A.n_v) {
-    int g = gather_regs(r, cnt, n_in, i, ops, A);
-    if (g == kGatherOvf) g = gather_slow(r, cnt, i, ops, A);
-    in_regs = g == kGatherOk;
+    in_regs = gather_regs(r, cnt, n_in, i, ops, A) == kGatherOk;
   }
   // An earlier step of the chunk failed: write nothing (no row, no overflow
   // entry, no workspace slot, no counter), so that the last good fields (the
