@@ -310,6 +310,107 @@ def test_wide_rows(lf, orc):
         U = O
 
 
+def test_overflow_rows_in_register_slots(lf, orc):
+    """Rows of five to seven entries (kept in the overflow area) whose
+    neighbourhoods touch at most eight layers: the row itself and its
+    neighbours, one of which reads two such rows, stay in register slots.
+    Three teacher-forced steps against the oracle, every row."""
+    lfb, ctx = lf
+    nx = 16
+    mesh = I.torus_grid(nx, nx)
+    L = orc.operator(mesh.V, mesh.F, 0)
+    n_s = 12
+    rows = [{n_s: 1.0} for _ in range(mesh.n_v)]
+    rows[0] = {c: 0.1 + 0.05 * c for c in range(6)}  # 6 entries
+    far = 8 + nx * 8
+    rows[far] = {c: 0.2 for c in range(6, 11)}  # 5 entries
+    rows[far + 2] = {6: 0.3, 7: 0.2, 8: 0.1, 11: 0.15, 2: 0.05, n_s: 0.2}  # 6 entries
+    rows[nx] = {0: 0.7, n_s: 0.3}  # a neighbour of vertex 0 that holds one of its layers
+    ptr = np.zeros(mesh.n_v + 1, np.int64)
+    col, val = [], []
+    for i, r in enumerate(rows):
+        tot = sum(r.values())
+        for c in sorted(r):
+            col.append(c)
+            val.append(r[c] / tot)
+        ptr[i + 1] = len(col)
+    U = f32((ptr, np.array(col, np.int32), np.array(val)))
+    nb = lambda v: [int(c) for c in L[1][L[0][v]:L[0][v + 1]] if c != v]
+    assert far + 1 in nb(far) and far + 1 in nb(far + 2)  # reads two overflow rows
+    for v in [0, far, far + 1, far + 2] + nb(0):  # every union within eight slots
+        seen = set()
+        for u in [v] + nb(v):
+            seen |= set(rows[u])
+        assert len(seen) <= 8, (v, len(seen))
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, np.arange(n_s, dtype=np.int32) + 40)
+    say("overflow rows in register slots")
+    for t in range(3):
+        gpu_load(f, U)
+        f.step(1)
+        G = as_oracle(f.export())
+        O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
+        if t == 0:
+            assert np.diff(G[0]).max() > 4  # overflow rows written as well as read
+        check_step(G, O, info["margin"], what=f"overflow t={t}", max_guarded_frac=0.05)
+        U = f32(O)
+
+
+def _bipyramid(k):
+    """Closed surface of 2k triangles: two apexes over a ring of k vertices
+    (apex degree k, ring degree 4)."""
+    t = 2 * np.pi * np.arange(k) / k
+    V = np.concatenate([np.stack([np.cos(t), np.sin(t), np.zeros(k)], 1),
+                        [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]]])
+    r = np.arange(k)
+    F = np.concatenate([np.stack([np.full(k, k), r, (r + 1) % k], 1),
+                        np.stack([np.full(k, k + 1), (r + 1) % k, r], 1)]).astype(np.int32)
+    return V, F
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_high_degree_vertex(lf, orc, op):
+    """Apexes of degree 12: the neighbours beyond the prefetched seven, in
+    the operator's eighth slice column and its CSR tail.  Every ring row
+    first holds five layers (overflow rows, read by the apexes from all
+    three places), three teacher-forced steps; then 30 free steps from
+    seeds; every row against the oracle."""
+    lfb, ctx = lf
+    k = 12
+    V, F = _bipyramid(k)
+    n_v, n_s = k + 2, 6
+    L = orc.operator(V, F, op)
+    assert np.diff(L[0]).max() == k + 1  # the apexes: 12 neighbours and the diagonal
+    ptr = np.zeros(n_v + 1, np.int64)
+    col, val = [], []
+    rng = np.random.default_rng(3)
+    for i in range(n_v):
+        c = list(range(5)) if i < k else [n_s]
+        w = rng.uniform(0.1, 1.0, len(c))
+        col += c
+        val += list(w / w.sum())
+        ptr[i + 1] = len(col)
+    U = f32((ptr, np.array(col, np.int32), np.array(val)))
+    seeds = np.array([0, 2, 4, 6, 8, 10], np.int32)
+    m = lfb.Mesh(ctx, V, F, op)
+    f = lfb.Fields(m, seeds)
+    say("high-degree vertex", op)
+    for t in range(3):
+        gpu_load(f, U)
+        f.step(1)
+        G = as_oracle(f.export())
+        O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
+        check_step(G, O, info["margin"], what=f"apex t={t}", max_guarded_frac=0.2)
+        U = f32(O)
+    f.reset(seeds)
+    f.step(30)
+    Uo = orc.init(n_v, seeds)
+    for _ in range(30):
+        Uo = orc.step(L, Uo, n_s, orc.default_params())
+    pat, diff = row_compare(as_oracle(f.export()), Uo)
+    assert pat.all() and diff.max() <= 1e-5
+
+
 def test_wide_workspace_growth(lf, orc):
     """Thousands of vertices touching more than 8 layers: the wide-row
     workspace (1024 rows at first) runs out, grows and the step is replayed."""
