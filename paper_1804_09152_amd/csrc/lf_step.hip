@@ -361,11 +361,12 @@ __device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
 // order.  The neighbour rows stream through a window of kWin rows (the row
 // of neighbour k + kWin is requested before neighbour k is merged, so a few
 // loads stay in flight without holding every neighbour row in registers),
-// in the operator's column order; a neighbour row kept in the overflow area
-// is merged after the others, from there, so that only the lanes that meet
-// one wait for the extra load round.  Returns kGatherOk, or kGatherWide
-// when the row touches more than kRowRegs layers.
-constexpr int kGatherOk = 0, kGatherWide = 2;
+// in the operator's column order.  A row kept in the overflow area (a
+// neighbour's, then the own row) is merged after the others, from there, so
+// that only the lanes that meet one wait for its extra load rounds (the
+// slots need no order: the output is ranked by layer).  Returns kGatherOk,
+// or kGatherWide when the row touches more than kRowRegs layers.
+constexpr int kGatherOk = 0, kGatherWide = 1;
 
 __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n_in, int i,
                                            const Ent* ops, const StepArgs& A) {
