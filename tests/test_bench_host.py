@@ -1,0 +1,104 @@
+"""Host logic of bench.py that needs no GPU: the HBM-traffic figure from
+counter runs, the kernel-trace summaries, and the refusal of more than one
+GPU."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+STEP = "void lf::(anonymous namespace)::k_step<false>(lf::StepArgs)"
+TYPED = "void lf::(anonymous namespace)::k_step<true>(lf::StepArgs)"
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def _write(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def _counters(d, counter, per_kernel):
+    rows = []
+    for name, values in per_kernel.items():
+        rows += [[name, counter, v] for v in values]
+    _write(os.path.join(d, "run_counter_collection.csv"),
+           ["Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+
+
+def test_counter_summary_scales_by_the_copy_probe(tmp_path):
+    """FETCH_SIZE and WRITE_SIZE of the scalar step kernel only (not the
+    typed instance), each scaled so that the copy probe reads its known
+    size."""
+    kib = 1024
+    _counters(tmp_path / "f", "FETCH_SIZE", {STEP: [100.0, 300.0], TYPED: [9e9]})
+    _counters(tmp_path / "w", "WRITE_SIZE", {STEP: [50.0, 50.0]})
+    probe_mib = 1
+    _counters(tmp_path / "cf", "FETCH_SIZE", {COPY: [512.0]})  # half of 1 MiB: scale 2
+    _counters(tmp_path / "cw", "WRITE_SIZE", {COPY: [1024.0]})  # scale 1
+    out = tmp_path / "c.json"
+    bench.summarize_counters(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                             str(tmp_path / "cw"), probe_mib, str(out))
+    d = json.load(open(out))
+    assert d["launches"] == [2, 2]
+    assert d["fetch_scale"] == 2.0 and d["write_scale"] == 1.0
+    assert d["hbm_read_bytes_per_launch"] == 200.0 * kib * 2.0
+    assert d["hbm_write_bytes_per_launch"] == 50.0 * kib
+    assert d["hbm_bytes_per_launch"] == 200.0 * kib * 2.0 + 50.0 * kib
+    assert d["kernel_src_sha"] == bench.kernel_source_sha()
+
+
+def _bench_line(step_us):
+    return json.dumps({"metric": bench.METRIC, "config": {"step_kernel_us": step_us}})
+
+
+def test_trace_summaries(tmp_path):
+    """The step kernel's line and the agreement sentence; the post-processing
+    of the last job split at its first dual-mesh kernel (with the fills
+    before it), ending before the first library kernel."""
+    tr = tmp_path / "trace"
+    _write(str(tr / "run_kernel_stats.csv"),
+           ["Name", "Calls", "AverageNs", "MinNs", "MaxNs", "Percentage"],
+           [[STEP, 8000, 97900, 95700, 106700, 94.4],
+            ["void lf::k_lloyd_accum(int)", 4, 2129000, 2124000, 2135000, 1.0]])
+    seq = ["k_step<false>", "k_lloyd_accum", "k_lloyd_hits",  # an earlier job
+           "k_step<false>", "k_lloyd_accum", "k_lloyd_hits", "k_lloyd_hits",
+           "k_fill64", "k_dual_pairs", "k_bitonic", "k_bitonic", "k_orient_level",
+           "at::native::fill", "k_copy_probe"]
+    rows, t = [], 0
+    for n in seq:
+        name = n if n.startswith("at::") else f"void lf::{n}(int)"
+        rows.append([name, t, t + 1000])
+        t += 2000
+    _write(str(tr / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+           rows)
+    (tmp_path / "plain.json").write_text("log line\n" + _bench_line(98.7) + "\n")
+    (tmp_path / "traced.json").write_text(_bench_line(102.5) + "\n")
+    out = tmp_path / "out"
+    out.mkdir()
+    bench.summarize_trace(str(tr), str(tmp_path / "plain.json"), str(tmp_path / "traced.json"),
+                          str(out))
+    step = (out / "k_step_c3_trace.md").read_text()
+    assert "| k_step<false> | 8000 | 97.9 | 95.7 | 106.7 | 94.40% |" in step
+    assert "(97.9 us over 8000 launches)" in step and "102.5 us" in step and "98.7 us" in step
+    post = (out / "post_c3_trace.md").read_text()
+    assert "## Lloyd re-seed: 3 launches, 0.00 ms" in post
+    assert "## dual mesh: 5 launches" in post
+    assert "| k_lloyd_hits | 2 | 2.0 |" in post
+    assert "k_fill64 | 1 |" in post.split("## dual mesh")[1]
+    assert "at::native" not in post and "k_copy_probe" not in post
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
