@@ -356,6 +356,53 @@ def test_overflow_rows_in_register_slots(lf, orc):
         U = f32(O)
 
 
+def test_overflow_rows_in_wide_path(lf, orc):
+    """An overflow row of seven layers whose neighbours add three more (ten:
+    the row leaves the register slots after its neighbours were merged), and
+    a row reading two overflow rows with eleven layers between them; three
+    teacher-forced steps against the oracle, every row."""
+    lfb, ctx = lf
+    nx = 16
+    mesh = I.torus_grid(nx, nx)
+    L = orc.operator(mesh.V, mesh.F, 0)
+    n_s = 14
+    nb = lambda v: [int(c) for c in L[1][L[0][v]:L[0][v + 1]] if c != v]
+    rows = [{n_s: 1.0} for _ in range(mesh.n_v)]
+    rows[0] = {c: 0.1 + 0.02 * c for c in range(7)}  # 7 entries
+    for j, u in enumerate(nb(0)[:3]):
+        rows[u] = {7 + j: 0.6, n_s: 0.4}
+    far = 8 + nx * 8
+    rows[far] = {c: 0.2 for c in range(3, 9)}  # 6 entries
+    rows[far + 2] = {c: 0.2 for c in range(8, 14)}  # 6 entries
+    ptr = np.zeros(mesh.n_v + 1, np.int64)
+    col, val = [], []
+    for i, r in enumerate(rows):
+        tot = sum(r.values())
+        for c in sorted(r):
+            col.append(c)
+            val.append(r[c] / tot)
+        ptr[i + 1] = len(col)
+    U = f32((ptr, np.array(col, np.int32), np.array(val)))
+
+    def union(v):
+        seen = set()
+        for u in [v] + nb(v):
+            seen |= set(rows[u])
+        return len(seen)
+
+    assert union(0) == 11 and union(far + 1) == 12  # with the base layer
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, np.arange(n_s, dtype=np.int32) + 40)
+    say("overflow rows in the wide path")
+    for t in range(3):
+        gpu_load(f, U)
+        f.step(1)
+        G = as_oracle(f.export())
+        O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
+        check_step(G, O, info["margin"], what=f"overflow wide t={t}", max_guarded_frac=0.05)
+        U = f32(O)
+
+
 def _bipyramid(k):
     """Closed surface of 2k triangles: two apexes over a ring of k vertices
     (apex degree k, ring degree 4)."""
