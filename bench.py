@@ -128,6 +128,70 @@ def summarize_counters(fetch_dir, write_dir, copyf_dir, copyw_dir, probe_mib, ou
     print(json.dumps(d))
 
 
+def state_probe(level: int, seeds_n: int, warm: int, steps: int):
+    """C3 job advanced `warm` steps from its seeds, then `steps` more (for
+    per-dispatch counters of the step kernel in a mid-job state)."""
+    import paper_1804_09152_amd as lfb
+    from paper_1804_09152_amd import inputs as I
+    import torch
+    lfb.load()
+    mesh, seeds = I.config_c3(level=level, n_seeds=seeds_n)
+    ctx = lfb.Context(0)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, lfb.LF_OP_COTAN)
+    f = lfb.Fields(m, seeds)
+    f.step(warm)
+    torch.cuda.synchronize()
+    log(f"state probe: {warm} steps done")
+    f.step(steps)
+    torch.cuda.synchronize()
+    log(f"state probe: {steps} more steps done")
+    f.close()
+    m.close()
+
+
+def summarize_instructions(pmc_dir: str, out_path: str, last: int = 10):
+    """Per-wavefront instruction counts of the step kernel over its last
+    `last` dispatches, and the VALU issue time they imply."""
+    import collections
+    import csv
+    import glob
+    per = collections.defaultdict(list)
+    for fn in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            if "k_step<false>" in r["Kernel_Name"]:
+                per[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    m = {k: sum(v[-last:]) / len(v[-last:]) for k, v in per.items()}
+    waves = m["SQ_WAVES"]
+    valu, salu = m["SQ_INSTS_VALU"] / waves, m["SQ_INSTS_SALU"] / waves
+    lanes = m["SQ_THREAD_CYCLES_VALU"] / (m["SQ_INSTS_VALU"] * 64)
+    simds, ghz = 1024, 2.4
+    issue_us = valu * waves * 4 / simds / (ghz * 1e3)
+    lines = ["# Instructions of the step kernel: C3 job, mid-job state", "",
+             "Commands (one MI355X, from the repository root):", "", "```",
+             "cd /tmp && export TMPDIR=/tmp",
+             "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_THREAD_CYCLES_VALU "
+             "SQ_INSTS_BRANCH SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES \\",
+             "    --output-format csv -d <out> -o run -- python3 <repo>/bench.py --state-probe 10",
+             "python3 <repo>/bench.py --instr-summary <out>",
+             "```", "",
+             f"Step 1,000 to 1,010 of the C3 job (icosphere level 9, 16,384 seeds); means over "
+             f"the last {last} dispatches.", "",
+             "| per wavefront | value |", "|---|---|",
+             f"| wavefronts per launch | {waves:,.0f} |",
+             f"| VALU instructions | {valu:,.0f} |",
+             f"| SALU instructions | {salu:,.0f} |",
+             f"| branch instructions | {m['SQ_INSTS_BRANCH'] / waves:,.0f} |",
+             f"| active lanes per VALU instruction | {lanes:.1%} |", "",
+             f"VALU issue: {valu:,.0f} instructions x {waves:,.0f} wavefronts x 4 cycles / "
+             f"{simds:,} SIMDs / {ghz} GHz = {issue_us:.1f} us per launch, against the step's "
+             "97-99 us", "(kernel trace summary of the same job): the step is bound by "
+             "VALU issue, not by HBM.", ""]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines))
+    print(json.dumps({"valu_per_wave": valu, "salu_per_wave": salu, "waves": waves,
+                      "lanes": lanes, "valu_issue_us": issue_us}))
+
+
 def _kname(name: str) -> str:
     import re
     m = re.search(r"(k_[A-Za-z0-9_]+(<[a-z]+>)?|__amd_rocclr_[A-Za-z]+)", name)
@@ -476,10 +540,22 @@ def main():
     ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_DIR", "PLAIN_JSON", "TRACE_JSON"),
                     help="only summarize a rocprofv3 kernel trace of the C3 section into "
                          "profiles/k_step_c3_trace.md and profiles/post_c3_trace.md")
+    ap.add_argument("--state-probe", type=int, default=0, metavar="STEPS",
+                    help="only advance the C3 job 1,000 steps, then STEPS more (for counters)")
+    ap.add_argument("--instr-summary", metavar="PMC_DIR",
+                    help="only summarize a rocprofv3 SQ counter run of --state-probe into "
+                         "profiles/k_step_c3_instructions.md")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB ten times (calibrates "
                          "the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.instr_summary:
+        summarize_instructions(args.instr_summary,
+                               os.path.join(ROOT, "profiles", "k_step_c3_instructions.md"))
+        return
+    if args.state_probe:
+        state_probe(args.level, args.seeds, 1000, args.state_probe)
+        return
     if args.trace_summary:
         summarize_trace(*args.trace_summary, out_dir=os.path.join(ROOT, "profiles"))
         return

@@ -102,3 +102,25 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_instruction_summary(tmp_path, monkeypatch):
+    """Per-wavefront counts over the last dispatches of the scalar step
+    kernel, and the VALU issue time they imply."""
+    d = tmp_path / "sq"
+    rows = []
+    for k, waves in enumerate([10.0, 40968.0, 40968.0]):  # the first is not among the last 2
+        for name, v in [("SQ_WAVES", waves), ("SQ_INSTS_VALU", 1000.0 * waves),
+                        ("SQ_INSTS_SALU", 500.0 * waves), ("SQ_INSTS_BRANCH", 300.0 * waves),
+                        ("SQ_THREAD_CYCLES_VALU", 0.5 * 64 * 1000.0 * waves)]:
+            rows.append([STEP, name, v])
+            rows.append([TYPED, name, 7 * v])
+    _write(str(d / "run_counter_collection.csv"), ["Kernel_Name", "Counter_Name", "Counter_Value"],
+           rows)
+    out = tmp_path / "instr.md"
+    bench.summarize_instructions(str(d), str(out), last=2)
+    text = out.read_text()
+    assert "| VALU instructions | 1,000 |" in text and "| SALU instructions | 500 |" in text
+    assert "| active lanes per VALU instruction | 50.0% |" in text
+    issue = 1000 * 40968 * 4 / 1024 / 2400
+    assert f"= {issue:.1f} us per launch" in text
