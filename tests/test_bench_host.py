@@ -7,8 +7,6 @@ import os
 import subprocess
 import sys
 
-import pytest
-
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
@@ -104,12 +102,12 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in (r.stdout + r.stderr)
 
 
-def test_instruction_summary(tmp_path, monkeypatch):
+def test_instruction_summary(tmp_path):
     """Per-wavefront counts over the last dispatches of the scalar step
     kernel, and the VALU issue time they imply."""
     d = tmp_path / "sq"
     rows = []
-    for k, waves in enumerate([10.0, 40968.0, 40968.0]):  # the first is not among the last 2
+    for waves in [10.0, 40968.0, 40968.0]:  # the first is not among the last 2
         for name, v in [("SQ_WAVES", waves), ("SQ_INSTS_VALU", 1000.0 * waves),
                         ("SQ_INSTS_SALU", 500.0 * waves), ("SQ_INSTS_BRANCH", 300.0 * waves),
                         ("SQ_THREAD_CYCLES_VALU", 0.5 * 64 * 1000.0 * waves)]:
