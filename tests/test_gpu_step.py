@@ -143,7 +143,8 @@ def test_labels_parity_on_shared_state(lf, orc):
 def test_full_size_c3_one_step(lf, orc):
     """The roofline workload at full size (icosphere level 9, 2,621,442
     vertices, 16,384 cells) in the benchmark's launch configuration: one step
-    from a synthetic mid-run state, every row against the oracle."""
+    from a synthetic mid-run state and one from a denser one, every row
+    against the oracle."""
     lfb, ctx = lf
     mesh, seeds = I.config_c3()
     say("c3 operator")
@@ -161,6 +162,16 @@ def test_full_size_c3_one_step(lf, orc):
     O, info = orc.step(L, U, seeds.size, orc.default_params(), want_info=True)
     r = check_step(G, O, info["margin"], what="c3")
     say("c3", r)
+    # a denser state: up to five layers and the base per row (about 127,000
+    # rows in the overflow area, read from register slots and from the wide
+    # path)
+    U5 = f32(I.synthetic_state(mesh, seeds, np.random.default_rng(1), k=5))
+    assert (np.diff(U5[0]) > 4).sum() > 100000
+    say("c3 dense step")
+    gpu_load(f, U5)
+    f.step(1)
+    O5, info5 = orc.step(L, U5, seeds.size, orc.default_params(), want_info=True)
+    say("c3 dense", check_step(as_oracle(f.export()), O5, info5["margin"], what="c3 dense"))
     # from seeds too: 5 free steps, teacher-forced comparison of the last
     f.reset(seeds)
     f.step(4)
