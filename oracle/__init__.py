@@ -33,7 +33,13 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
              faces, a miss keeps the seed, collision rule cases.
   dual_mesh  pinned: hand-built adjacency cases, regular lattice on a torus
              (every dual vertex of degree 6, Euler characteristic 0), sphere
-             case (Euler characteristic 2) against the convex hull of seeds.
+             case (Euler characteristic 2) against the convex hull of seeds;
+             spurious-triangle removal (Section 5.2): six octahedral cells plus
+             a small cell in one octant, whose known dual is the octahedron
+             with the covered face replaced by the fan around the small cell
+             (one triangle removed), and no removal without a cell of degree 3.
+  step(threads > 1) pinned: identical, bit for bit, to the one-thread step
+             (rows are independent; blocks joined in row order).
 """
 from __future__ import annotations
 
@@ -53,7 +59,7 @@ def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (plain -O2, IEEE arithmetic)."""
     src = os.path.join(_HERE, "oracle.c")
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-fopenmp",
                                "-o", _SO, src, "-lm"])
     return _SO
 
@@ -89,13 +95,16 @@ def _load():
         lib.orc_init.argtypes = [C.c_int32, P, C.c_int32, P, C.POINTER(P), C.POINTER(P)]
         lib.orc_step.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, C.POINTER(Params),
                                  P, C.POINTER(P), C.POINTER(P), P, P, P]
+        lib.orc_step_threads.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P,
+                                         C.POINTER(Params), P, C.POINTER(P), C.POINTER(P), P, P,
+                                         P, P, C.c_int32]
         lib.orc_labels.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P]
         lib.orc_lloyd.argtypes = [C.c_int32, P, C.c_int32, P, C.c_int32, P, P, P, P, P, P, P]
         lib.orc_dual_mesh.argtypes = [C.c_int32, P, C.c_int32, P, C.c_int32, P, P, P, P,
                                       C.c_double, C.POINTER(_Dual)]
         lib.orc_dual_free.argtypes = [C.POINTER(_Dual)]
-        for f in ("orc_operator", "orc_init", "orc_step", "orc_labels", "orc_lloyd",
-                  "orc_dual_mesh"):
+        for f in ("orc_operator", "orc_init", "orc_step", "orc_step_threads", "orc_labels",
+                  "orc_lloyd", "orc_dual_mesh"):
             getattr(lib, f).restype = C.c_int
         _lib = lib
     return _lib
@@ -176,8 +185,20 @@ def init(n_v: int, seeds):
     return ptr, _take(cp, n_v, np.int32), _take(vp, n_v, np.float64)
 
 
-def step(L, U, n_s: int, params: dict, want_info: bool = False):
-    """One time step.  L, U: CSR triples.  Returns U' (and info dict)."""
+def host_threads() -> int:
+    """Threads for the row-block oracle: the host's CPUs, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def step(L, U, n_s: int, params: dict, want_info: bool = False, threads: int = 1):
+    """One time step.  L, U: CSR triples.  Returns U' (and info dict with
+    margin, smargin (rows-of-interest decisions only), skel, events).
+    threads > 1 splits the rows into blocks run in parallel; the result is
+    the same for any thread count."""
     lib = _load()
     Lp, Lc, Lv = (np.ascontiguousarray(L[0], np.int64), np.ascontiguousarray(L[1], np.int32),
                   np.ascontiguousarray(L[2], np.float64))
@@ -186,25 +207,33 @@ def step(L, U, n_s: int, params: dict, want_info: bool = False):
     n_v = Lp.size - 1
     Op = np.zeros(n_v + 1, dtype=np.int64)
     margin = np.zeros(n_v, dtype=np.float64)
+    smargin = np.zeros(n_v, dtype=np.float64)
     skel = np.zeros(n_v, dtype=np.int32)
     ev = np.zeros(1, dtype=np.int64)
     prm = _params(params)
     cp, vp = C.c_void_p(), C.c_void_p()
-    _check(lib.orc_step(n_v, n_s, _p(Lp), _p(Lc), _p(Lv), _p(Up), _p(Uc), _p(Uv), C.byref(prm),
-                        _p(Op), C.byref(cp), C.byref(vp), _p(margin), _p(skel), _p(ev)), "step")
+    if threads == 1:
+        rc = lib.orc_step(n_v, n_s, _p(Lp), _p(Lc), _p(Lv), _p(Up), _p(Uc), _p(Uv), C.byref(prm),
+                          _p(Op), C.byref(cp), C.byref(vp), _p(margin), _p(skel), _p(ev))
+        smargin = None
+    else:
+        rc = lib.orc_step_threads(n_v, n_s, _p(Lp), _p(Lc), _p(Lv), _p(Up), _p(Uc), _p(Uv),
+                                  C.byref(prm), _p(Op), C.byref(cp), C.byref(vp), _p(margin),
+                                  _p(smargin), _p(skel), _p(ev), int(threads))
+    _check(rc, "step")
     nnz = int(Op[-1])
     out = (Op, _take(cp, nnz, np.int32), _take(vp, nnz, np.float64))
     if want_info:
-        return out, {"margin": margin, "skel": skel, "events": int(ev[0])}
+        return out, {"margin": margin, "smargin": smargin, "skel": skel, "events": int(ev[0])}
     return out
 
 
-def run(L, U, n_s: int, params: dict, steps: int, record=None):
+def run(L, U, n_s: int, params: dict, steps: int, record=None, threads: int = 1):
     """Free-running steps; record(t, U) is called after every step if given."""
     skel_total = 0
     events = 0
     for t in range(steps):
-        U, info = step(L, U, n_s, params, want_info=True)
+        U, info = step(L, U, n_s, params, want_info=True, threads=threads)
         skel_total += int(info["skel"].sum())
         events += info["events"]
         if record is not None:

@@ -233,130 +233,202 @@ static void isort_i32(int32_t* a, int32_t n) {
 }
 
 /* ---- one time step ----------------------------------------------------------
- * Algorithm 1, body of the time loop:
- *   L_t = Phi L^T                                   (SpGEMM)
- *   for every vertex i (column of Phi):
- *     irows = (Phi(:,i) > 0) or (Phi(:,i) = 0 and L_t(:,i) > 0);  n_i = |irows|
- *     for j, k, l over irows:
- *       sum = sum_l 1/2 (a_jl - a_kl) L_t(l,i) + (w_jl - w_kl) Phi(l,i)
- *       d  += -(mu/n_i) (sum - e_jk sqrt(Phi(j,i) Phi(k,i)))
- *     Phi(j,i) += d dt, clamped to [0, 1]
- *   normalise each column by the sum of its nonzeros.
- * Equations (11)-(13) are the same update written as a PDE.
+ * The explicit Euler step of Section 3 (equations (11)-(13)) restricted to
+ * the rows of interest of Algorithm 1, row by row in U = Phi^T terms.
+ *
+ * For vertex i: the field Laplacian lambda_k = L_t(k, i) = sum_u L(i,u) U(u,k)
+ * (the sparse product of Section 3.2), the current values phi_k = U(i, k),
+ * and the rows of interest S: layers with phi_k > 0, or phi_k = 0 with
+ * lambda_k > 0 (growth where the field Laplacian is positive).  n = |S|.
+ * For every layer m of S (the paper's i in equation (11)):
+ *   dphi_m/dt = - sum_{j in S} (mu/n) ( sum_{k in S} [ (w_mk - w_jk) phi_k
+ *                   + (a_mk - a_jk) lambda_k / 2 ]  +  (dg_m - dg_j) ),
+ * the g-difference of equation (12) being dg_m - dg_j = -e_mj sqrt(phi_m phi_j)
+ * (the gradient coefficients enter linearly, see the readings); the Euler
+ * step of equation (13) v_m = phi_m + dt dphi_m/dt, clamped to [0, 1]; and
+ * the row is normalised by the sum of its clamped values (Section 4,
+ * normalization).
  * Reading (Jacobi): every value of the step is computed from the fields of
- * the previous step; Section 4 describes the update as producing an updated
- * copy of Phi-hat.  Reading (prune): after normalisation entries below theta
- * are dropped (theta = 0 keeps every positive entry); zeros are never stored.
- * In U = Phi^T terms, L_t(l,i) = sum_u L(i,u) U(u,l). */
+ * the previous step (Section 4: the update produces an updated copy).
+ * Reading (prune): after normalisation entries below theta are dropped
+ * (theta = 0 keeps every positive entry); zeros are never stored. */
+
+/* per-row work arrays (one set per thread), n_r = n_s + 1 long */
+typedef struct {
+  double *lam, *phi, *pre, *upd;
+  char* touched;
+  int32_t *list, *irows;
+} row_ws;
+
+static void ws_free(row_ws* w) {
+  free(w->lam); free(w->phi); free(w->pre); free(w->upd);
+  free(w->touched); free(w->list); free(w->irows);
+}
+
+static int ws_alloc(row_ws* w, int32_t n_r) {
+  memset(w, 0, sizeof(*w));
+  w->lam = (double*)calloc((size_t)n_r, sizeof(double));
+  w->phi = (double*)calloc((size_t)n_r, sizeof(double));
+  w->pre = (double*)calloc((size_t)n_r, sizeof(double));
+  w->upd = (double*)calloc((size_t)n_r, sizeof(double));
+  w->touched = (char*)calloc((size_t)n_r, 1);
+  w->list = (int32_t*)calloc((size_t)n_r, sizeof(int32_t));
+  w->irows = (int32_t*)calloc((size_t)n_r, sizeof(int32_t));
+  if (!w->lam || !w->phi || !w->pre || !w->upd || !w->touched || !w->list || !w->irows) {
+    ws_free(w);
+    return ORC_ENOMEM;
+  }
+  return ORC_OK;
+}
+
+/* One row.  Appends the kept entries to (oc, ov); mg = smallest distance of
+ * any discrete decision from its threshold, smg = the same over the
+ * rows-of-interest decisions only; *ev counts a row whose clamped values
+ * sum to zero (left empty). */
+static int step_row(int32_t i, int32_t n_s, const int64_t* Lp, const int32_t* Lc,
+                    const double* Lv, const int64_t* Up, const int32_t* Uc, const double* Uv,
+                    const orc_params* P, row_ws* w, vi32* oc, vf64* ov, double* mg_out,
+                    double* smg_out, int32_t* skel_out, int64_t* ev) {
+  const int32_t n_r = n_s + 1, b = n_s;
+  int32_t nt = 0;
+  /* lambda: row i of L times U, over the layers met in the neighbourhood */
+  for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) {
+    const int32_t u = Lc[q];
+    for (int64_t p = Up[u]; p < Up[u + 1]; ++p) {
+      const int32_t l = Uc[p];
+      if (l < 0 || l >= n_r) return ORC_EINVAL;
+      if (!w->touched[l]) { w->touched[l] = 1; w->list[nt++] = l; w->lam[l] = 0.0; w->phi[l] = 0.0; }
+      w->lam[l] += Lv[q] * Uv[p];
+    }
+  }
+  for (int64_t p = Up[i]; p < Up[i + 1]; ++p) {
+    const int32_t l = Uc[p];
+    if (l < 0 || l >= n_r || Uv[p] < 0.0) return ORC_EINVAL;
+    if (!w->touched[l]) { w->touched[l] = 1; w->list[nt++] = l; w->lam[l] = 0.0; w->phi[l] = 0.0; }
+    w->phi[l] = Uv[p];
+  }
+  isort_i32(w->list, nt);
+  const double* lam = w->lam;
+  const double* phi = w->phi;
+
+  /* rows of interest, and the margins of their decisions */
+  double smg = INFINITY;
+  int32_t n = 0;
+  for (int32_t t = 0; t < nt; ++t) {
+    const int32_t l = w->list[t];
+    if (phi[l] > 0.0 || (phi[l] == 0.0 && lam[l] > 0.0)) w->irows[n++] = l;
+    if (phi[l] == 0.0 && fabs(lam[l]) < smg) smg = fabs(lam[l]);
+  }
+  if (skel_out) *skel_out = n;
+  const int32_t* S = w->irows;
+
+  /* equation (11) for every layer m of S, then the Euler step (13) */
+  for (int32_t mm = 0; mm < n; ++mm) {
+    const int32_t m = S[mm];
+    double rate = 0.0;
+    for (int32_t jj = 0; jj < n; ++jj) {
+      const int32_t j = S[jj];
+      double inner = 0.0;
+      for (int32_t kk = 0; kk < n; ++kk) {
+        const int32_t k = S[kk];
+        inner += (coef_w(m, k, b, P) - coef_w(j, k, b, P)) * phi[k] +
+                 0.5 * (coef_a(m, k, b, P) - coef_a(j, k, b, P)) * lam[k];
+      }
+      const double dg = -coef_e(m, j, b, P) * sqrt(phi[m] * phi[j]);
+      rate += -(P->mu / n) * (inner + dg);
+    }
+    const double v = phi[m] + rate * P->dt;
+    w->pre[mm] = v;
+    w->upd[mm] = v > 1.0 ? 1.0 : (v <= 0.0 ? 0.0 : v);
+  }
+
+  /* normalise by the sum of the clamped values, then prune */
+  double mg = smg, sum = 0.0;
+  for (int32_t jj = 0; jj < n; ++jj) sum += w->upd[jj];
+  if (n > 0 && sum > 0.0) {
+    for (int32_t jj = 0; jj < n; ++jj) {
+      const double v = w->upd[jj] / sum;
+      const double m = P->theta > 0.0 ? fabs(v - P->theta) : fabs(w->pre[jj]);
+      if (m < mg) mg = m;
+      if (v > 0.0 && v >= P->theta)
+        if (vi32_push(oc, S[jj]) || vf64_push(ov, v)) return ORC_ENOMEM;
+    }
+  } else if (n > 0) {
+    ++*ev; /* every value clamped to zero: the column is left empty */
+  }
+  if (mg_out) *mg_out = mg;
+  if (smg_out) *smg_out = smg;
+  for (int32_t t = 0; t < nt; ++t) w->touched[w->list[t]] = 0;
+  return ORC_OK;
+}
+
+int orc_step_threads(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc,
+                     const double* Lv, const int64_t* Up, const int32_t* Uc, const double* Uv,
+                     const orc_params* P, int64_t* Op, int32_t** Oc, double** Ov, double* margin,
+                     double* smargin, int32_t* skel, int64_t* events, int32_t threads) {
+  if (n_v <= 0 || n_s < 0 || !P || threads < 1) return ORC_EINVAL;
+  const int32_t n_r = n_s + 1;
+  if (P->n_types < 0 || (P->n_types > 0 && (!P->types || !P->tab))) return ORC_EINVAL;
+  for (int32_t l = 0; P->n_types > 0 && l < n_r; ++l)
+    if (P->types[l] < 0 || P->types[l] >= P->n_types) return ORC_EINVAL;
+  /* rows in `threads` contiguous blocks, each with its own work arrays and
+   * output; the blocks are joined in row order, so the result does not depend
+   * on the thread count */
+  const int32_t nb = threads < n_v ? threads : n_v;
+  vi32* boc = (vi32*)calloc((size_t)nb, sizeof(vi32));
+  vf64* bov = (vf64*)calloc((size_t)nb, sizeof(vf64));
+  int64_t* bev = (int64_t*)calloc((size_t)nb, sizeof(int64_t));
+  int* brc = (int*)calloc((size_t)nb, sizeof(int));
+  int rc = ORC_OK;
+  if (!boc || !bov || !bev || !brc) { rc = ORC_ENOMEM; goto done; }
+#pragma omp parallel for schedule(static, 1) num_threads(nb)
+  for (int32_t k = 0; k < nb; ++k) {
+    const int32_t i0 = (int32_t)((int64_t)n_v * k / nb), i1 = (int32_t)((int64_t)n_v * (k + 1) / nb);
+    row_ws w;
+    if (ws_alloc(&w, n_r)) { brc[k] = ORC_ENOMEM; continue; }
+    for (int32_t i = i0; i < i1 && !brc[k]; ++i) {
+      Op[i] = boc[k].n; /* block-relative for now */
+      brc[k] = step_row(i, n_s, Lp, Lc, Lv, Up, Uc, Uv, P, &w, &boc[k], &bov[k],
+                        margin ? margin + i : 0, smargin ? smargin + i : 0, skel ? skel + i : 0,
+                        &bev[k]);
+    }
+    ws_free(&w);
+  }
+  for (int32_t k = 0; k < nb; ++k)
+    if (brc[k]) { rc = brc[k]; goto done; }
+  {
+    int64_t total = 0, ev = 0;
+    for (int32_t k = 0; k < nb; ++k) { total += boc[k].n; ev += bev[k]; }
+    int32_t* oc = (int32_t*)malloc((size_t)(total ? total : 1) * sizeof(int32_t));
+    double* ov = (double*)malloc((size_t)(total ? total : 1) * sizeof(double));
+    if (!oc || !ov) { free(oc); free(ov); rc = ORC_ENOMEM; goto done; }
+    int64_t off = 0;
+    for (int32_t k = 0; k < nb; ++k) {
+      const int32_t i0 = (int32_t)((int64_t)n_v * k / nb), i1 = (int32_t)((int64_t)n_v * (k + 1) / nb);
+      for (int32_t i = i0; i < i1; ++i) Op[i] += off;
+      if (boc[k].n) {
+        memcpy(oc + off, boc[k].a, (size_t)boc[k].n * sizeof(int32_t));
+        memcpy(ov + off, bov[k].a, (size_t)boc[k].n * sizeof(double));
+      }
+      off += boc[k].n;
+    }
+    Op[n_v] = total;
+    if (events) *events = ev;
+    *Oc = oc;
+    *Ov = ov;
+  }
+done:
+  for (int32_t k = 0; boc && bov && k < nb; ++k) { free(boc[k].a); free(bov[k].a); }
+  free(boc); free(bov); free(bev); free(brc);
+  return rc;
+}
+
 int orc_step(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc, const double* Lv,
              const int64_t* Up, const int32_t* Uc, const double* Uv, const orc_params* P,
              int64_t* Op, int32_t** Oc, double** Ov, double* margin, int32_t* skel,
              int64_t* events) {
-  if (n_v <= 0 || n_s < 0 || !P) return ORC_EINVAL;
-  const int32_t n_r = n_s + 1, b = n_s;
-  if (P->n_types < 0 || (P->n_types > 0 && (!P->types || !P->tab))) return ORC_EINVAL;
-  for (int32_t l = 0; P->n_types > 0 && l < n_r; ++l)
-    if (P->types[l] < 0 || P->types[l] >= P->n_types) return ORC_EINVAL;
-  double* lam = (double*)calloc((size_t)n_r, sizeof(double));
-  double* phi = (double*)calloc((size_t)n_r, sizeof(double));
-  char* touched = (char*)calloc((size_t)n_r, 1);
-  int32_t* list = (int32_t*)malloc((size_t)n_r * sizeof(int32_t));
-  int32_t* irows = (int32_t*)malloc((size_t)n_r * sizeof(int32_t));
-  double* pre = (double*)malloc((size_t)n_r * sizeof(double));
-  double* upd = (double*)malloc((size_t)n_r * sizeof(double));
-  vi32 oc = {0, 0, 0};
-  vf64 ov = {0, 0, 0};
-  int rc = ORC_OK;
-  int64_t ev = 0;
-  if (!lam || !phi || !touched || !list || !irows || !pre || !upd) { rc = ORC_ENOMEM; goto done; }
-
-  for (int32_t i = 0; i < n_v; ++i) {
-    int32_t nt = 0;
-    /* column i of L_t = Phi L^T, accumulated over the vertices u of row i of L */
-    for (int64_t q = Lp[i]; q < Lp[i + 1]; ++q) {
-      int32_t u = Lc[q];
-      double wu = Lv[q];
-      for (int64_t p = Up[u]; p < Up[u + 1]; ++p) {
-        int32_t l = Uc[p];
-        if (l < 0 || l >= n_r) { rc = ORC_EINVAL; goto done; }
-        if (!touched[l]) { touched[l] = 1; list[nt++] = l; lam[l] = 0.0; phi[l] = 0.0; }
-        lam[l] += wu * Uv[p];
-      }
-    }
-    /* column i of Phi */
-    for (int64_t p = Up[i]; p < Up[i + 1]; ++p) {
-      int32_t l = Uc[p];
-      if (l < 0 || l >= n_r || Uv[p] < 0.0) { rc = ORC_EINVAL; goto done; }
-      if (!touched[l]) { touched[l] = 1; list[nt++] = l; lam[l] = 0.0; phi[l] = 0.0; }
-      phi[l] = Uv[p];
-    }
-    isort_i32(list, nt);
-
-    /* rows of interest */
-    double mg = INFINITY;
-    int32_t n = 0;
-    for (int32_t t = 0; t < nt; ++t) {
-      int32_t l = list[t];
-      if (phi[l] > 0.0 || (phi[l] == 0.0 && lam[l] > 0.0)) irows[n++] = l;
-      if (phi[l] == 0.0 && fabs(lam[l]) < mg) mg = fabs(lam[l]);
-    }
-    if (skel) skel[i] = n;
-
-    /* update: triple loop over the rows of interest (Jacobi: reads phi, lam) */
-    for (int32_t jj = 0; jj < n; ++jj) {
-      int32_t j = irows[jj];
-      double d = 0.0;
-      for (int32_t kk = 0; kk < n; ++kk) {
-        int32_t k = irows[kk];
-        double sum = 0.0;
-        for (int32_t ll = 0; ll < n; ++ll) {
-          int32_t l = irows[ll];
-          sum += 0.5 * (coef_a(j, l, b, P) - coef_a(k, l, b, P)) * lam[l] +
-                 (coef_w(j, l, b, P) - coef_w(k, l, b, P)) * phi[l];
-        }
-        d += -(P->mu / n) * (sum - coef_e(j, k, b, P) * sqrt(phi[j] * phi[k]));
-      }
-      double v = phi[j] + d * P->dt;
-      pre[jj] = v;
-      if (v > 1.0) v = 1.0;
-      if (v <= 0.0) v = 0.0;
-      upd[jj] = v;
-    }
-
-    /* normalise the column by the sum of its nonzeros */
-    double s = 0.0;
-    for (int32_t jj = 0; jj < n; ++jj) s += upd[jj];
-    Op[i] = oc.n;
-    if (n > 0 && s > 0.0) {
-      for (int32_t jj = 0; jj < n; ++jj) {
-        double v = upd[jj] / s;
-        if (P->theta > 0.0) {
-          if (fabs(v - P->theta) < mg) mg = fabs(v - P->theta);
-        } else if (fabs(pre[jj]) < mg) {
-          mg = fabs(pre[jj]);
-        }
-        if (v > 0.0 && v >= P->theta) {
-          if (vi32_push(&oc, irows[jj]) || vf64_push(&ov, v)) { rc = ORC_ENOMEM; goto done; }
-        }
-      }
-    } else if (n > 0) {
-      ++ev; /* every value clamped to zero: the column is left empty */
-    }
-    if (margin) margin[i] = mg;
-    for (int32_t t = 0; t < nt; ++t) touched[list[t]] = 0;
-  }
-  Op[n_v] = oc.n;
-  if (events) *events = ev;
-  /* hand the arrays over even when empty */
-  if (!oc.a) { oc.a = (int32_t*)malloc(sizeof(int32_t)); ov.a = (double*)malloc(sizeof(double)); }
-  *Oc = oc.a;
-  *Ov = ov.a;
-  oc.a = 0;
-  ov.a = 0;
-done:
-  free(lam); free(phi); free(touched); free(list); free(irows); free(pre); free(upd);
-  free(oc.a); free(ov.a);
-  return rc;
+  return orc_step_threads(n_v, n_s, Lp, Lc, Lv, Up, Uc, Uv, P, Op, Oc, Ov, margin, 0, skel,
+                          events, 1);
 }
 
 /* ---- labels -------------------------------------------------------------------

@@ -65,6 +65,16 @@ int orc_step(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc, con
              int64_t* Op /* n_v+1 */, int32_t** Oc, double** Ov,
              double* margin, int32_t* skel, int64_t* events);
 
+/* orc_step over `threads` contiguous blocks of rows (OpenMP when built with
+ * it; the blocks run one after the other otherwise).  Every row does the same
+ * arithmetic as in orc_step, so the result is identical for any thread count.
+ * smargin[n_v] (may be NULL) = smallest |L_t| over the row's zero entries,
+ * the margin of its rows-of-interest decisions alone. */
+int orc_step_threads(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc,
+                     const double* Lv, const int64_t* Up, const int32_t* Uc, const double* Uv,
+                     const orc_params* P, int64_t* Op, int32_t** Oc, double** Ov, double* margin,
+                     double* smargin, int32_t* skel, int64_t* events, int32_t threads);
+
 /* Sharp labels (Section 5.2 and Figure 10): argmax over the cell columns of
  * a row, lowest column on ties, -1 when the row has no cell entry.
  * gap[n_v] (may be NULL) = best minus second-best cell value (second = 0 if

@@ -28,7 +28,7 @@ lf_status host_oom() {
 }
 
 static lf_status fail(lf_status st, const std::string& msg) {
-  g_err = msg;
+  set_error(msg);
   return st;
 }
 
@@ -55,7 +55,7 @@ static float bits_float(unsigned long long u) {
   return x;
 }
 
-static StepArgs make_args(lf_fields* f, int parity) {
+StepArgs step_args(lf_fields* f, int parity) {
   StepArgs a;
   lf_mesh* m = f->mesh;
   a.lell = m->lell;
@@ -586,6 +586,23 @@ static hipEvent_t pool_event(std::vector<hipEvent_t>& pool, size_t k) {
 
 namespace lf {
 
+void book_steps(lf_fields* f, const StepStats* st, int64_t ok) {
+  for (int64_t k = 0; k < ok; ++k) {
+    f->skel_total += st[k].skel;
+    f->out_total += st[k].out;
+    f->in_total += st[k].in;
+    f->events_total += st[k].events;
+  }
+  f->cur = (int)((f->cur + ok) & 1);
+  f->steps += ok;
+  if (ok > 0) {
+    f->nnz = (int64_t)st[ok - 1].out;
+    f->csr_valid = false;
+    f->last_changed = st[ok - 1].changed;
+    f->last_dmax = bits_float(st[ok - 1].dmax);
+  }
+}
+
 // Enqueues n steps on the context stream, then asynchronous copies of the
 // failure flags and per-step counters and an event; does not wait.
 lf_status step_issue(lf_fields* f, int64_t n) {
@@ -619,7 +636,7 @@ lf_status step_issue(lf_fields* f, int64_t n) {
   LF_HIP(launch_reset_flags(f->flags, f->parts, n, s));
   size_t used = 0;
   for (int64_t k = 0; k < n; ++k) {
-    StepArgs a = make_args(f, (int)((f->cur + k) & 1));
+    StepArgs a = step_args(f, (int)((f->cur + k) & 1));
     a.parts = f->parts + k * kParts;
     a.step_idx = (uint32_t)k;
     a.measure = (f->measure_all || k == n - 1) ? 1u : 0u;
@@ -664,21 +681,7 @@ lf_status step_complete(lf_fields* f, int64_t* remaining) {
   const StepFlags fl = *f->flags_host;
   // steps before the first failed one are complete; the later ones did nothing
   const int64_t ok = fl.poisoned ? std::min<int64_t>(fl.fail_step, n) : n;
-  for (int64_t k = 0; k < ok; ++k) {
-    const StepStats& t = f->stats_pinned[k];
-    f->skel_total += t.skel;
-    f->out_total += t.out;
-    f->in_total += t.in;
-    f->events_total += t.events;
-  }
-  f->cur = (int)((f->cur + ok) & 1);
-  f->steps += ok;
-  if (ok > 0) {
-    f->nnz = (int64_t)f->stats_pinned[ok - 1].out;
-    f->csr_valid = false;
-    f->last_changed = f->stats_pinned[ok - 1].changed;
-    f->last_dmax = bits_float(f->stats_pinned[ok - 1].dmax);
-  }
+  book_steps(f, f->stats_pinned, ok);
   *remaining = n - ok;
   if (!fl.poisoned) return LF_OK;
   if (fl.poisoned & 2u) {

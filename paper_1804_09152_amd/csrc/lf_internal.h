@@ -216,6 +216,12 @@ lf_status step_complete(lf_fields* f, int64_t* remaining);
 // quiet: no row changed its label or its layers at or above tau, and no
 // value moved by more than eps
 bool chunk_quiet(const lf_fields* f, int64_t n, double eps);
+// step arguments over the fields' own buffers for a step that reads the
+// buffer of the given parity (the caller sets parts, step_idx and measure)
+StepArgs step_args(lf_fields* f, int parity);
+// books the first ok of the per-step counters st[]: totals, current buffer,
+// entry count and change measures of the last booked step
+void book_steps(lf_fields* f, const StepStats* st, int64_t ok);
 
 // device allocation helpers
 template <class T>

@@ -57,6 +57,19 @@ int main(void) {
       double* Ov = NULL;
       int64_t ev = 0;
       rc |= orc_step(NV, NS, Lp, Lc, Lv, Up, Uc, Uv, &P, Op, &Oc, &Ov, margin, skel, &ev);
+      {  // the row-block variant gives the same step
+        int64_t Op3[NV + 1];
+        int32_t* Oc3 = NULL;
+        double *Ov3 = NULL, sm[NV];
+        rc |= orc_step_threads(NV, NS, Lp, Lc, Lv, Up, Uc, Uv, &P, Op3, &Oc3, &Ov3, NULL, sm,
+                               NULL, NULL, 3);
+        if (!rc) {
+          for (int i = 0; i <= NV; ++i) rc |= Op3[i] != Op[i];
+          for (int64_t q = 0; !rc && q < Op[NV]; ++q) rc |= Oc3[q] != Oc[q] || Ov3[q] != Ov[q];
+        }
+        orc_free(Oc3);
+        orc_free(Ov3);
+      }
       orc_free(Uc);
       orc_free(Uv);
       Uc = Oc;

@@ -119,13 +119,57 @@ def _cyc(t):
     return tuple(int(x) for x in np.roll(t, -k))
 
 
-@pytest.mark.parametrize("name", list(CASES))
+def _octa(orc):
+    from tests.dual_cases import octahedron_plus_face
+    m, seeds, U, _, _ = octahedron_plus_face()
+    return m, seeds, 1, f32(U)
+
+
+DUAL_CASES = dict(CASES, octa_face_spurious=_octa)
+
+
+def check_dual(tris, adj, d, guarded_pairs):
+    """GPU dual mesh (triangles, curated adjacency) against the oracle's.
+    Outside the candidate pairs whose isoline verdict is a near-tie
+    (`guarded_pairs`, unordered) everything must match exactly: the curated
+    adjacency, the triangle set (a triangle may differ only if it has a
+    guarded pair as an edge, or if it lies in the neighbourhood of a cell of a
+    guarded pair, whose degree decides the spurious-triangle rule), and the
+    orientation of the common triangles when the oracle's propagation met no
+    conflict and no non-manifold edge."""
+    g_adj, o_adj = _csr_pairs(*adj), _csr_pairs(*d["A_d"])
+    und = lambda S: {(min(a, b), max(a, b)) for a, b in S}
+    diff = und(g_adj) ^ und(o_adj)
+    assert diff <= guarded_pairs, sorted(diff - guarded_pairs)[:10]
+    tg = {tuple(sorted(int(x) for x in t)) for t in tris}
+    to = {tuple(sorted(int(x) for x in t)) for t in d["tri"]}
+    X = {c for p in guarded_pairs for c in p}
+    nb = {}
+    for a, b in g_adj | o_adj:
+        nb.setdefault(a, set()).add(b)
+    near = [nb.get(x, set()) for x in X]
+
+    def allowed(t):
+        edges = {(t[0], t[1]), (t[0], t[2]), (t[1], t[2])}
+        return bool(edges & guarded_pairs) or any(set(t) <= n for n in near)
+
+    bad = [t for t in tg ^ to if not allowed(t)]
+    assert not bad, bad[:10]
+    if d["n_conflict"] == 0 and d["n_nonmanifold"] == 0:
+        og = {tuple(sorted(int(x) for x in t)): _cyc(t) for t in tris}
+        oo = {tuple(sorted(int(x) for x in t)): _cyc(t) for t in d["tri"]}
+        common = tg & to
+        assert all(og[t] == oo[t] for t in common)
+    return len(tg ^ to)
+
+
+@pytest.mark.parametrize("name", list(DUAL_CASES))
 def test_dual_mesh_parity(lf, orc, name):
     lfb, ctx = lf
-    mesh, seeds, op, U = CASES[name](orc)
+    mesh, seeds, op, U = DUAL_CASES[name](orc)
     m, f = _fields(lfb, ctx, mesh, seeds, op, U)
     say("dual", name)
-    tris, (rp, col) = f.dual_mesh(0.25)
+    tris, adj = f.dual_mesh(0.25)
     d = orc.dual_mesh(mesh.V, mesh.F, U, seeds, 0.25)
     # A_v and A_t: exact (thresholds on identical float32 values)
     assert _csr_pairs(*f.dual_matrix(0)) == _csr_pairs(*d["A_v"])
@@ -134,11 +178,11 @@ def test_dual_mesh_parity(lf, orc, name):
     assert np.array_equal(pairs, d["cand"])
     clear = d["cand_margin"] > 1e-12
     assert np.array_equal(state[clear], d["cand_state"][clear])
-    if clear.all():
-        assert _csr_pairs(rp, col) == _csr_pairs(*d["A_d"])
-        assert {tuple(sorted(t)) for t in tris} == {tuple(sorted(t)) for t in d["tri"]}
-        if d["n_conflict"] == 0 and d["n_nonmanifold"] == 0:
-            assert {_cyc(t) for t in tris} == {_cyc(t) for t in d["tri"]}
+    guarded = {(int(p), int(q)) for p, q in d["cand"][~clear]}
+    check_dual(tris, adj, d, guarded)
+    if name == "octa_face_spurious":
+        # the case exists for the spurious-triangle rule: one triangle removed
+        assert d["n_removed"] == 1 and len(tris) == 10
 
 
 def test_full_size_c3_post(lf, orc):
@@ -152,14 +196,18 @@ def test_full_size_c3_post(lf, orc):
     new_o, st_o, mg = orc.lloyd(mesh.V, mesh.F, U, seeds)
     clear = mg > 1e-9
     assert np.array_equal(new_g[clear], new_o[clear])
+    assert clear.mean() > 0.99, clear.mean()
     say("c3 dual")
-    tris, (rp, col) = f.dual_mesh(0.25)
+    tris, adj = f.dual_mesh(0.25)
     d = orc.dual_mesh(mesh.V, mesh.F, U, seeds, 0.25)
     assert _csr_pairs(*f.dual_matrix(0)) == _csr_pairs(*d["A_v"])
+    assert _csr_pairs(*f.dual_matrix(1)) == _csr_pairs(*d["A_t"])
     pairs, state = f.dual_candidates()
     assert np.array_equal(pairs, d["cand"])
     clear = d["cand_margin"] > 1e-12
     assert np.array_equal(state[clear], d["cand_state"][clear])
+    guarded = {(int(p), int(q)) for p, q in d["cand"][~clear]}
+    check_dual(tris, adj, d, guarded)
 
 
 def test_lloyd_rounds_entry_point(lf):

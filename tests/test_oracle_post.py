@@ -245,3 +245,52 @@ def test_manifold_rule(orc):
     d = orc.dual_mesh(V, F, U, seeds)
     i = [tuple(c) for c in d["cand"]].index((0, 1))
     assert d["cand_state"][i] == 2
+
+
+def test_spurious_triangle_removed(orc):
+    """Section 5.2, mesh construction: a cell with exactly three neighbours
+    that are neighbours of each other (here a small cell in one octant of an
+    octahedral arrangement) is covered by the 3-clique of those three; that
+    triangle is spurious and removed.  The result is known by construction:
+    the octahedron with the covered face replaced by the fan around the small
+    cell, a closed consistently oriented sphere."""
+    from tests.dual_cases import octahedron_plus_face
+    m, seeds, U, expect, covered = octahedron_plus_face()
+    d = orc.dual_mesh(m.V, m.F, U, seeds)
+    k = seeds.size
+    assert d["n_removed"] == 1
+    T = d["tri"]
+    got = {tuple(sorted(int(x) for x in t)) for t in T}
+    assert got == expect and covered not in got
+    # adjacency: the octahedron's 12 edges plus the small cell's 3
+    assert d["A_d"][1].size == 2 * 15
+    assert list(np.diff(d["A_d"][0])) == [5, 4, 5, 4, 5, 4, 3]
+    assert k - 15 + len(T) == 2  # Euler characteristic of the sphere
+    de = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+    key = de[:, 0].astype(np.int64) * k + de[:, 1]
+    assert np.unique(key).size == key.size  # every directed edge once
+    assert d["n_conflict"] == 0 and d["n_nonmanifold"] == 0
+    X = m.V[seeds]
+    n = np.cross(X[T[:, 1]] - X[T[:, 0]], X[T[:, 2]] - X[T[:, 0]])
+    assert (np.einsum("ij,ij->i", n, X[T].mean(1)) > 0).all()  # outward
+
+
+def test_three_mutual_neighbours_without_a_covered_cell(orc):
+    """The removal needs a cell of degree exactly three: with the seventh
+    cell gone, the octahedron's eight faces all stay (every cell has four
+    neighbours)."""
+    from tests.dual_cases import octahedron_plus_face
+    m, seeds, U, expect, covered = octahedron_plus_face()
+    seeds6 = seeds[:6]
+    ang = np.arccos(np.clip(m.V @ m.V[seeds6].T, -1.0, 1.0))
+    near = ang.min(1, keepdims=True)
+    ptr, col, val = [0], [], []
+    for v in range(m.n_v):
+        cs = np.nonzero(ang[v] - near[v, 0] < 0.08)[0]
+        w = np.where(ang[v, cs] == near[v, 0], 1.0, 0.6)
+        col += [int(c) for c in cs]
+        val += list(w / w.sum())
+        ptr.append(len(col))
+    U6 = (np.array(ptr, np.int64), np.array(col, np.int32), np.array(val))
+    d = orc.dual_mesh(m.V, m.F, U6, seeds6)
+    assert d["n_removed"] == 0 and len(d["tri"]) == 8

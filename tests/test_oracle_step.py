@@ -251,3 +251,21 @@ def test_voronoi_agreement_c1(orc):
     vor = np.argmin(Dd, 0)
     assert (lab[~tied] == vor[~tied]).mean() >= 0.99
     assert (lab >= 0).all()
+
+
+def test_row_blocks_give_the_same_step(orc):
+    """The row-block (threaded) step equals the one-thread step bit for bit,
+    also its margins and rows-of-interest sizes, on a jittered icosphere state
+    with bands and junctions."""
+    mesh, seeds = I.config_c2(level=5, n_seeds=64, seed=3)
+    L = orc.operator(mesh.V, mesh.F, 1)
+    p = orc.default_params()
+    U = orc.run(L, orc.init(mesh.n_v, seeds), 64, p, 80)[0]
+    A, ia = orc.step(L, U, 64, p, want_info=True)
+    for t in (2, 5, 16):
+        B, ib = orc.step(L, U, 64, p, want_info=True, threads=t)
+        for x, y in zip(A, B):
+            assert np.array_equal(x, y)
+        assert np.array_equal(ia["margin"], ib["margin"]) and np.array_equal(ia["skel"], ib["skel"])
+        # the rows-of-interest margin is part of the whole margin
+        assert (ib["smargin"] >= ib["margin"]).all()
