@@ -266,36 +266,91 @@ def summarize_trace(trace_dir: str, plain_json: str, traced_json: str, out_dir: 
         fh.write("\n".join(lines))
 
 
-def cpu_baseline(mesh, seeds, seconds: float, max_steps: int = 200):
-    import oracle
-    oracle.build()
-    log("cpu baseline: oracle operator")
-    L = oracle.operator(mesh.V, mesh.F, 1)
-    U = oracle.init(mesh.n_v, seeds)
-    P = oracle.default_params()
-    skel = 0
-    n = 0
-    t0 = time.perf_counter()
-    while n < max_steps:
-        U, info = oracle.step(L, U, seeds.size, P, want_info=True)
-        skel += int(info["skel"].sum())
-        n += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    log(f"cpu baseline: {n} steps in {dt:.1f} s")
-    model = "unknown"
+def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": skel / dt, "unit": "nnz-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} Euler steps of the same job from its seeds, FP64 C oracle, "
-                      f"one thread, operator build excluded ({dt:.1f} s)",
-            "host_cpu": model, "host_threads": os.cpu_count()}
+    return "unknown"
+
+
+def cpu_baseline(mesh, seeds, seconds: float, batch_items=None, max_steps: int = 200):
+    """The FP64 oracle on the host: the same job from its seeds on one thread
+    and on every host thread (rows in blocks, identical results), and the
+    batch workload with one mesh per thread.  Each leg stops at the first
+    chunk that ends past `seconds`; rates are rows-of-interest entries per
+    second of wall time (operator builds excluded)."""
+    import threading
+
+    import oracle
+    oracle.build()
+    threads = oracle.host_threads()
+    P = oracle.default_params()
+    log("cpu baseline: oracle operator")
+    L = oracle.operator(mesh.V, mesh.F, 1)
+
+    def single_mesh(th, chunk):
+        U = oracle.init(mesh.n_v, seeds)
+        skel, n = 0, 0
+        t0 = time.perf_counter()
+        while n < max_steps:
+            U, info = oracle.run(L, U, seeds.size, P, chunk, threads=th)
+            skel += info["skel_total"]
+            n += chunk
+            if time.perf_counter() - t0 >= seconds:
+                break
+        return skel, n, time.perf_counter() - t0
+
+    sk1, n1, dt1 = single_mesh(1, 1)
+    log(f"cpu baseline: one thread, {n1} steps in {dt1:.1f} s")
+    skm, nm, dtm = single_mesh(threads, 4)
+    log(f"cpu baseline: {threads} threads, {nm} steps in {dtm:.1f} s")
+    out = {"value": skm / dtm, "unit": "nnz-updates/s", "cores": threads, "kind": "oracle",
+           "sample": (f"first {nm} Euler steps of the same job from its seeds, FP64 C oracle, "
+                      f"rows in {threads} blocks on {threads} threads (results identical to one "
+                      f"thread), operator build excluded ({dtm:.1f} s)"),
+           "single_thread": {"value": sk1 / dt1, "cores": 1,
+                             "sample": f"first {n1} Euler steps, one thread ({dt1:.1f} s)"},
+           "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
+    if batch_items:
+        # one mesh per thread: the batch's meshes in order, each its own
+        # oracle run of `bsteps` steps, until the time is up
+        bsteps = 50
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:  # operator builds, not timed
+            ops = list(ex.map(lambda it: oracle.operator(it[0].V, it[0].F, 0), batch_items))
+        lock = threading.Lock()
+        state = {"next": 0, "skel": 0, "meshes": 0}
+        t0 = time.perf_counter()
+
+        def worker():
+            while True:
+                with lock:
+                    k = state["next"]
+                    if k >= len(batch_items) or time.perf_counter() - t0 >= seconds:
+                        return
+                    state["next"] = k + 1
+                bm, bs = batch_items[k]
+                _, info = oracle.run(ops[k], oracle.init(bm.n_v, bs), bs.size, P, bsteps)
+                with lock:
+                    state["skel"] += info["skel_total"]
+                    state["meshes"] += 1
+
+        ts = [threading.Thread(target=worker) for _ in range(threads)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        dtb = time.perf_counter() - t0
+        log(f"cpu baseline: batch, {state['meshes']} meshes x {bsteps} steps in {dtb:.1f} s")
+        out["batch_one_mesh_per_thread"] = {
+            "value": state["skel"] / dtb, "cores": threads,
+            "sample": (f"the first {state['meshes']} meshes of the batch workload, {bsteps} Euler "
+                       f"steps each from their seeds, one mesh per thread on {threads} threads, "
+                       f"operator builds excluded ({dtb:.1f} s)")}
+    return out
 
 
 def copy_roof(mib: int = 1024, reps: int = 10):
@@ -447,12 +502,60 @@ def run_batch(lfb, I, n_meshes: int, steps: int):
     }
 
 
-def run_serving(lfb, I, n_jobs: int, qps: float, steps: int, rounds: int, max_active: int,
+def run_graphs(lfb, I):
+    """Step chunks launched one by one against chunks replayed from captured
+    graphs: a jittered icosphere level 5 (10,242 vertices, 64 seeds) and
+    level 7 (the c2 mesh), 1,024 steps each, and the 256-torus batch, 512
+    steps; wall time of the step loop (results are identical)."""
+    import torch
+    ctx = lfb.Context(0)
+    out = {"what": "wall ms of the step loop, launches one by one vs 256-step chunks from a graph"}
+
+    def timed(fields, steps, reps=3):
+        best = []
+        for on in (False, True):
+            fields.use_graphs(on)
+            fields.step(256)  # captures (when on) and warms
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fields.step(steps)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            best.append(min(ts) * 1e3)
+        fields.use_graphs(False)
+        return {"launches_ms": best[0], "graphs_ms": best[1], "speedup": best[0] / best[1]}
+
+    for lv, k in ((5, 64), (7, 1024)):
+        mesh, seeds = I.config_c2(level=lv, n_seeds=k)
+        m = lfb.Mesh(ctx, mesh.V, mesh.F, lfb.LF_OP_COTAN)
+        f = lfb.Fields(m, seeds)
+        out[f"icosphere{lv}_1024_steps"] = timed(f, 1024)
+        log(f"graphs: icosphere {lv}: {out[f'icosphere{lv}_1024_steps']}")
+        f.close()
+        m.close()
+    items = I.batch_tori(256)
+    B = lfb.Batch(ctx, [(mm.V, mm.F) for mm, _ in items], lfb.LF_OP_GRAPH, [sd for _, sd in items])
+    out["batch_512_steps"] = timed(B, 512, reps=2)
+    log(f"graphs: batch: {out['batch_512_steps']}")
+    B.close()
+    return out
+
+
+def _mono_ms() -> float:
+    return time.clock_gettime(time.CLOCK_MONOTONIC) * 1e3
+
+
+def run_serving(lfb, I, n_jobs: int, rates, steps: int, rounds: int, max_active: int,
                 budget_gib: float):
+    """The serving stream at each offered rate, then the same jobs one at a
+    time with the plain calls.  Latency runs from a job's Poisson arrival to
+    its completion (the library's monotonic timestamps), so time the loop
+    spends before submitting counts against the server."""
     import numpy as np
     jobs = I.serving_jobs(n_jobs, seed=0)
-    base = {}
-    inputs = []
+    base, inputs = {}, []
     for j in jobs:
         lv = j["level"]
         if lv not in base:
@@ -460,55 +563,91 @@ def run_serving(lfb, I, n_jobs: int, qps: float, steps: int, rounds: int, max_ac
         rng = np.random.default_rng(j["seed"])
         m = I.jitter(base[lv], rng)
         inputs.append((m, I.seeds_uniform(m.n_v, j["n_seeds"], rng)))
-    arrivals = np.cumsum(np.random.default_rng(1).exponential(1.0 / qps, n_jobs))
-    log(f"serving: {n_jobs} jobs, levels {[j['level'] for j in jobs]}, {qps} jobs/s")
-    S = lfb.Server(0, int(budget_gib * (1 << 30)), max_active, 64)
-    # one small job first: loads the kernels and warms the allocator
-    wm, ws = inputs[0]
+    budget = int(budget_gib * (1 << 30))
+    log(f"serving: {n_jobs} jobs, levels {np.bincount([j['level'] for j in jobs], minlength=10)[5:]}")
+    S = lfb.Server(0, budget, max_active, 64)
+    wm, ws = inputs[0]  # one small job first: loads the kernels, warms the allocator
     w = S.submit(wm.V, wm.F, ws, 50, 1, True, lfb.LF_OP_COTAN)
     S.run()
     S.release(w)
-    ids = [None] * n_jobs
-    t0 = time.perf_counter()
-    nxt = 0
-    done = 0
-    while done < n_jobs:
-        now = time.perf_counter() - t0
-        while nxt < n_jobs and arrivals[nxt] <= now:
-            m, s = inputs[nxt]
-            ids[nxt] = S.submit(m.V, m.F, s, steps, rounds, True, lfb.LF_OP_COTAN)
-            nxt += 1
-        q, a, d = S.poll()
-        done = d - 1
-        if q == 0 and a == 0 and nxt < n_jobs:
-            time.sleep(max(0.0, min(1e-3, arrivals[nxt] - (time.perf_counter() - t0))))
-    wall = time.perf_counter() - t0
-    lat, qms, nsteps = [], [], 0
-    for i in ids:
-        r = S.result(i)
-        lat.append(r["latency_ms"])
-        qms.append(r["queue_ms"])
-        nsteps += r["steps"]
-        S.release(i)
-    peak = S.memory()[1]
     S.close()
-    lat = np.array(lat)
-    log(f"serving: p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms")
-    return {
-        "workload": (f"Poisson arrivals at {qps} jobs/s of {n_jobs} jobs, jittered icospheres "
-                     f"levels 5-9, 64*4^(level-5) seeds, cotangent operator, {steps} steps + "
-                     f"{rounds} Lloyd rounds + labels + dual mesh each"),
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "mean_queue_ms": float(np.mean(qms)),
-        "jobs_per_s": n_jobs / wall,
-        "offered_jobs_per_s": qps,
-        "wall_s": wall,
-        "euler_steps": int(nsteps),
-        "max_active": max_active,
-        "hbm_budget_gib": budget_gib,
-        "peak_admitted_gib": peak / (1 << 30),
-    }
+    out = {"workload": (f"Poisson arrivals of {n_jobs} jobs, jittered icospheres levels 5-9, "
+                        f"64*4^(level-5) seeds, cotangent operator, {steps} steps + {rounds} "
+                        f"Lloyd rounds + labels + dual mesh each"),
+           "max_active": max_active, "hbm_budget_gib": budget_gib, "rates": []}
+    for qps in rates:
+        arrivals = np.cumsum(np.random.default_rng(1).exponential(1.0 / qps, n_jobs)) * 1e3
+        S = lfb.Server(0, budget, max_active, 64)
+        ids = [None] * n_jobs
+        t0 = _mono_ms()
+        nxt, done = 0, 0
+        while done < n_jobs:
+            now = _mono_ms() - t0
+            while nxt < n_jobs and arrivals[nxt] <= now:
+                m, sd = inputs[nxt]
+                ids[nxt] = S.submit(m.V, m.F, sd, steps, rounds, True, lfb.LF_OP_COTAN)
+                nxt += 1
+            q, a, done = S.poll()
+            if q == 0 and a == 0 and nxt < n_jobs:
+                time.sleep(max(0.0, min(1e-3, (arrivals[nxt] - (_mono_ms() - t0)) * 1e-3)))
+        lat, qms, ends, nsteps = [], [], [], 0
+        for k, i in enumerate(ids):
+            r = S.result(i)
+            sub, adm, fin = S.times(i)
+            lat.append(fin - (t0 + arrivals[k]))
+            qms.append(adm - (t0 + arrivals[k]))
+            ends.append(fin - t0)
+            nsteps += r["steps"]
+            S.release(i)
+        peak = S.memory()[1]
+        ticks, launches = S.stats()
+        S.close()
+        lat = np.array(lat)
+        wall = max(ends) * 1e-3
+        log(f"serving at {qps} jobs/s: p50 {np.percentile(lat, 50):.1f} ms, "
+            f"p99 {np.percentile(lat, 99):.1f} ms, {n_jobs / wall:.2f} jobs/s")
+        out["rates"].append({
+            "offered_jobs_per_s": qps, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_to_admission_ms": float(np.mean(qms)),
+            "jobs_per_s": n_jobs / wall, "wall_s": wall, "euler_steps": int(nsteps),
+            "peak_charged_gib": peak / (1 << 30), "ticks": ticks, "grouped_launches": launches,
+            "arrivals_s": float(arrivals[-1] * 1e-3)})
+    # one job at a time, back to back, with the plain calls (mesh, fields,
+    # steps, Lloyd rounds, labels, dual mesh; results to host memory)
+    ctx = lfb.Context(0)
+    service = []
+    for m, sd in inputs:
+        t = _mono_ms()
+        M = lfb.Mesh(ctx, m.V, m.F, lfb.LF_OP_COTAN)
+        f = lfb.Fields(M, sd)
+        f.step(steps)
+        for _ in range(rounds):
+            ns, _ = f.lloyd_reseed()
+            f.reset(ns)
+            f.step(steps)
+        f.labels()
+        f.seeds()
+        f.dual_mesh(0.25)
+        f.close()
+        M.close()
+        service.append(_mono_ms() - t)
+    service = np.array(service)
+    solo = {"jobs_per_s": n_jobs / (service.sum() * 1e-3), "mean_service_ms": float(service.mean())}
+    # the same arrivals served first come first served by that one-at-a-time
+    # solver (its measured service times)
+    for r in out["rates"]:
+        arrivals = np.cumsum(np.random.default_rng(1).exponential(1.0 / r["offered_jobs_per_s"],
+                                                                 n_jobs)) * 1e3
+        fin, lat = 0.0, []
+        for a, sv in zip(arrivals, service):
+            fin = max(fin, a) + sv
+            lat.append(fin - a)
+        r["one_at_a_time_p50_ms"] = float(np.percentile(lat, 50))
+        r["one_at_a_time_p99_ms"] = float(np.percentile(lat, 99))
+        r["one_at_a_time_jobs_per_s"] = n_jobs / (fin * 1e-3)
+    out["one_at_a_time"] = solo
+    log(f"serving: one at a time {solo['jobs_per_s']:.2f} jobs/s")
+    return out
 
 
 def main():
@@ -519,19 +658,20 @@ def main():
     ap.add_argument("--euler-steps", type=int, default=2000)
     ap.add_argument("--level", type=int, default=9)
     ap.add_argument("--seeds", type=int, default=16384)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-post", action="store_true", help="skip Lloyd and dual mesh")
     ap.add_argument("--batch-meshes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=500)
-    ap.add_argument("--serve-jobs", type=int, default=24)
-    ap.add_argument("--serve-qps", type=float, default=2.0)
+    ap.add_argument("--serve-jobs", type=int, default=200)
+    ap.add_argument("--serve-qps", type=float, nargs="+", default=[4.0, 8.0])
     ap.add_argument("--serve-steps", type=int, default=1000)
     ap.add_argument("--serve-rounds", type=int, default=3)
-    ap.add_argument("--serve-active", type=int, default=8)
-    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-active", type=int, default=16)
+    ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-typed", action="store_true", help="skip the per-pair coefficient steps")
     ap.add_argument("--counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPYF_DIR", "COPYW_DIR"),
@@ -631,8 +771,9 @@ def main():
     wall = t1 - t0
     skel = st1["skeleton_total"] - st0["skeleton_total"]
     n_v = mesh.n_v
-    nnz_off = lfb.lf_mesh_operator(m.h) - n_v
-    op_bytes = 4 * (n_v + 1) + 8 * nnz_off + 4 * n_v
+    # the operator as CSR with its diagonal: 4 (n_v + 1) + 8 nnz(L)
+    nnz_l = lfb.lf_mesh_operator(m.h)
+    op_bytes = 4 * (n_v + 1) + 8 * nnz_l
     # per step: the operator, both row-pointer arrays, and the mean entries of
     # U_t and U_{t+1} over every step of the timed jobs
     steps_run = st1["steps"] - st0["steps"]
@@ -690,11 +831,14 @@ def main():
         out["c2"] = run_c2(lfb, I, 1000, 5, 3)
     if not args.no_batch:
         out["batch"] = run_batch(lfb, I, args.batch_meshes, args.batch_steps)
+    if not args.no_graphs:
+        out["graphs"] = run_graphs(lfb, I)
     if not args.no_serve:
         out["serving"] = run_serving(lfb, I, args.serve_jobs, args.serve_qps, args.serve_steps,
                                      args.serve_rounds, args.serve_active, args.serve_budget_gib)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, seeds, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(mesh, seeds, args.cpu_seconds,
+                                           I.batch_tori(args.batch_meshes))
     print(json.dumps(out), flush=True)
 
 

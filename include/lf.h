@@ -97,6 +97,17 @@ lf_status lf_mesh_operator(lf_mesh* mesh, int64_t* nnz, int32_t* rowptr, int32_t
 lf_status lf_fields_create(lf_mesh* mesh, const int32_t* seeds, int32_t n_s,
                            const lf_params* params, lf_fields** out);
 lf_status lf_fields_destroy(lf_fields* f);
+/* Fields from seeds grown into regions (Algorithm 1, first line; the
+ * Initialization paragraph of Section 3.2 suggests a vertex and its immediate
+ * neighbours): every vertex within `rings` edges of a seed starts with 1 in
+ * the layer of its nearest seed, ties to the lowest seed index, a seed always
+ * in its own layer; every other vertex with 1 in the base layer.  rings = 0
+ * is lf_fields_create; rings = 1 gives the 1-ring seeds.  Edges are those of
+ * the mesh's triangles.  Regions grow on the GPU, one launch per ring.
+ * lf_fields_reset (and so Lloyd rounds) grows the new seeds by the same
+ * rings.  LF_EINVAL for rings outside [0, 1024] or invalid seeds. */
+lf_status lf_fields_create_rings(lf_mesh* mesh, const int32_t* seeds, int32_t n_s, int32_t rings,
+                                 const lf_params* params, lf_fields** out);
 /* Fields from initial regions (Algorithm 1, first line: "seeds and/or
  * initial regions"): cell k starts as the vertices
  * region_vertices[region_ptr[k] .. region_ptr[k+1]), each with 1 in layer k;
@@ -112,7 +123,9 @@ lf_status lf_fields_create_regions(lf_mesh* mesh, const int32_t* region_ptr,
 /* Re-initialise from new regions (same count). */
 lf_status lf_fields_reset_regions(lf_fields* f, const int32_t* region_ptr,
                                   const int32_t* region_vertices);
-/* Re-initialise from new seeds (same count), as after a Lloyd re-seeding. */
+/* Re-initialise from new seeds (same count), as after a Lloyd re-seeding;
+ * fields made by lf_fields_create_rings grow the seeds by their rings, fields
+ * made from regions start from the single seed vertices. */
 lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds);
 /* Current seeds, int32[n_s] host. */
 lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds);
@@ -163,6 +176,14 @@ lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t che
  * steps; so always for the last step of a call). */
 lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta);
 lf_status lf_sync(lf_fields* f);
+/* on = 1: lf_step (and lf_step_until) runs whole chunks of 256 steps from a
+ * HIP graph captured on first use (the chunk's kernels only; the counters'
+ * copies to the host stay outside), one graph per starting buffer, captured
+ * again when storage grows or the coefficients change; chunks of other
+ * lengths, and launches timed by lf_step_timing, are launched one by one.
+ * Needs a stream other than the legacy default stream.  on = 0 (the
+ * default): every launch one by one.  Results are identical either way. */
+lf_status lf_fields_use_graphs(lf_fields* f, int32_t on);
 
 /* Export U.  Size query with NULL buffers (*nnz always written).  rowptr
  * int32[n_v+1], col int32[nnz], val float32[nnz]; host or device. */
@@ -262,16 +283,21 @@ lf_status lf_batch_labels(lf_batch* b, int32_t mesh, int32_t* labels);
 
 /* ---- serving: a continuous-batching job loop -------------------------------
  * Jobs (a mesh, seeds and a recipe) are queued on submission and admitted
- * while the HBM they will hold fits the budget and an active slot is free;
- * each active job runs on a stream of its own, so the work of all active
- * jobs overlaps on the GPU; a job's fields stay resident from admission to
+ * while the HBM they will hold fits the budget and an active slot is free.
+ * A job runs `steps` Euler steps, then `lloyd_rounds` times (re-seed,
+ * re-initialise, `steps` steps), then labels and optionally the dual mesh
+ * (with conv_eps > 0, each phase stops at convergence instead).  The steps of
+ * all active jobs advance together: each step launch covers the slices of
+ * every job that is stepping (one grouped kernel over their independent
+ * field objects), in ticks of `chunk` launches; jobs join at the tick after
+ * their admission and leave at the end of a phase.  Admission (mesh,
+ * operator, fields) and the work between phases (re-seeding, labels, dual
+ * mesh) run on a host worker thread per job, on the job's own stream, while
+ * the others keep stepping.  A job's fields stay resident from admission to
  * completion, and its memory is released as soon as it finishes, which lets
- * queued jobs in.  A job runs `steps` Euler steps, then `lloyd_rounds` times
- * (re-seed, re-initialise, `steps` steps), then labels and optionally the
- * dual mesh (with conv_eps > 0, each phase stops at convergence instead).
- * Each job computes exactly what it computes alone.  The caller
- * drives the loop with lf_server_poll (non-blocking apart from short waits
- * at job phase boundaries). */
+ * queued jobs in.  Each job computes exactly what it computes alone.  The
+ * caller drives the loop with lf_server_poll, which does not wait for the
+ * GPU. */
 typedef struct lf_server lf_server;
 typedef struct {
   const double* V;     /* float64[n_v*3] */
@@ -287,8 +313,8 @@ typedef struct {
   const int32_t* layer_types;  /* int32[n_s+1] (NULL when n_types = 0) */
   const double* table;         /* double[n_types*n_types*3] */
 } lf_job;
-/* hbm_budget: bytes the active jobs may hold (estimated per job from its
- * size); max_active: concurrent jobs; chunk: steps issued per job per poll. */
+/* hbm_budget: bytes the active jobs may hold; max_active: concurrent jobs;
+ * chunk: step launches per tick (1..256). */
 lf_status lf_server_create(int32_t device, int64_t hbm_budget, int32_t max_active, int32_t chunk,
                            lf_server** out);
 lf_status lf_server_destroy(lf_server* s);
@@ -314,8 +340,16 @@ lf_status lf_server_result(lf_server* s, int64_t id, int32_t* seeds, int32_t* la
                            int64_t* steps);
 /* Frees a finished job's results. */
 lf_status lf_server_release(lf_server* s, int64_t id);
-/* Bytes currently held by active jobs (estimate) and the peak so far. */
+/* Bytes charged to the budget by active jobs and the peak so far: per job
+ * the larger of an estimate from its size (used for admission) and what its
+ * mesh and fields actually hold (storage growth included). */
 lf_status lf_server_memory(lf_server* s, int64_t* in_use, int64_t* peak);
+/* Times of a job on the host's monotonic clock (CLOCK_MONOTONIC, ms):
+ * submission, admission (fields ready) and completion (0 until reached). */
+lf_status lf_server_times(lf_server* s, int64_t id, double* submit_ms, double* admit_ms,
+                          double* done_ms);
+/* Ticks issued and grouped step launches made so far. */
+lf_status lf_server_stats(lf_server* s, int64_t* ticks, int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,11 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
              values moving by at most eps (above that oscillation).
   init_regions pinned: single-vertex regions reproduce init(seeds); a
              region's vertices all start in its layer.
+  init_rings pinned: rings = 0 is init(seeds); on the regular torus grid an
+             isolated seed's regions hold 1, 7 and 19 vertices for 0, 1, 2
+             rings (the triangular lattice's hexagonal rings); a vertex between
+             two seeds goes to the lower index, a seed next to a lower seed
+             keeps itself; the nearest seed wins over a lower index.
   lloyd      pinned: hand-built single-cell cases with known centroids and hit
              faces, a miss keeps the seed, collision rule cases.
   dual_mesh  pinned: hand-built adjacency cases, regular lattice on a torus
@@ -93,6 +98,8 @@ def _load():
         lib.orc_operator.argtypes = [C.c_int32, P, C.c_int32, P, C.c_int32, P,
                                      C.POINTER(P), C.POINTER(P)]
         lib.orc_init.argtypes = [C.c_int32, P, C.c_int32, P, C.POINTER(P), C.POINTER(P)]
+        lib.orc_init_rings.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int32, C.c_int32, P,
+                                       C.POINTER(P), C.POINTER(P)]
         lib.orc_step.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, C.POINTER(Params),
                                  P, C.POINTER(P), C.POINTER(P), P, P, P]
         lib.orc_step_threads.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P,
@@ -103,7 +110,11 @@ def _load():
         lib.orc_dual_mesh.argtypes = [C.c_int32, P, C.c_int32, P, C.c_int32, P, P, P, P,
                                       C.c_double, C.POINTER(_Dual)]
         lib.orc_dual_free.argtypes = [C.POINTER(_Dual)]
-        for f in ("orc_operator", "orc_init", "orc_step", "orc_step_threads", "orc_labels",
+        lib.orc_run_threads.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P,
+                                        C.POINTER(Params), C.c_int32, C.c_int32, P,
+                                        C.POINTER(P), C.POINTER(P), P, P]
+        for f in ("orc_operator", "orc_init", "orc_init_rings", "orc_step", "orc_step_threads", "orc_run_threads",
+                  "orc_labels",
                   "orc_lloyd", "orc_dual_mesh"):
             getattr(lib, f).restype = C.c_int
         _lib = lib
@@ -194,6 +205,19 @@ def host_threads() -> int:
     return max(1, min(16, n))
 
 
+def init_rings(n_v: int, F, seeds, rings: int):
+    """Seeds grown by `rings` edge-rings: nearest seed, ties to the lowest
+    index (breadth-first search from every seed)."""
+    lib = _load()
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    ptr = np.zeros(n_v + 1, dtype=np.int64)
+    cp, vp = C.c_void_p(), C.c_void_p()
+    _check(lib.orc_init_rings(n_v, F.shape[0], _p(F), _p(seeds), seeds.size, rings, _p(ptr),
+                              C.byref(cp), C.byref(vp)), "init_rings")
+    return ptr, _take(cp, n_v, np.int32), _take(vp, n_v, np.float64)
+
+
 def step(L, U, n_s: int, params: dict, want_info: bool = False, threads: int = 1):
     """One time step.  L, U: CSR triples.  Returns U' (and info dict with
     margin, smargin (rows-of-interest decisions only), skel, events).
@@ -212,14 +236,9 @@ def step(L, U, n_s: int, params: dict, want_info: bool = False, threads: int = 1
     ev = np.zeros(1, dtype=np.int64)
     prm = _params(params)
     cp, vp = C.c_void_p(), C.c_void_p()
-    if threads == 1:
-        rc = lib.orc_step(n_v, n_s, _p(Lp), _p(Lc), _p(Lv), _p(Up), _p(Uc), _p(Uv), C.byref(prm),
-                          _p(Op), C.byref(cp), C.byref(vp), _p(margin), _p(skel), _p(ev))
-        smargin = None
-    else:
-        rc = lib.orc_step_threads(n_v, n_s, _p(Lp), _p(Lc), _p(Lv), _p(Up), _p(Uc), _p(Uv),
-                                  C.byref(prm), _p(Op), C.byref(cp), C.byref(vp), _p(margin),
-                                  _p(smargin), _p(skel), _p(ev), int(threads))
+    rc = lib.orc_step_threads(n_v, n_s, _p(Lp), _p(Lc), _p(Lv), _p(Up), _p(Uc), _p(Uv),
+                              C.byref(prm), _p(Op), C.byref(cp), C.byref(vp), _p(margin),
+                              _p(smargin), _p(skel), _p(ev), int(threads))
     _check(rc, "step")
     nnz = int(Op[-1])
     out = (Op, _take(cp, nnz, np.int32), _take(vp, nnz, np.float64))
@@ -229,7 +248,26 @@ def step(L, U, n_s: int, params: dict, want_info: bool = False, threads: int = 1
 
 
 def run(L, U, n_s: int, params: dict, steps: int, record=None, threads: int = 1):
-    """Free-running steps; record(t, U) is called after every step if given."""
+    """Free-running steps; record(t, U) is called after every step if given
+    (without it the steps loop in C)."""
+    if record is None:
+        lib = _load()
+        Lp, Lc, Lv = (np.ascontiguousarray(L[0], np.int64), np.ascontiguousarray(L[1], np.int32),
+                      np.ascontiguousarray(L[2], np.float64))
+        Up, Uc, Uv = (np.ascontiguousarray(U[0], np.int64), np.ascontiguousarray(U[1], np.int32),
+                      np.ascontiguousarray(U[2], np.float64))
+        n_v = Lp.size - 1
+        Op = np.zeros(n_v + 1, dtype=np.int64)
+        sk = np.zeros(1, dtype=np.int64)
+        ev = np.zeros(1, dtype=np.int64)
+        prm = _params(params)
+        cp, vp = C.c_void_p(), C.c_void_p()
+        _check(lib.orc_run_threads(n_v, n_s, _p(Lp), _p(Lc), _p(Lv), _p(Up), _p(Uc), _p(Uv),
+                                   C.byref(prm), int(steps), int(threads), _p(Op), C.byref(cp),
+                                   C.byref(vp), _p(sk), _p(ev)), "run")
+        nnz = int(Op[-1])
+        out = (Op, _take(cp, nnz, np.int32), _take(vp, nnz, np.float64))
+        return out, {"skel_total": int(sk[0]), "events": int(ev[0])}
     skel_total = 0
     events = 0
     for t in range(steps):

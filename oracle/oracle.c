@@ -9,6 +9,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -232,6 +233,84 @@ static void isort_i32(int32_t* a, int32_t n) {
   }
 }
 
+/* ---- seeds grown into rings ------------------------------------------------
+ * Algorithm 1 starts from "seeds and/or initial regions"; the Initialization
+ * paragraph of Section 3.2 suggests a vertex and its immediate neighbours.
+ * Reading: the region of seed k holds the vertices within `rings` edges of
+ * the mesh's triangles from s_k; a vertex within reach of several seeds
+ * belongs to the nearest, ties to the lowest seed index (so a seed keeps
+ * itself).  Plain definition: a breadth-first search from every seed, one
+ * after the other, keeping for each vertex the lexicographically smallest
+ * (distance, seed index). */
+int orc_init_rings(int32_t n_v, int32_t n_f, const int32_t* F, const int32_t* seeds, int32_t n_s,
+                   int32_t rings, int64_t* ptr, int32_t** col_out, double** val_out) {
+  if (check_faces(n_v, n_f, F) || !seeds || n_s < 1 || rings < 0) return ORC_EINVAL;
+  for (int32_t k = 0; k < n_s; ++k)
+    if (seeds[k] < 0 || seeds[k] >= n_v) return ORC_EINVAL;
+  /* vertex adjacency from the faces' edges (both directions, duplicates kept) */
+  int64_t* ap = (int64_t*)calloc((size_t)n_v + 1, sizeof(int64_t));
+  int32_t* aj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(6 * (int64_t)n_f + 1));
+  int32_t* best_d = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_v);
+  int32_t* best_k = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_v);
+  int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_v);
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_v);
+  int32_t* col = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_v);
+  double* val = (double*)malloc(sizeof(double) * (size_t)n_v);
+  int rc = ORC_OK;
+  if (!ap || !aj || !best_d || !best_k || !dist || !queue || !col || !val) { rc = ORC_ENOMEM; goto done; }
+  for (int64_t f = 0; f < n_f; ++f)
+    for (int e = 0; e < 3; ++e) {
+      ap[F[3 * f + e] + 1]++;
+      ap[F[3 * f + (e + 1) % 3] + 1]++;
+    }
+  for (int32_t v = 0; v < n_v; ++v) ap[v + 1] += ap[v];
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)n_v);
+    if (!fill) { rc = ORC_ENOMEM; goto done; }
+    memcpy(fill, ap, sizeof(int64_t) * (size_t)n_v);
+    for (int64_t f = 0; f < n_f; ++f)
+      for (int e = 0; e < 3; ++e) {
+        const int32_t a = F[3 * f + e], b = F[3 * f + (e + 1) % 3];
+        aj[fill[a]++] = b;
+        aj[fill[b]++] = a;
+      }
+    free(fill);
+  }
+  for (int32_t v = 0; v < n_v; ++v) { best_d[v] = INT32_MAX; best_k[v] = n_s; dist[v] = -1; }
+  for (int32_t k = 0; k < n_s; ++k) {
+    int32_t head = 0, tail = 0;
+    queue[tail++] = seeds[k];
+    dist[seeds[k]] = 0;
+    while (head < tail) {
+      const int32_t v = queue[head++];
+      if (dist[v] < best_d[v] || (dist[v] == best_d[v] && k < best_k[v])) {
+        best_d[v] = dist[v];
+        best_k[v] = k;
+      }
+      if (dist[v] == rings) continue;
+      for (int64_t q = ap[v]; q < ap[v + 1]; ++q)
+        if (dist[aj[q]] < 0) {
+          dist[aj[q]] = dist[v] + 1;
+          queue[tail++] = aj[q];
+        }
+    }
+    for (int32_t t = 0; t < tail; ++t) dist[queue[t]] = -1;
+  }
+  for (int32_t v = 0; v < n_v; ++v) {
+    ptr[v] = v;
+    col[v] = best_k[v]; /* n_s: the base layer */
+    val[v] = 1.0;
+  }
+  ptr[n_v] = n_v;
+  *col_out = col;
+  *val_out = val;
+  col = 0;
+  val = 0;
+done:
+  free(ap); free(aj); free(best_d); free(best_k); free(dist); free(queue); free(col); free(val);
+  return rc;
+}
+
 /* ---- one time step ----------------------------------------------------------
  * The explicit Euler step of Section 3 (equations (11)-(13)) restricted to
  * the rows of interest of Algorithm 1, row by row in U = Phi^T terms.
@@ -362,6 +441,94 @@ static int step_row(int32_t i, int32_t n_s, const int64_t* Lp, const int32_t* Lc
   return ORC_OK;
 }
 
+/* Rows in `nb` contiguous blocks, each with its own work arrays and output
+ * lists; kept across the steps of a run so that long runs allocate nothing
+ * per step. */
+typedef struct {
+  int32_t nb, n_r;
+  row_ws* ws;
+  vi32* oc;
+  vf64* ov;
+  int64_t* ev;
+  int* rc;
+} blocks;
+
+static void blocks_free(blocks* B) {
+  for (int32_t k = 0; k < B->nb; ++k) {
+    if (B->ws) ws_free(&B->ws[k]);
+    if (B->oc) free(B->oc[k].a);
+    if (B->ov) free(B->ov[k].a);
+  }
+  free(B->ws); free(B->oc); free(B->ov); free(B->ev); free(B->rc);
+  memset(B, 0, sizeof(*B));
+}
+
+static int blocks_alloc(blocks* B, int32_t nb, int32_t n_r) {
+  memset(B, 0, sizeof(*B));
+  B->nb = nb;
+  B->n_r = n_r;
+  B->ws = (row_ws*)calloc((size_t)nb, sizeof(row_ws));
+  B->oc = (vi32*)calloc((size_t)nb, sizeof(vi32));
+  B->ov = (vf64*)calloc((size_t)nb, sizeof(vf64));
+  B->ev = (int64_t*)calloc((size_t)nb, sizeof(int64_t));
+  B->rc = (int*)calloc((size_t)nb, sizeof(int));
+  if (!B->ws || !B->oc || !B->ov || !B->ev || !B->rc) { blocks_free(B); return ORC_ENOMEM; }
+  for (int32_t k = 0; k < nb; ++k)
+    if (ws_alloc(&B->ws[k], n_r)) { blocks_free(B); return ORC_ENOMEM; }
+  return ORC_OK;
+}
+
+/* One step of every row into the blocks' output lists; Op[i] is left
+ * block-relative.  The blocks run in parallel. */
+static int step_blocks(blocks* B, int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc,
+                       const double* Lv, const int64_t* Up, const int32_t* Uc, const double* Uv,
+                       const orc_params* P, int64_t* Op, double* margin, double* smargin,
+                       int32_t* skel) {
+  const int32_t nb = B->nb;
+#pragma omp parallel for schedule(static, 1) num_threads(nb)
+  for (int32_t k = 0; k < nb; ++k) {
+    const int32_t i0 = (int32_t)((int64_t)n_v * k / nb), i1 = (int32_t)((int64_t)n_v * (k + 1) / nb);
+    B->oc[k].n = 0;
+    B->ov[k].n = 0;
+    B->ev[k] = 0;
+    B->rc[k] = ORC_OK;
+    for (int32_t i = i0; i < i1 && !B->rc[k]; ++i) {
+      Op[i] = B->oc[k].n;
+      B->rc[k] = step_row(i, n_s, Lp, Lc, Lv, Up, Uc, Uv, P, &B->ws[k], &B->oc[k], &B->ov[k],
+                          margin ? margin + i : 0, smargin ? smargin + i : 0, skel ? skel + i : 0,
+                          &B->ev[k]);
+    }
+  }
+  for (int32_t k = 0; k < nb; ++k)
+    if (B->rc[k]) return B->rc[k];
+  return ORC_OK;
+}
+
+/* joins the blocks' outputs in row order into oc / ov (room for the total),
+ * makes Op absolute */
+static int64_t join_blocks(const blocks* B, int32_t n_v, int64_t* Op, int32_t* oc, double* ov) {
+  int64_t off = 0;
+  for (int32_t k = 0; k < B->nb; ++k) {
+    const int32_t i0 = (int32_t)((int64_t)n_v * k / B->nb);
+    const int32_t i1 = (int32_t)((int64_t)n_v * (k + 1) / B->nb);
+    for (int32_t i = i0; i < i1; ++i) Op[i] += off;
+    if (B->oc[k].n) {
+      memcpy(oc + off, B->oc[k].a, (size_t)B->oc[k].n * sizeof(int32_t));
+      memcpy(ov + off, B->ov[k].a, (size_t)B->oc[k].n * sizeof(double));
+    }
+    off += B->oc[k].n;
+  }
+  Op[n_v] = off;
+  return off;
+}
+
+static int64_t blocks_total(const blocks* B, int64_t* ev) {
+  int64_t t = 0, e = 0;
+  for (int32_t k = 0; k < B->nb; ++k) { t += B->oc[k].n; e += B->ev[k]; }
+  if (ev) *ev = e;
+  return t;
+}
+
 int orc_step_threads(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc,
                      const double* Lv, const int64_t* Up, const int32_t* Uc, const double* Uv,
                      const orc_params* P, int64_t* Op, int32_t** Oc, double** Ov, double* margin,
@@ -371,55 +538,26 @@ int orc_step_threads(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t*
   if (P->n_types < 0 || (P->n_types > 0 && (!P->types || !P->tab))) return ORC_EINVAL;
   for (int32_t l = 0; P->n_types > 0 && l < n_r; ++l)
     if (P->types[l] < 0 || P->types[l] >= P->n_types) return ORC_EINVAL;
-  /* rows in `threads` contiguous blocks, each with its own work arrays and
-   * output; the blocks are joined in row order, so the result does not depend
-   * on the thread count */
-  const int32_t nb = threads < n_v ? threads : n_v;
-  vi32* boc = (vi32*)calloc((size_t)nb, sizeof(vi32));
-  vf64* bov = (vf64*)calloc((size_t)nb, sizeof(vf64));
-  int64_t* bev = (int64_t*)calloc((size_t)nb, sizeof(int64_t));
-  int* brc = (int*)calloc((size_t)nb, sizeof(int));
-  int rc = ORC_OK;
-  if (!boc || !bov || !bev || !brc) { rc = ORC_ENOMEM; goto done; }
-#pragma omp parallel for schedule(static, 1) num_threads(nb)
-  for (int32_t k = 0; k < nb; ++k) {
-    const int32_t i0 = (int32_t)((int64_t)n_v * k / nb), i1 = (int32_t)((int64_t)n_v * (k + 1) / nb);
-    row_ws w;
-    if (ws_alloc(&w, n_r)) { brc[k] = ORC_ENOMEM; continue; }
-    for (int32_t i = i0; i < i1 && !brc[k]; ++i) {
-      Op[i] = boc[k].n; /* block-relative for now */
-      brc[k] = step_row(i, n_s, Lp, Lc, Lv, Up, Uc, Uv, P, &w, &boc[k], &bov[k],
-                        margin ? margin + i : 0, smargin ? smargin + i : 0, skel ? skel + i : 0,
-                        &bev[k]);
-    }
-    ws_free(&w);
-  }
-  for (int32_t k = 0; k < nb; ++k)
-    if (brc[k]) { rc = brc[k]; goto done; }
-  {
-    int64_t total = 0, ev = 0;
-    for (int32_t k = 0; k < nb; ++k) { total += boc[k].n; ev += bev[k]; }
+  blocks B;
+  int rc = blocks_alloc(&B, threads < n_v ? threads : n_v, n_r);
+  if (rc) return rc;
+  rc = step_blocks(&B, n_v, n_s, Lp, Lc, Lv, Up, Uc, Uv, P, Op, margin, smargin, skel);
+  if (!rc) {
+    int64_t ev = 0;
+    const int64_t total = blocks_total(&B, &ev);
     int32_t* oc = (int32_t*)malloc((size_t)(total ? total : 1) * sizeof(int32_t));
     double* ov = (double*)malloc((size_t)(total ? total : 1) * sizeof(double));
-    if (!oc || !ov) { free(oc); free(ov); rc = ORC_ENOMEM; goto done; }
-    int64_t off = 0;
-    for (int32_t k = 0; k < nb; ++k) {
-      const int32_t i0 = (int32_t)((int64_t)n_v * k / nb), i1 = (int32_t)((int64_t)n_v * (k + 1) / nb);
-      for (int32_t i = i0; i < i1; ++i) Op[i] += off;
-      if (boc[k].n) {
-        memcpy(oc + off, boc[k].a, (size_t)boc[k].n * sizeof(int32_t));
-        memcpy(ov + off, bov[k].a, (size_t)boc[k].n * sizeof(double));
-      }
-      off += boc[k].n;
+    if (!oc || !ov) {
+      free(oc); free(ov);
+      rc = ORC_ENOMEM;
+    } else {
+      join_blocks(&B, n_v, Op, oc, ov);
+      if (events) *events = ev;
+      *Oc = oc;
+      *Ov = ov;
     }
-    Op[n_v] = total;
-    if (events) *events = ev;
-    *Oc = oc;
-    *Ov = ov;
   }
-done:
-  for (int32_t k = 0; boc && bov && k < nb; ++k) { free(boc[k].a); free(bov[k].a); }
-  free(boc); free(bov); free(bev); free(brc);
+  blocks_free(&B);
   return rc;
 }
 
@@ -429,6 +567,86 @@ int orc_step(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc, con
              int64_t* events) {
   return orc_step_threads(n_v, n_s, Lp, Lc, Lv, Up, Uc, Uv, P, Op, Oc, Ov, margin, 0, skel,
                           events, 1);
+}
+
+/* n_steps free-running steps (orc_step_threads repeated), in C so that long
+ * trajectories need no round trip per step; the work arrays, block lists and
+ * the two field buffers are kept across steps.  U_in is not modified; the
+ * final fields are returned in (Op, Oc, Ov); *skel_total and *events sum the
+ * rows-of-interest sizes and the empty-row events over the steps. */
+int orc_run_threads(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc,
+                    const double* Lv, const int64_t* Up, const int32_t* Uc, const double* Uv,
+                    const orc_params* P, int32_t n_steps, int32_t threads, int64_t* Op,
+                    int32_t** Oc, double** Ov, int64_t* skel_total, int64_t* events) {
+  if (n_v <= 0 || n_s < 0 || n_steps < 0 || !P || threads < 1) return ORC_EINVAL;
+  const int32_t n_r = n_s + 1;
+  if (P->n_types < 0 || (P->n_types > 0 && (!P->types || !P->tab))) return ORC_EINVAL;
+  for (int32_t l = 0; P->n_types > 0 && l < n_r; ++l)
+    if (P->types[l] < 0 || P->types[l] >= P->n_types) return ORC_EINVAL;
+  blocks B;
+  int rc = blocks_alloc(&B, threads < n_v ? threads : n_v, n_r);
+  if (rc) return rc;
+  int64_t *p[2] = {0, 0}, cap = Up[n_v] > 0 ? Up[n_v] : 1;
+  int32_t *c[2] = {0, 0}, *skel = 0;
+  double* v[2] = {0, 0};
+  int64_t sk = 0, evs = 0;
+  int cur = 0;
+  for (int b = 0; b < 2; ++b) {
+    p[b] = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_v + 1));
+    c[b] = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+    v[b] = (double*)malloc(sizeof(double) * (size_t)cap);
+  }
+  skel = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_v);
+  if (!p[0] || !p[1] || !c[0] || !c[1] || !v[0] || !v[1] || !skel) { rc = ORC_ENOMEM; goto done; }
+  memcpy(p[0], Up, sizeof(int64_t) * ((size_t)n_v + 1));
+  if (Up[n_v]) {
+    memcpy(c[0], Uc, sizeof(int32_t) * (size_t)Up[n_v]);
+    memcpy(v[0], Uv, sizeof(double) * (size_t)Up[n_v]);
+  }
+  for (int32_t t = 0; t < n_steps; ++t) {
+    const int nx = 1 - cur;
+    rc = step_blocks(&B, n_v, n_s, Lp, Lc, Lv, p[cur], c[cur], v[cur], P, p[nx], 0, 0, skel);
+    if (rc) goto done;
+    int64_t e = 0;
+    const int64_t total = blocks_total(&B, &e);
+    if (total > cap) { /* both buffers grow, the current one keeps its contents */
+      const int64_t nc = total + total / 4 + 1024;
+      int32_t* c0 = (int32_t*)realloc(c[cur], sizeof(int32_t) * (size_t)nc);
+      if (c0) c[cur] = c0;
+      double* v0 = (double*)realloc(v[cur], sizeof(double) * (size_t)nc);
+      if (v0) v[cur] = v0;
+      free(c[nx]);
+      free(v[nx]);
+      c[nx] = (int32_t*)malloc(sizeof(int32_t) * (size_t)nc);
+      v[nx] = (double*)malloc(sizeof(double) * (size_t)nc);
+      if (!c0 || !v0 || !c[nx] || !v[nx]) { rc = ORC_ENOMEM; goto done; }
+      cap = nc;
+    }
+    join_blocks(&B, n_v, p[nx], c[nx], v[nx]);
+    for (int32_t i = 0; i < n_v; ++i) sk += skel[i];
+    evs += e;
+    cur = nx;
+  }
+  {
+    const int64_t nnz = p[cur][n_v];
+    int32_t* oc = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz ? nnz : 1));
+    double* ov = (double*)malloc(sizeof(double) * (size_t)(nnz ? nnz : 1));
+    if (!oc || !ov) { free(oc); free(ov); rc = ORC_ENOMEM; goto done; }
+    memcpy(Op, p[cur], sizeof(int64_t) * ((size_t)n_v + 1));
+    if (nnz) {
+      memcpy(oc, c[cur], sizeof(int32_t) * (size_t)nnz);
+      memcpy(ov, v[cur], sizeof(double) * (size_t)nnz);
+    }
+    *Oc = oc;
+    *Ov = ov;
+    if (skel_total) *skel_total = sk;
+    if (events) *events = evs;
+  }
+done:
+  for (int b = 0; b < 2; ++b) { free(p[b]); free(c[b]); free(v[b]); }
+  free(skel);
+  blocks_free(&B);
+  return rc;
 }
 
 /* ---- labels -------------------------------------------------------------------

@@ -54,6 +54,13 @@ int orc_operator(int32_t n_v, const double* V, int32_t n_f, const int32_t* F, in
 int orc_init(int32_t n_v, const int32_t* seeds, int32_t n_s,
              int64_t* ptr /* n_v+1 */, int32_t** col, double** val);
 
+/* Seeds grown into regions of `rings` edge-rings (Algorithm 1, first line;
+ * Initialization paragraph): each vertex within reach takes the layer of its
+ * nearest seed, ties to the lowest seed index; every other vertex the base.
+ * rings = 0 gives orc_init.  Output as orc_init. */
+int orc_init_rings(int32_t n_v, int32_t n_f, const int32_t* F, const int32_t* seeds, int32_t n_s,
+                   int32_t rings, int64_t* ptr, int32_t** col, double** val);
+
 /* One explicit Euler step of Algorithm 1 (Jacobi form), followed by the
  * column normalisation, the theta prune and compaction.  L must include its
  * diagonal.  Optional outputs (may be NULL): margin[n_v] = smallest distance
@@ -74,6 +81,14 @@ int orc_step_threads(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t*
                      const double* Lv, const int64_t* Up, const int32_t* Uc, const double* Uv,
                      const orc_params* P, int64_t* Op, int32_t** Oc, double** Ov, double* margin,
                      double* smargin, int32_t* skel, int64_t* events, int32_t threads);
+
+/* n_steps free-running steps of orc_step_threads in one call (U_in is not
+ * modified; the final fields go to Op[n_v+1], *Oc, *Ov).  skel_total and
+ * events (may be NULL) sum the rows-of-interest sizes and empty-row events. */
+int orc_run_threads(int32_t n_v, int32_t n_s, const int64_t* Lp, const int32_t* Lc,
+                    const double* Lv, const int64_t* Up, const int32_t* Uc, const double* Uv,
+                    const orc_params* P, int32_t n_steps, int32_t threads, int64_t* Op,
+                    int32_t** Oc, double** Ov, int64_t* skel_total, int64_t* events);
 
 /* Sharp labels (Section 5.2 and Figure 10): argmax over the cell columns of
  * a row, lowest column on ties, -1 when the row has no cell entry.

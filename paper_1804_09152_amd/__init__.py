@@ -52,12 +52,13 @@ class lf_job(C.Structure):
 EXPORTS = [
     "lf_last_error", "lf_params_default", "lf_ctx_create", "lf_ctx_destroy", "lf_mesh_create",
     "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
-    "lf_fields_reset", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_fields_set_coefficients", "lf_step", "lf_sync", "lf_fields_export",
+    "lf_fields_reset", "lf_fields_create_rings", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_fields_set_coefficients", "lf_step", "lf_sync", "lf_fields_use_graphs", "lf_fields_export",
     "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_lloyd", "lf_dual_mesh", "lf_dual_matrix",
     "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
     "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
     "lf_server_create", "lf_server_destroy", "lf_server_submit", "lf_server_poll", "lf_server_cancel",
-    "lf_server_result", "lf_server_release", "lf_server_memory",
+    "lf_server_result", "lf_server_release", "lf_server_memory", "lf_server_times",
+    "lf_server_stats",
 ]
 
 _lib = None
@@ -99,6 +100,7 @@ def load(path: str | None = None):
         "lf_fields_create": (C.c_int, [V, V, I32, C.POINTER(lf_params), PV]),
         "lf_fields_destroy": (C.c_int, [V]),
         "lf_fields_reset": (C.c_int, [V, V]),
+        "lf_fields_create_rings": (C.c_int, [V, V, I32, I32, C.POINTER(lf_params), PV]),
         "lf_fields_create_regions": (C.c_int, [V, V, V, I32, C.POINTER(lf_params), PV]),
         "lf_fields_reset_regions": (C.c_int, [V, V, V]),
         "lf_fields_seeds": (C.c_int, [V, V]),
@@ -107,6 +109,7 @@ def load(path: str | None = None):
         "lf_step_until": (C.c_int, [V, I32, D, I32, V, V]),
         "lf_last_change": (C.c_int, [V, V, V]),
         "lf_sync": (C.c_int, [V]),
+        "lf_fields_use_graphs": (C.c_int, [V, I32]),
         "lf_fields_export": (C.c_int, [V, V, V, V, V, I32]),
         "lf_fields_import": (C.c_int, [V, I64, V, V, V, I32]),
         "lf_labels": (C.c_int, [V, V, I32]),
@@ -131,6 +134,8 @@ def load(path: str | None = None):
         "lf_server_result": (C.c_int, [V, I64, V, V, V, V, V, V, V]),
         "lf_server_release": (C.c_int, [V, I64]),
         "lf_server_memory": (C.c_int, [V, V, V]),
+        "lf_server_times": (C.c_int, [V, I64, V, V, V]),
+        "lf_server_stats": (C.c_int, [V, V, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -208,6 +213,15 @@ def lf_fields_create(mesh, seeds, params: lf_params | None = None):
     _check(load().lf_fields_create(mesh, seeds.ctypes.data, seeds.size,
                                    C.byref(params) if params is not None else None, C.byref(h)))
     return h
+
+
+def lf_fields_create_rings(mesh, seeds, rings: int, params: lf_params | None = None):
+    s = np.ascontiguousarray(seeds, np.int32)
+    out = C.c_void_p()
+    _check(load().lf_fields_create_rings(mesh, s.ctypes.data, s.size, rings,
+                                         C.byref(params) if params is not None else None,
+                                         C.byref(out)))
+    return out
 
 
 def lf_fields_create_regions(mesh, region_ptr, region_vertices, params: lf_params | None = None):
@@ -522,6 +536,9 @@ class Batch:
     def timing(self, enable: int = -1):
         return lf_step_timing(self.fh, enable)
 
+    def use_graphs(self, on: bool = True):
+        _check(load().lf_fields_use_graphs(self.fh, int(bool(on))))
+
     def close(self):
         if self.h:
             lf_batch_destroy(self.h)
@@ -599,6 +616,18 @@ class Server:
     def memory(self):
         return lf_server_memory(self.h)
 
+    def times(self, job_id: int):
+        """(submit, admit, done) on the monotonic clock, ms."""
+        v = [C.c_double() for _ in range(3)]
+        _check(load().lf_server_times(self.h, job_id, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def stats(self):
+        """(ticks, grouped step launches)."""
+        v = [C.c_int64() for _ in range(2)]
+        _check(load().lf_server_stats(self.h, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
     def close(self):
         if self.h:
             lf_server_destroy(self.h)
@@ -614,11 +643,15 @@ class Server:
 
 
 class Fields:
-    def __init__(self, mesh: Mesh, seeds=None, params: lf_params | None = None, regions=None):
-        """From seeds (int32 vertex ids), or from initial regions given as
-        (region_ptr, region_vertices)."""
+    def __init__(self, mesh: Mesh, seeds=None, params: lf_params | None = None, regions=None,
+                 rings: int = 0):
+        """From seeds (int32 vertex ids; grown by `rings` rings), or from
+        initial regions given as (region_ptr, region_vertices)."""
         self.mesh = mesh
-        if regions is not None:
+        if rings:
+            self.n_s = int(np.asarray(seeds).size)
+            self.h = lf_fields_create_rings(mesh.h, seeds, rings, params)
+        elif regions is not None:
             rp, rv = regions
             self.n_s = int(np.asarray(rp).size) - 1
             self.h = lf_fields_create_regions(mesh.h, rp, rv, params)
@@ -636,6 +669,9 @@ class Fields:
 
     def step(self, n: int = 1):
         lf_step(self.h, n)
+
+    def use_graphs(self, on: bool = True):
+        _check(load().lf_fields_use_graphs(self.h, int(bool(on))))
 
     def step_until(self, max_steps: int, eps: float = 1e-2, check_every: int = 32):
         return lf_step_until(self.h, max_steps, eps, check_every)

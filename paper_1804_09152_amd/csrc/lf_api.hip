@@ -384,6 +384,19 @@ static lf_status init_fields(lf_fields* f) {
   if (f->region_owner.empty()) {
     LF_HIP(launch_fill_i32(f->owner, n_v, f->n_s, s));
     LF_HIP(launch_scatter_owner(f->d_seeds, f->n_s, f->owner, s));
+    if (f->rings > 0) {
+      DevBuf<int32_t> tmp;
+      LF_HIP(tmp.alloc(n_v));
+      int32_t* a = f->owner;
+      int32_t* b = tmp.p;
+      for (int32_t r = 0; r < f->rings; ++r) {
+        LF_HIP(launch_ring_grow(f->mesh->lptr, f->mesh->lent, a, b, n_v, f->n_s, s));
+        std::swap(a, b);
+      }
+      if (a != f->owner)
+        LF_HIP(hipMemcpyAsync(f->owner, a, sizeof(int32_t) * n_v, hipMemcpyDeviceToDevice, s));
+      LF_HIP(hipStreamSynchronize(s));
+    }
   } else {
     LF_HIP(hipMemcpyAsync(f->owner, f->region_owner.data(), sizeof(int32_t) * n_v,
                           hipMemcpyHostToDevice, s));
@@ -401,6 +414,7 @@ static lf_status init_fields(lf_fields* f) {
 lf_status lf_fields_destroy(lf_fields* f) try {
   if (!f) return LF_OK;
   (void)hipSetDevice(f->mesh->ctx->device);
+  drop_graphs(f);
   for (int k = 0; k < 2; ++k) {
     (void)hipFree(f->ell[k]);
     (void)hipFree(f->ovf[k]);
@@ -455,7 +469,7 @@ static lf_status check_regions(const int32_t* ptr, const int32_t* verts, int32_t
 }
 
 static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const lf_params* P,
-                            std::vector<int32_t>&& region_owner, lf_fields** out);
+                            std::vector<int32_t>&& region_owner, int32_t rings, lf_fields** out);
 
 lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const lf_params* P,
                            lf_fields** out) try {
@@ -463,7 +477,19 @@ lf_status lf_fields_create(lf_mesh* m, const int32_t* seeds, int32_t n_s, const 
   *out = nullptr;
   lf_status st = check_seeds(seeds, n_s, m->n_v);
   if (st) return st;
-  return fields_new(m, seeds, n_s, P, std::vector<int32_t>(), out);
+  return fields_new(m, seeds, n_s, P, std::vector<int32_t>(), 0, out);
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
+}
+
+lf_status lf_fields_create_rings(lf_mesh* m, const int32_t* seeds, int32_t n_s, int32_t rings,
+                                 const lf_params* P, lf_fields** out) try {
+  if (!m || !out) return fail(LF_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (rings < 0 || rings > 1024) return fail(LF_EINVAL, "rings must be in [0, 1024]");
+  lf_status st = check_seeds(seeds, n_s, m->n_v);
+  if (st) return st;
+  return fields_new(m, seeds, n_s, P, std::vector<int32_t>(), rings, out);
 } catch (const std::bad_alloc&) {
   return lf::host_oom();
 }
@@ -476,7 +502,7 @@ lf_status lf_fields_create_regions(lf_mesh* m, const int32_t* region_ptr,
   std::vector<int32_t> owner, first;
   lf_status st = check_regions(region_ptr, region_vertices, n_s, m->n_v, owner, first);
   if (st) return st;
-  return fields_new(m, first.data(), n_s, P, std::move(owner), out);
+  return fields_new(m, first.data(), n_s, P, std::move(owner), 0, out);
 } catch (const std::bad_alloc&) {
   return lf::host_oom();
 }
@@ -490,6 +516,7 @@ lf_status lf_fields_reset_regions(lf_fields* f, const int32_t* region_ptr,
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   f->seeds = std::move(first);
   f->region_owner = std::move(owner);
+  f->rings = 0;
   return init_fields(f);
 } catch (const std::bad_alloc&) {
   return lf::host_oom();
@@ -498,7 +525,7 @@ lf_status lf_fields_reset_regions(lf_fields* f, const int32_t* region_ptr,
 }  // extern "C"
 
 static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const lf_params* P,
-                            std::vector<int32_t>&& region_owner, lf_fields** out) {
+                            std::vector<int32_t>&& region_owner, int32_t rings, lf_fields** out) {
   lf_status st = LF_OK;
   lf_params prm;
   if (P) prm = *P;
@@ -513,6 +540,7 @@ static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const
   f->P = prm;
   f->seeds.assign(seeds, seeds + n_s);
   f->region_owner = std::move(region_owner);
+  f->rings = rings;
   const int64_t hint = prm.capacity_hint > 0 ? prm.capacity_hint
                                              : std::max<int64_t>(4096, m->n_v / 16);
   f->ovf_cap = std::min<int64_t>(hint, (1ll << 31) - 1);
@@ -603,10 +631,22 @@ void book_steps(lf_fields* f, const StepStats* st, int64_t ok) {
   }
 }
 
-// Enqueues n steps on the context stream, then asynchronous copies of the
-// failure flags and per-step counters and an event; does not wait.
-lf_status step_issue(lf_fields* f, int64_t n) {
-  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+int64_t mesh_bytes(const lf_mesh* m) {
+  const int64_t nv = m->n_v;
+  return 24 * nv + 12ll * m->n_f + 2 * (4 * (nv + 1) + 8 * m->nnz_off + 4 * nv) + 8 * nv +
+         8ll * m->n_slices * m->op_w * kSlice;
+}
+
+int64_t fields_bytes(const lf_fields* f) {
+  const int64_t nv = f->mesh->n_v;
+  return 2 * (int64_t)sizeof(EllRow) * nv + 2 * 8 * f->ovf_cap + 4 * nv + 4ll * f->n_s +
+         (int64_t)sizeof(WideRow) * f->wide_cap + 4 * (nv + 1) + 8 * f->csr_cap +
+         8 * scan_tmp_elems(nv) + (int64_t)sizeof(StepStats) * f->stats_cap * (1 + kParts) +
+         4ll * (f->n_s + 1) * (f->n_types > 0) + 16ll * f->n_types * f->n_types;
+}
+
+// Step counters and host copies for chunks of up to n steps.
+lf_status ensure_step_buffers(lf_fields* f, int64_t n) {
   hipStream_t s = f->mesh->ctx->stream;
   if (n > f->stats_cap) {
     const int64_t c = std::max<int64_t>(n, 2 * f->stats_cap);
@@ -633,13 +673,113 @@ lf_status step_issue(lf_fields* f, int64_t n) {
     f->stats_pinned_cap = c;
   }
   if (!f->done_ev) LF_HIP(hipEventCreateWithFlags(&f->done_ev, hipEventDisableTiming));
+  return LF_OK;
+}
+
+StepArgs chunk_step_args(lf_fields* f, int64_t k, int64_t n) {
+  StepArgs a = step_args(f, (int)((f->cur + k) & 1));
+  a.parts = f->parts + k * kParts;
+  a.step_idx = (uint32_t)k;
+  a.measure = (f->measure_all || k == n - 1) ? 1u : 0u;
+  return a;
+}
+
+static lf_status chunk_tail_copies(lf_fields* f, int64_t n, hipStream_t s) {
+  LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
+  LF_HIP(hipMemcpyAsync(f->stats_pinned, f->stats, sizeof(StepStats) * n, hipMemcpyDeviceToHost, s));
+  return LF_OK;
+}
+
+lf_status chunk_tail(lf_fields* f, int64_t n, hipStream_t s) {
+  LF_HIP(launch_reduce_parts(f->parts, n, f->stats, s));
+  return chunk_tail_copies(f, n, s);
+}
+
+// what a captured chunk's kernels name: buffers, capacities, coefficient
+// tables and which steps measure
+static uint64_t graph_key(const lf_fields* f, int parity) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
+  mix((uint64_t)parity);
+  mix((uint64_t)(uintptr_t)f->ovf[0]);
+  mix((uint64_t)(uintptr_t)f->ovf[1]);
+  mix((uint64_t)f->ovf_cap);
+  mix((uint64_t)(uintptr_t)f->wide);
+  mix((uint64_t)f->wide_cap);
+  mix((uint64_t)(uintptr_t)f->parts);
+  mix((uint64_t)(uintptr_t)f->stats);
+  mix((uint64_t)(uintptr_t)f->types);
+  mix((uint64_t)(uintptr_t)f->coef);
+  mix((uint64_t)f->n_types);
+  mix((uint64_t)f->measure_all);
+  return h;
+}
+
+void drop_graphs(lf_fields* f) {
+  for (int p = 0; p < 2; ++p) {
+    if (f->graph[p]) (void)hipGraphExecDestroy(f->graph[p]);
+    f->graph[p] = nullptr;
+    f->graph_key[p] = 0;
+  }
+}
+
+// the kernels of a chunk of n steps starting from the current buffer
+static lf_status enqueue_chunk(lf_fields* f, int64_t n, hipStream_t s) {
+  LF_HIP(launch_reset_flags(f->flags, f->parts, n, s));
+  for (int64_t k = 0; k < n; ++k) LF_HIP(launch_step(chunk_step_args(f, k, n), s, nullptr, nullptr));
+  LF_HIP(launch_reduce_parts(f->parts, n, f->stats, s));
+  return LF_OK;
+}
+
+// a whole chunk from its captured graph (captured on first use)
+static lf_status launch_chunk_graph(lf_fields* f, hipStream_t s) {
+  const int p = f->cur & 1;
+  const uint64_t key = graph_key(f, p);
+  if (!f->graph[p] || f->graph_key[p] != key) {
+    if (f->graph[p]) (void)hipGraphExecDestroy(f->graph[p]);
+    f->graph[p] = nullptr;
+    hipGraph_t g = nullptr;
+    LF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    lf_status st = enqueue_chunk(f, kMaxChunk, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&f->graph[p], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      f->graph[p] = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    f->graph_key[p] = key;
+  }
+  LF_HIP(hipGraphLaunch(f->graph[p], s));
+  return LF_OK;
+}
+
+// Enqueues n steps on the context stream, then asynchronous copies of the
+// failure flags and per-step counters and an event; does not wait.
+lf_status step_issue(lf_fields* f, int64_t n) {
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  hipStream_t s = f->mesh->ctx->stream;
+  lf_status st = ensure_step_buffers(f, n);
+  if (st) return st;
+  if (f->use_graphs && n == kMaxChunk && f->timing <= 0 && s != nullptr) {
+    st = launch_chunk_graph(f, s);
+    if (st) return st;
+    st = chunk_tail_copies(f, n, s);
+    if (st) return st;
+    LF_HIP(hipEventRecord(f->done_ev, s));
+    f->pending = n;
+    f->ev_issued = 0;
+    return LF_OK;
+  }
   LF_HIP(launch_reset_flags(f->flags, f->parts, n, s));
   size_t used = 0;
   for (int64_t k = 0; k < n; ++k) {
-    StepArgs a = step_args(f, (int)((f->cur + k) & 1));
-    a.parts = f->parts + k * kParts;
-    a.step_idx = (uint32_t)k;
-    a.measure = (f->measure_all || k == n - 1) ? 1u : 0u;
+    StepArgs a = chunk_step_args(f, k, n);
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (f->timing > 0 && f->timing_ctr++ % f->timing == 0) {
       t0 = pool_event(f->ev0, used);
@@ -648,9 +788,8 @@ lf_status step_issue(lf_fields* f, int64_t n) {
     }
     LF_HIP(launch_step(a, s, t0, t1));
   }
-  LF_HIP(launch_reduce_parts(f->parts, n, f->stats, s));
-  LF_HIP(hipMemcpyAsync(f->flags_host, f->flags, sizeof(StepFlags), hipMemcpyDeviceToHost, s));
-  LF_HIP(hipMemcpyAsync(f->stats_pinned, f->stats, sizeof(StepStats) * n, hipMemcpyDeviceToHost, s));
+  st = chunk_tail(f, n, s);
+  if (st) return st;
   LF_HIP(hipEventRecord(f->done_ev, s));
   f->pending = n;
   f->ev_issued = used;
@@ -661,23 +800,10 @@ bool step_ready(lf_fields* f) {
   return f->pending == 0 || hipEventQuery(f->done_ev) == hipSuccess;
 }
 
-// Waits for the issued steps and books the completed ones.  *remaining is
-// the number of issued steps that did not complete (storage was grown: issue
-// them again).
-lf_status step_complete(lf_fields* f, int64_t* remaining) {
-  *remaining = 0;
-  if (f->pending == 0) return LF_OK;
-  LF_HIP(hipSetDevice(f->mesh->ctx->device));
-  LF_HIP(hipEventSynchronize(f->done_ev));
-  for (size_t k = 0; k < f->ev_issued; ++k) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, f->ev0[k], f->ev1[k]) == hipSuccess) {
-      f->timed_ms += ms;
-      f->timed_launches++;
-    }
-  }
-  const int64_t n = f->pending;
-  f->pending = 0;
+// Books a completed chunk of n steps from its flags and per-step counters
+// (host copies): the steps before the first failed one count; storage that
+// ran out is grown.  *remaining = steps that did not complete.
+lf_status step_book(lf_fields* f, int64_t n, int64_t* remaining) {
   const StepFlags fl = *f->flags_host;
   // steps before the first failed one are complete; the later ones did nothing
   const int64_t ok = fl.poisoned ? std::min<int64_t>(fl.fail_step, n) : n;
@@ -697,6 +823,26 @@ lf_status step_complete(lf_fields* f, int64_t* remaining) {
     if (st) return st;
   }
   return clear_step_state(f);
+}
+
+// Waits for the issued steps and books the completed ones.  *remaining is
+// the number of issued steps that did not complete (storage was grown: issue
+// them again).
+lf_status step_complete(lf_fields* f, int64_t* remaining) {
+  *remaining = 0;
+  if (f->pending == 0) return LF_OK;
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  LF_HIP(hipEventSynchronize(f->done_ev));
+  for (size_t k = 0; k < f->ev_issued; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, f->ev0[k], f->ev1[k]) == hipSuccess) {
+      f->timed_ms += ms;
+      f->timed_launches++;
+    }
+  }
+  const int64_t n = f->pending;
+  f->pending = 0;
+  return step_book(f, n, remaining);
 }
 
 bool chunk_quiet(const lf_fields* f, int64_t n, double eps) {
@@ -824,6 +970,16 @@ lf_status lf_step(lf_fields* f, int32_t n) try {
     left -= m - rem;
     if (rem > 0 && ++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
   }
+  return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
+}
+
+lf_status lf_fields_use_graphs(lf_fields* f, int32_t on) try {
+  if (!f || (on != 0 && on != 1)) return fail(LF_EINVAL, "invalid argument");
+  LF_HIP(hipSetDevice(f->mesh->ctx->device));
+  if (!on) drop_graphs(f);
+  f->use_graphs = on == 1;
   return LF_OK;
 } catch (const std::bad_alloc&) {
   return lf::host_oom();

@@ -126,6 +126,12 @@ lf_status host_oom();
 
 // launchers (each defined next to its kernels) ------------------------------
 hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
+// one step of n_jobs field objects in one launch: device arrays G[n_jobs] of
+// their arguments and first[n_jobs + 1] of their first slices in the launch
+// (first[n_jobs] = total_slices); all scalar (typed = false) or all with
+// per-pair coefficients (typed = true)
+hipError_t launch_step_group(const StepArgs* G, const int32_t* first, int32_t n_jobs,
+                             int32_t total_slices, bool typed, hipStream_t s);
 // clears the failure flags and n steps' partial counters (n * kParts slots)
 hipError_t launch_reset_flags(StepFlags* f, StepStats* parts, int64_t n, hipStream_t s);
 // folds the partial counters of n steps into one StepStats per step
@@ -135,6 +141,10 @@ hipError_t launch_init_fields(const int32_t* owner, const int32_t* perm, int32_t
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owner, hipStream_t s);
+// one ring of seed regions over the operator's off-diagonal pattern (caller's
+// vertex order)
+hipError_t launch_ring_grow(const int32_t* lptr, const Ent* lent, const int32_t* own_in,
+                            int32_t* own_out, int32_t n_v, int32_t n_s, hipStream_t s);
 
 // exclusive scan of n int32 counts into out[0..n] (out[n] = total); tmp must
 // hold scan_tmp_elems(n) int64
@@ -216,6 +226,21 @@ lf_status step_complete(lf_fields* f, int64_t* remaining);
 // quiet: no row changed its label or its layers at or above tau, and no
 // value moved by more than eps
 bool chunk_quiet(const lf_fields* f, int64_t n, double eps);
+// device bytes a mesh / a field object holds (their allocations, as sized now)
+int64_t mesh_bytes(const lf_mesh* m);
+int64_t fields_bytes(const lf_fields* f);
+// per-step counters, their host copies and the chunk event for chunks of up
+// to n steps
+lf_status ensure_step_buffers(lf_fields* f, int64_t n);
+// arguments of step k of a chunk of n steps starting at the current buffer
+StepArgs chunk_step_args(lf_fields* f, int64_t k, int64_t n);
+// after a chunk of n steps: fold the counters and copy them and the flags to
+// the host (stream s)
+lf_status chunk_tail(lf_fields* f, int64_t n, hipStream_t s);
+// books a completed chunk of n steps from the host copies (see step_complete)
+lf_status step_book(lf_fields* f, int64_t n, int64_t* remaining);
+// releases the captured chunk graphs of a field object
+void drop_graphs(lf_fields* f);
 // step arguments over the fields' own buffers for a step that reads the
 // buffer of the given parity (the caller sets parts, step_idx and measure)
 StepArgs step_args(lf_fields* f, int parity);
@@ -269,6 +294,7 @@ struct lf_fields {
   lf_params P;
   std::vector<int32_t> seeds;
   std::vector<int32_t> region_owner;  // initial regions: owner of every vertex (empty: seeds)
+  int32_t rings = 0;           // seeds grown by this many rings at (re-)initialisation
   int32_t* d_seeds;
   int32_t* owner;              // scratch n_v
   lf::EllRow* ell[2];          // fields, double-buffered
@@ -305,6 +331,11 @@ struct lf_fields {
   int32_t n_types;
   int32_t* types;    // n_s + 1
   float4* coef;      // n_types * n_types
+  // chunks of kMaxChunk steps replayed from a captured graph (kernels only),
+  // one per starting buffer; rebuilt when a buffer they name changes
+  bool use_graphs = false;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  uint64_t graph_key[2] = {0, 0};
   // timing
   int32_t timing;             // time every timing-th step launch (0: off)
   int64_t timing_ctr;         // step launches issued while timing

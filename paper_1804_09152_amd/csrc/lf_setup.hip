@@ -33,6 +33,22 @@ __global__ void k_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owne
   if (k < n_s) owner[seeds[k]] = k;
 }
 
+// One ring of seed regions (Algorithm 1, first line: a seed and its
+// neighbours): a vertex not yet in a region joins the lowest-index region
+// among its neighbours' (n_s = none); the regions of the previous ring are
+// read from own_in, the grown ones written to own_out.  Ring by ring this
+// gives every vertex within r edges of a seed the lowest index among its
+// nearest seeds, and a seed keeps itself.
+__global__ void k_ring_grow(const int32_t* lptr, const Ent* lent, const int32_t* own_in,
+                            int32_t* own_out, int32_t n_v, int32_t n_s) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_v) return;
+  int32_t o = own_in[v];
+  if (o == n_s)
+    for (int32_t q = lptr[v]; q < lptr[v + 1]; ++q) o = min(o, own_in[lent[q].col]);
+  own_out[v] = o;
+}
+
 // owner[v] = seed index of v, or n_s (the base layer) for unseeded vertices
 // (fields rows are in the step's vertex order: row k holds vertex perm[k])
 __global__ void k_init_fields(const int32_t* owner, const int32_t* perm, int32_t n_v, EllRow* u) {
@@ -452,6 +468,12 @@ hipError_t launch_scatter_owner(const int32_t* seeds, int32_t n_s, int32_t* owne
                                 hipStream_t s) {
   if (n_s <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_owner, dim3(blocks_for(n_s)), dim3(kT), 0, s, seeds, n_s, owner);
+  return hipGetLastError();
+}
+hipError_t launch_ring_grow(const int32_t* lptr, const Ent* lent, const int32_t* own_in,
+                           int32_t* own_out, int32_t n_v, int32_t n_s, hipStream_t s) {
+  hipLaunchKernelGGL(k_ring_grow, dim3(blocks_for(n_v)), dim3(kT), 0, s, lptr, lent, own_in,
+                     own_out, n_v, n_s);
   return hipGetLastError();
 }
 hipError_t launch_init_fields(const int32_t* owner, const int32_t* perm, int32_t n_v, EllRow* u,

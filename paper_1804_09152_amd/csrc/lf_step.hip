@@ -617,18 +617,12 @@ __device__ __forceinline__ EllRow row_regs(const RowBuf<kRowRegs>& r, int cnt) {
   return o;
 }
 
+// One wavefront's slice sl of one step of the fields described by A.
 // TYPED: per-pair coefficients (a separate instance, so that the scalar
-// step keeps its registers)
+// step keeps its registers).
 template <bool TYPED>
-__global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
-    StepArgs A) {
+__device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
   const int lane = threadIdx.x;
-  // XCD-aware: workgroups are dealt to the 8 XCDs round-robin, so XCD x runs
-  // blocks x, x + 8, ...; giving it the contiguous slices [x * per, (x+1) * per)
-  // keeps neighbouring rows (close in the step's vertex order) in one L2
-  const int per = (A.n_slices + kXcds - 1) / kXcds;
-  const int sl = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-  if (sl >= A.n_slices) return;
   // Whether an earlier step of the chunk failed: the flag is set by atomics
   // in an earlier launch, and a scalar load sees it (caches are made
   // coherent between launches).  It is loaded here and tested after the
@@ -723,6 +717,42 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   }
 }
 
+// XCD-aware block order: workgroups are dealt to the 8 XCDs round-robin, so
+// XCD x runs blocks x, x + 8, ...; giving it the contiguous slices
+// [x * per, (x+1) * per) of n keeps neighbouring rows (close in the step's
+// vertex order) in one L2
+__device__ __forceinline__ int xcd_slice(int n) {
+  const int per = (n + kXcds - 1) / kXcds;
+  return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+
+template <bool TYPED>
+__global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
+    StepArgs A) {
+  const int sl = xcd_slice(A.n_slices);
+  if (sl >= A.n_slices) return;
+  step_slice<TYPED>(A, sl);
+}
+
+// One step of several independent field objects in one launch: their slices
+// follow one another (job j owns slices [first[j], first[j+1]) of the
+// launch, first[n_jobs] = total), each with its own arguments G[j]; the XCD
+// order runs over the whole launch.
+template <bool TYPED>
+__global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step_group(
+    const StepArgs* __restrict__ G, const int32_t* __restrict__ first, int32_t n_jobs) {
+  const int total = first[n_jobs];
+  const int g = xcd_slice(total);
+  if (g >= total) return;
+  int lo = 0, hi = n_jobs - 1;  // the last job whose first slice is <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  step_slice<TYPED>(G[lo], g - first[lo]);
+}
+
 __global__ void k_reset_flags(StepFlags* f, StepStats* parts, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0) {
@@ -773,6 +803,15 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent
     if (a.c.n_types > 0) hipLaunchKernelGGL(k_step<true>, grid, dim3(kSlice), 0, s, a);
     else hipLaunchKernelGGL(k_step<false>, grid, dim3(kSlice), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_group(const StepArgs* G, const int32_t* first, int32_t n_jobs,
+                             int32_t total_slices, bool typed, hipStream_t s) {
+  if (n_jobs <= 0 || total_slices <= 0) return hipSuccess;
+  const dim3 grid((unsigned)(kXcds * ((total_slices + kXcds - 1) / kXcds)));
+  if (typed) hipLaunchKernelGGL(k_step_group<true>, grid, dim3(kSlice), 0, s, G, first, n_jobs);
+  else hipLaunchKernelGGL(k_step_group<false>, grid, dim3(kSlice), 0, s, G, first, n_jobs);
   return hipGetLastError();
 }
 

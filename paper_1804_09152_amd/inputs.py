@@ -186,33 +186,6 @@ def morton_order(V: np.ndarray, bits: int = 10) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
-def ring_regions(mesh: Mesh, seeds: np.ndarray):
-    """Initial regions of 1-ring seeds: each seed with the vertices that share
-    a face with it.  A vertex in several rings goes to the lowest seed index;
-    a seed always keeps itself.  Returns (region_ptr, region_vertices)."""
-    n_v = mesh.n_v
-    seeds = np.asarray(seeds, dtype=np.int64)
-    owner = np.full(n_v, -1, dtype=np.int64)
-    owner[seeds] = np.arange(seeds.size)
-    F = mesh.F.astype(np.int64)
-    # vertex pairs that share a face, both directions
-    a = np.concatenate([F[:, 0], F[:, 1], F[:, 2], F[:, 1], F[:, 2], F[:, 0]])
-    b = np.concatenate([F[:, 1], F[:, 2], F[:, 0], F[:, 0], F[:, 1], F[:, 2]])
-    sel = owner[a] >= 0
-    a, b = a[sel], b[sel]
-    cand = np.full(n_v, seeds.size, dtype=np.int64)
-    np.minimum.at(cand, b, owner[a])
-    free = owner < 0
-    owner[free] = np.where(cand[free] < seeds.size, cand[free], -1)
-    verts = np.nonzero(owner >= 0)[0]
-    k = owner[verts]
-    order = np.lexsort((verts != seeds[k], k))  # by region, its seed first
-    verts, k = verts[order], k[order]
-    ptr = np.zeros(seeds.size + 1, dtype=np.int32)
-    ptr[1:] = np.cumsum(np.bincount(k, minlength=seeds.size))
-    return ptr, verts.astype(np.int32)
-
-
 def permute_mesh(mesh: Mesh, order: np.ndarray) -> tuple[Mesh, np.ndarray]:
     """Relabel vertices so that new id k is old vertex order[k].
     Returns the mesh and the old->new map."""

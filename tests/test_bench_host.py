@@ -122,3 +122,17 @@ def test_instruction_summary(tmp_path):
     assert "| active lanes per VALU instruction | 50.0% |" in text
     issue = 1000 * 40968 * 4 / 1024 / 2400
     assert f"= {issue:.1f} us per launch" in text
+
+
+def test_cpu_baseline_legs():
+    """The CPU baseline's three legs (one thread, every thread, one batch mesh
+    per thread) on a small mesh and a small batch, with a tiny time budget."""
+    import numpy as np
+    from paper_1804_09152_amd import inputs as I
+    mesh, seeds = I.config_c2(level=3, n_seeds=16, seed=1)
+    items = I.batch_tori(4, nv_hi=2e3, s_hi=16)
+    out = bench.cpu_baseline(mesh, seeds, 0.2, items, max_steps=8)
+    assert out["kind"] == "oracle" and out["cores"] >= 1 and out["value"] > 0
+    assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
+    b = out["batch_one_mesh_per_thread"]
+    assert b["value"] > 0 and b["cores"] == out["cores"]

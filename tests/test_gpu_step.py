@@ -90,11 +90,14 @@ def test_step_teacher_forced(lf, orc, name, over, ts):
         f.step(1)
         G = as_oracle(f.export())
         O, info = orc.step(L, Uf, k, P, want_info=True)
-        # with theta = 0 every entry whose update lands near zero is a near-tie
-        # of the pattern decision; only the rows clear of it are compared
-        frac = 0.5 if P["theta"] == 0.0 else 1e-2
-        r = check_step(G, O, info["margin"], max_guarded_frac=frac, what=f"{name} t={t}")
-        if r["guarded"] == 0:
+        # with theta = 0 tiny entries are never pruned, so many zero entries
+        # sit next to layers whose field Laplacian is within 1e-5 of zero
+        # (up to 26% of the rows measured on this mesh); with theta = 1e-3
+        # none at these states
+        frac = 0.3 if P["theta"] == 0.0 else 1e-3
+        r = check_step(G, O, info, P["theta"], max_skel_guarded_frac=frac, what=f"{name} t={t}")
+        say(r)
+        if r["skel_guarded"] + r["output_guarded"] == 0:
             assert f.stats()["skeleton_total"] - s0 == int(info["skel"].sum())
 
 
@@ -160,7 +163,7 @@ def test_full_size_c3_one_step(lf, orc):
     f.step(1)
     G = as_oracle(f.export())
     O, info = orc.step(L, U, seeds.size, orc.default_params(), want_info=True)
-    r = check_step(G, O, info["margin"], what="c3")
+    r = check_step(G, O, info, 1e-3, what="c3")
     say("c3", r)
     # a denser state: up to five layers and the base per row (about 127,000
     # rows in the overflow area, read from register slots and from the wide
@@ -171,7 +174,7 @@ def test_full_size_c3_one_step(lf, orc):
     gpu_load(f, U5)
     f.step(1)
     O5, info5 = orc.step(L, U5, seeds.size, orc.default_params(), want_info=True)
-    say("c3 dense", check_step(as_oracle(f.export()), O5, info5["margin"], what="c3 dense"))
+    say("c3 dense", check_step(as_oracle(f.export()), O5, info5, 1e-3, what="c3 dense"))
     # from seeds too: 5 free steps, teacher-forced comparison of the last
     f.reset(seeds)
     f.step(4)
@@ -260,8 +263,8 @@ def test_capacity_growth_replays_exactly(lf, orc):
     O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
     gpu_load(a, U)
     a.step(1)
-    check_step(as_oracle(a.export()), O, info["margin"], what="overflow rows",
-               max_guarded_frac=0.05)
+    check_step(as_oracle(a.export()), O, info, 1e-3, what="overflow rows",
+               max_skel_guarded_frac=0.05)
 
 
 def test_export_import_roundtrip_with_long_rows(lf, orc):
@@ -317,7 +320,7 @@ def test_wide_rows(lf, orc):
         if t == 0:  # vertex 0 sees its own layer and two per neighbour
             seen = set(U[1][U[0][0]:U[0][1]]).union(*[set(U[1][U[0][u]:U[0][u + 1]]) for u in nb])
             assert len(seen) == 13
-        check_step(G, O, info["margin"], what=f"wide t={t}", max_guarded_frac=0.05)
+        check_step(G, O, info, 1e-3, what=f"wide t={t}", max_skel_guarded_frac=0.05)
         U = O
 
 
@@ -363,7 +366,7 @@ def test_overflow_rows_in_register_slots(lf, orc):
         O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
         if t == 0:
             assert np.diff(G[0]).max() > 4  # overflow rows written as well as read
-        check_step(G, O, info["margin"], what=f"overflow t={t}", max_guarded_frac=0.05)
+        check_step(G, O, info, 1e-3, what=f"overflow t={t}", max_skel_guarded_frac=0.05)
         U = f32(O)
 
 
@@ -410,7 +413,7 @@ def test_overflow_rows_in_wide_path(lf, orc):
         f.step(1)
         G = as_oracle(f.export())
         O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
-        check_step(G, O, info["margin"], what=f"overflow wide t={t}", max_guarded_frac=0.05)
+        check_step(G, O, info, 1e-3, what=f"overflow wide t={t}", max_skel_guarded_frac=0.05)
         U = f32(O)
 
 
@@ -458,7 +461,7 @@ def test_high_degree_vertex(lf, orc, op):
         f.step(1)
         G = as_oracle(f.export())
         O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
-        check_step(G, O, info["margin"], what=f"apex t={t}", max_guarded_frac=0.2)
+        check_step(G, O, info, 1e-3, what=f"apex t={t}", max_skel_guarded_frac=0.2)
         U = f32(O)
     f.reset(seeds)
     f.step(30)
@@ -486,7 +489,7 @@ def test_wide_workspace_growth(lf, orc):
     f.step(1)
     assert f.stats()["grow_events"] > g0
     O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
-    check_step(as_oracle(f.export()), O, info["margin"], max_guarded_frac=0.05, what="wide growth")
+    check_step(as_oracle(f.export()), O, info, 1e-3, max_skel_guarded_frac=0.05, what="wide growth")
 
 
 def test_determinism(lf):

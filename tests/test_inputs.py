@@ -57,26 +57,3 @@ def test_batch_and_jobs():
     assert len(b) == 8 and all(1 <= s.size <= m.n_v for m, s in b)
     jobs = I.serving_jobs(10)
     assert all(j["n_seeds"] == 64 * 4 ** (j["level"] - 5) for j in jobs)
-
-
-def test_ring_regions():
-    mesh = I.torus_grid(10, 10)
-    seeds = np.array([0, 1, 55], np.int32)
-    ptr, verts = I.ring_regions(mesh, seeds)
-    assert ptr[0] == 0 and ptr[-1] == verts.size
-    assert len(set(verts.tolist())) == verts.size  # disjoint
-    nb = [set() for _ in range(mesh.n_v)]
-    for a, b, c in mesh.F:
-        nb[a] |= {b, c}
-        nb[b] |= {a, c}
-        nb[c] |= {a, b}
-    for k, s in enumerate(seeds):
-        reg = verts[ptr[k]:ptr[k + 1]]
-        assert reg[0] == s
-        for v in reg[1:]:
-            assert v in nb[s] and v not in seeds
-            # a vertex next to several seeds belongs to the lowest of them
-            assert k == min(j for j, t in enumerate(seeds) if v in nb[t])
-    # every neighbour of a seed is in some region
-    for s in seeds:
-        assert nb[s] <= set(verts.tolist())

@@ -121,3 +121,37 @@ def test_init_regions(orc):
         pass
     else:
         raise AssertionError("overlapping regions accepted")
+
+
+def test_init_rings(orc):
+    """Seeds grown into rings of edges (Algorithm 1, first line;
+    Initialization paragraph): sizes on the regular torus grid (a triangular
+    lattice: hexagonal rings of 6 and 12 vertices), the nearest seed, ties
+    to the lower index, seeds keeping themselves."""
+    mesh = I.torus_grid(20, 20)
+    n_v = mesh.n_v
+    seeds = np.array([210, 0], np.int32)
+    for r in (0, 1, 2):
+        U = orc.init_rings(n_v, mesh.F, seeds, r)
+        col = np.asarray(U[1])
+        assert np.array_equal(U[0], np.arange(n_v + 1)) and (np.asarray(U[2]) == 1.0).all()
+        assert [(col == 0).sum(), (col == 1).sum()] == [[1, 1], [7, 7], [19, 19]][r]
+    a, b = orc.init(n_v, seeds), orc.init_rings(n_v, mesh.F, seeds, 0)
+    assert all(np.array_equal(np.asarray(x), np.asarray(y)) for x, y in zip(a, b))
+    # the 1-ring of vertex 0 on this grid: (x, y) offsets (+-1, 0), (0, +-1),
+    # (+1, +1), (-1, -1) (faces (a, a+x, a+x+y) and (a, a+x+y, a+y))
+    ring = {1, 19, 20, 380, 21, 399}
+    col = np.asarray(orc.init_rings(n_v, mesh.F, seeds, 1)[1])
+    assert set(np.nonzero(col == 1)[0]) == ring | {0}
+    # two seeds two edges apart: the vertices between them go to the lower
+    # seed index; a seed next to a lower seed keeps itself
+    s2 = np.array([2, 0, 1], np.int32)  # 0 and 1 adjacent, 2 two steps from 0
+    col = np.asarray(orc.init_rings(n_v, mesh.F, s2, 1)[1])
+    assert col[2] == 0 and col[0] == 1 and col[1] == 2
+    assert col[21] == 1  # next to vertices 0 (index 1) and 1 (index 2)
+    assert col[3] == 0  # next to vertex 2 only
+    # the nearest seed wins over a lower index: vertex 4 is two edges from
+    # vertex 2 (index 1) and three from vertex 7 (index 0); vertex 5 the
+    # other way round
+    col2 = np.asarray(orc.init_rings(n_v, mesh.F, np.array([7, 2], np.int32), 2)[1])
+    assert col2[4] == 1 and col2[5] == 0
