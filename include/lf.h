@@ -52,8 +52,8 @@ typedef enum { LF_OP_GRAPH = 0, LF_OP_COTAN = 1 } lf_operator;
  * base_mode 0: the base layer couples to cells through the gradient term
  * and an antisymmetric band term only; 1: the base is an ordinary layer.
  * capacity_hint: initial size, in entries, of the overflow area that holds
- * the rows with more than four entries (the library keeps the fields as
- * fixed-width rows of four entries; 0 = max(4096, n_v / 16)); it grows on
+ * the rows with more than three entries (the library keeps the fields as
+ * fixed-width rows of three entries; 0 = max(4096, n_v / 16)); it grows on
  * demand. */
 typedef struct {
   double w, a, e, mu, dt, theta, tau;
@@ -176,6 +176,21 @@ lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t che
  * steps; so always for the last step of a call). */
 lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta);
 lf_status lf_sync(lf_fields* f);
+/* Work-class ordering of the step's rows: every `every` steps (first 128
+ * steps after an initialisation), lf_step re-orders the rows within tiles of
+ * tile_rows consecutive rows by work class -- rows inside a cell (one layer,
+ * and every neighbour the same single layer) first, then rows whose
+ * neighbourhood holds 2, 3, or more layers (`classes` = 2 keeps only the
+ * first split) -- so that wavefronts hold rows of one class; wavefronts of
+ * rows inside a cell are written without the merge and update.  The order is
+ * invisible at the boundary and the results do not depend on it.  Off by
+ * default: on the meshes measured it costs more (the rows of a wavefront no
+ * longer gather neighbours from a few cache lines) than the short path saves.
+ * every = 0 keeps the current order.  tile_rows: a multiple of 256 in
+ * [256, 4096]; classes in [2, 4].  lf_fields_reorders returns how many
+ * re-orderings have happened. */
+lf_status lf_fields_set_reorder(lf_fields* f, int32_t every, int32_t tile_rows, int32_t classes);
+lf_status lf_fields_reorders(lf_fields* f, int64_t* n);
 /* on = 1: lf_step (and lf_step_until) runs whole chunks of 256 steps from a
  * HIP graph captured on first use (the chunk's kernels only; the counters'
  * copies to the host stay outside), one graph per starting buffer, captured

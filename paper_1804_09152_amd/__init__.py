@@ -52,7 +52,7 @@ class lf_job(C.Structure):
 EXPORTS = [
     "lf_last_error", "lf_params_default", "lf_ctx_create", "lf_ctx_destroy", "lf_mesh_create",
     "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
-    "lf_fields_reset", "lf_fields_create_rings", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_fields_set_coefficients", "lf_step", "lf_sync", "lf_fields_use_graphs", "lf_fields_export",
+    "lf_fields_reset", "lf_fields_create_rings", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_fields_set_coefficients", "lf_step", "lf_sync", "lf_fields_use_graphs", "lf_fields_set_reorder", "lf_fields_reorders", "lf_fields_export",
     "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_lloyd", "lf_dual_mesh", "lf_dual_matrix",
     "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
     "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
@@ -110,6 +110,8 @@ def load(path: str | None = None):
         "lf_last_change": (C.c_int, [V, V, V]),
         "lf_sync": (C.c_int, [V]),
         "lf_fields_use_graphs": (C.c_int, [V, I32]),
+        "lf_fields_set_reorder": (C.c_int, [V, I32, I32, I32]),
+        "lf_fields_reorders": (C.c_int, [V, V]),
         "lf_fields_export": (C.c_int, [V, V, V, V, V, I32]),
         "lf_fields_import": (C.c_int, [V, I64, V, V, V, I32]),
         "lf_labels": (C.c_int, [V, V, I32]),
@@ -539,6 +541,9 @@ class Batch:
     def use_graphs(self, on: bool = True):
         _check(load().lf_fields_use_graphs(self.fh, int(bool(on))))
 
+    def set_reorder(self, every: int, tile_rows: int = 4096, classes: int = 4):
+        _check(load().lf_fields_set_reorder(self.fh, int(every), int(tile_rows), int(classes)))
+
     def close(self):
         if self.h:
             lf_batch_destroy(self.h)
@@ -672,6 +677,14 @@ class Fields:
 
     def use_graphs(self, on: bool = True):
         _check(load().lf_fields_use_graphs(self.h, int(bool(on))))
+
+    def set_reorder(self, every: int, tile_rows: int = 4096, classes: int = 4):
+        _check(load().lf_fields_set_reorder(self.h, int(every), int(tile_rows), int(classes)))
+
+    def reorders(self) -> int:
+        n = C.c_int64()
+        _check(load().lf_fields_reorders(self.h, C.byref(n)))
+        return n.value
 
     def step_until(self, max_steps: int, eps: float = 1e-2, check_every: int = 32):
         return lf_step_until(self.h, max_steps, eps, check_every)

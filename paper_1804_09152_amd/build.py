@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["lf_api.hip", "lf_setup.hip", "lf_step.hip", "lf_post.hip", "lf_batch.hip", "lf_serve.hip"]
+SOURCES = ["lf_api.hip", "lf_setup.hip", "lf_step.hip", "lf_post.hip", "lf_batch.hip", "lf_serve.hip",
+           "lf_order.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -58,12 +58,13 @@ static float bits_float(unsigned long long u) {
 StepArgs step_args(lf_fields* f, int parity) {
   StepArgs a;
   lf_mesh* m = f->mesh;
-  a.lell = m->lell;
-  a.lptr = m->slptr;
-  a.lent = m->slent;
-  a.op_w = m->op_w;
+  a.lell = f->lell;
+  a.lptr = f->slptr;
+  a.lent = f->slent;
+  a.op_w = f->op_w;
   a.pad0_ = 0;
-  a.ldiag = m->sldiag;
+  a.ldiag = f->sldiag;
+  a.slice_cls = f->slice_cls;
   a.u_in = f->ell[parity];
   a.u_out = f->ell[1 - parity];
   a.ovf_in = f->ovf[parity];
@@ -159,8 +160,8 @@ lf_status fields_csr(lf_fields* f, const int32_t** uptr, const Ent** uent) {
     const int32_t n_v = f->mesh->n_v;
     lf_status st = reserve_csr(f, f->nnz);
     if (st) return st;
-    LF_HIP(ell_to_csr_ptr(f->ell[f->cur], f->mesh->inv, n_v, f->owner, f->uptr, f->scan_tmp, s));
-    LF_HIP(ell_to_csr_fill(f->ell[f->cur], f->ovf[f->cur], f->mesh->inv, n_v, f->uptr, f->uent, s));
+    LF_HIP(ell_to_csr_ptr(f->ell[f->cur], f->inv, n_v, f->owner, f->uptr, f->scan_tmp, s));
+    LF_HIP(ell_to_csr_fill(f->ell[f->cur], f->ovf[f->cur], f->inv, n_v, f->uptr, f->uent, s));
     f->csr_valid = true;
   }
   *uptr = f->uptr;
@@ -402,7 +403,8 @@ static lf_status init_fields(lf_fields* f) {
                           hipMemcpyHostToDevice, s));
   }
   f->cur = 0;
-  LF_HIP(launch_init_fields(f->owner, f->mesh->perm, n_v, f->ell[0], s));
+  f->next_reorder = f->steps + 128;  // once the fronts have met
+  LF_HIP(launch_init_fields(f->owner, f->perm, n_v, f->ell[0], s));
   f->nnz = n_v;
   f->csr_valid = false;
   lf_status st = clear_step_state(f);
@@ -415,6 +417,7 @@ lf_status lf_fields_destroy(lf_fields* f) try {
   if (!f) return LF_OK;
   (void)hipSetDevice(f->mesh->ctx->device);
   drop_graphs(f);
+  fields_order_reset(f);
   for (int k = 0; k < 2; ++k) {
     (void)hipFree(f->ell[k]);
     (void)hipFree(f->ovf[k]);
@@ -541,6 +544,7 @@ static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const
   f->seeds.assign(seeds, seeds + n_s);
   f->region_owner = std::move(region_owner);
   f->rings = rings;
+  fields_order_reset(f);
   const int64_t hint = prm.capacity_hint > 0 ? prm.capacity_hint
                                              : std::max<int64_t>(4096, m->n_v / 16);
   f->ovf_cap = std::min<int64_t>(hint, (1ll << 31) - 1);
@@ -642,7 +646,10 @@ int64_t fields_bytes(const lf_fields* f) {
   return 2 * (int64_t)sizeof(EllRow) * nv + 2 * 8 * f->ovf_cap + 4 * nv + 4ll * f->n_s +
          (int64_t)sizeof(WideRow) * f->wide_cap + 4 * (nv + 1) + 8 * f->csr_cap +
          8 * scan_tmp_elems(nv) + (int64_t)sizeof(StepStats) * f->stats_cap * (1 + kParts) +
-         4ll * (f->n_s + 1) * (f->n_types > 0) + 16ll * f->n_types * f->n_types;
+         4ll * (f->n_s + 1) * (f->n_types > 0) + 16ll * f->n_types * f->n_types +
+         (f->own_order ? 2 * 4 * nv + 4 * (nv + 1) + 8 * f->mesh->nnz_off + 4 * nv +
+                             8ll * f->mesh->n_slices * f->op_w * kSlice + f->mesh->n_slices
+                       : 0);
 }
 
 // Step counters and host copies for chunks of up to n steps.
@@ -712,6 +719,8 @@ static uint64_t graph_key(const lf_fields* f, int parity) {
   mix((uint64_t)(uintptr_t)f->coef);
   mix((uint64_t)f->n_types);
   mix((uint64_t)f->measure_all);
+  mix((uint64_t)(uintptr_t)f->lell);
+  mix((uint64_t)(uintptr_t)f->slice_cls);
   return h;
 }
 
@@ -764,6 +773,11 @@ static lf_status launch_chunk_graph(lf_fields* f, hipStream_t s) {
 lf_status step_issue(lf_fields* f, int64_t n) {
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   hipStream_t s = f->mesh->ctx->stream;
+  if (f->reorder_every > 0 && f->steps >= f->next_reorder) {
+    lf_status st = fields_reorder(f);
+    if (st) return st;
+    f->next_reorder = f->steps + f->reorder_every;
+  }
   lf_status st = ensure_step_buffers(f, n);
   if (st) return st;
   if (f->use_graphs && n == kMaxChunk && f->timing <= 0 && s != nullptr) {
@@ -975,6 +989,28 @@ lf_status lf_step(lf_fields* f, int32_t n) try {
   return lf::host_oom();
 }
 
+lf_status lf_fields_set_reorder(lf_fields* f, int32_t every, int32_t tile_rows,
+                                int32_t classes) try {
+  if (!f || every < 0 || tile_rows < 256 || tile_rows > kTileRows || tile_rows % 256 ||
+      classes < 2 || classes > 4)
+    return fail(LF_EINVAL, "invalid argument");
+  f->reorder_every = every;
+  f->reorder_tile = tile_rows;
+  f->reorder_classes = classes;
+  if (every > 0) f->next_reorder = std::min<int64_t>(f->next_reorder, f->steps + every);
+  return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
+}
+
+lf_status lf_fields_reorders(lf_fields* f, int64_t* n) try {
+  if (!f || !n) return fail(LF_EINVAL, "NULL argument");
+  *n = f->reorders;
+  return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
+}
+
 lf_status lf_fields_use_graphs(lf_fields* f, int32_t on) try {
   if (!f || (on != 0 && on != 1)) return fail(LF_EINVAL, "invalid argument");
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
@@ -1079,7 +1115,7 @@ lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, con
   if (hb) return fail(LF_EINVAL, "imported fields are not canonical (code " + std::to_string(hb) + ")");
   LF_HIP(hipMemcpyAsync(f->uptr, p, sizeof(int32_t) * (n_v + 1), hipMemcpyDeviceToDevice, s));
   const int tgt = 1 - f->cur;
-  LF_HIP(csr_to_ell(f->uptr, f->uent, f->mesh->inv, n_v, f->ell[tgt], f->ovf[tgt], s));
+  LF_HIP(csr_to_ell(f->uptr, f->uent, f->inv, n_v, f->ell[tgt], f->ovf[tgt], s));
   f->cur = tgt;
   f->nnz = nnz;
   f->csr_valid = true;

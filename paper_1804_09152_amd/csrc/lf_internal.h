@@ -17,18 +17,19 @@ struct __attribute__((aligned(8))) Ent {
 };
 
 constexpr int kSlice = 64;      // rows per operator slice = one wavefront of the step kernel
-constexpr int kEll = 4;         // field entries per row held inline
+constexpr int kEll = 3;         // field entries per row held inline
 constexpr int kRowRegs = 8;     // layers per row held in registers
 constexpr int kRowWide = 64;    // row limit of the wide (spill) path
 constexpr int kMaxVerts = 1 << 25;
 constexpr int kParts = 256;     // partial-sum slots of the per-step counters
 constexpr int32_t kOvfMark = -2;  // first column of a row kept in the overflow area
 constexpr int64_t kMaxChunk = 256;  // steps lf_step issues before it books them
+constexpr int kTileRows = 4096;     // rows per re-ordering tile (64 slices)
 
 // One row of the fields in fixed-width form: up to kEll entries, ascending
 // layers, unused slots {-1, 0}.  A row with more entries keeps them in the
 // overflow area: e[0] = {kOvfMark, 0}, e[1].col = offset, e[2].col = count.
-struct __attribute__((aligned(32))) EllRow {
+struct __attribute__((aligned(8))) EllRow {
   Ent e[kEll];
 };
 
@@ -110,6 +111,11 @@ struct StepArgs {
   StepStats* parts;                // kParts partial sums of this step
   uint32_t step_idx;               // index of this step within the chunk
   uint32_t measure;                // compute the convergence measures of this step
+  // per slice: 1 when every row of the slice was an interior row (one layer,
+  // and every neighbour the same single layer) at the last re-ordering; such
+  // slices check that it still holds and then skip the merge and update
+  // (nullptr: no slice is tried)
+  const uint8_t* slice_cls;
 };
 
 // error handling -----------------------------------------------------------
@@ -241,6 +247,11 @@ lf_status chunk_tail(lf_fields* f, int64_t n, hipStream_t s);
 lf_status step_book(lf_fields* f, int64_t n, int64_t* remaining);
 // releases the captured chunk graphs of a field object
 void drop_graphs(lf_fields* f);
+// re-orders the step's rows: within tiles of kTileRows rows, interior rows
+// first; the fields, the operator copy and the order maps are permuted
+lf_status fields_reorder(lf_fields* f);
+// the fields' order arrays back to the mesh's (frees owned ones)
+void fields_order_reset(lf_fields* f);
 // step arguments over the fields' own buffers for a step that reads the
 // buffer of the given parity (the caller sets parts, step_idx and measure)
 StepArgs step_args(lf_fields* f, int parity);
@@ -295,6 +306,23 @@ struct lf_fields {
   std::vector<int32_t> seeds;
   std::vector<int32_t> region_owner;  // initial regions: owner of every vertex (empty: seeds)
   int32_t rings = 0;           // seeds grown by this many rings at (re-)initialisation
+  // the step's row order: the mesh's (locality order) until the first
+  // re-ordering, then the fields' own (owned = true): within tiles of
+  // kTileRows rows, the interior rows first (see StepArgs::slice_cls)
+  const int32_t* perm = nullptr;  // row k is vertex perm[k]
+  const int32_t* inv = nullptr;   // vertex v is row inv[v]
+  const lf::Ent* lell = nullptr;  // operator slices, CSR and diagonal in this order
+  const int32_t* slptr = nullptr;
+  const lf::Ent* slent = nullptr;
+  const float* sldiag = nullptr;
+  int32_t op_w = 0;
+  uint8_t* slice_cls = nullptr;   // owned (nullptr before the first re-ordering)
+  bool own_order = false;
+  int32_t reorder_every = 0;      // steps between re-orderings (0: never)
+  int32_t reorder_tile = lf::kTileRows;  // rows per tile (a multiple of 256, at most kTileRows)
+  int32_t reorder_classes = 4;    // work classes the tiles are sorted into (2..4)
+  int64_t next_reorder = 128;     // step count at which the next one happens
+  int64_t reorders = 0;
   int32_t* d_seeds;
   int32_t* owner;              // scratch n_v
   lf::EllRow* ell[2];          // fields, double-buffered

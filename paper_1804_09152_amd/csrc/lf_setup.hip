@@ -122,7 +122,6 @@ __global__ void k_csr_to_ell(const int32_t* uptr, const Ent* uent, const int32_t
     r.e[0] = Ent{kOvfMark, 0.f};
     r.e[1] = Ent{a, 0.f};
     r.e[2] = Ent{n, 0.f};
-    r.e[3] = Ent{-1, 0.f};
     for (int j = 0; j < n; ++j) ovf[a + j] = uent[a + j];
   } else {
 #pragma unroll

@@ -18,8 +18,8 @@
 // which is equation (11) with the alternate inner sum of equation (15).
 //
 // Design: one wavefront per slice of 64 consecutive rows, one thread per
-// row.  The fields are held in fixed-width rows of four entries (32 bytes,
-// one aligned segment; longer rows, rare, live in an overflow area), so a
+// row.  The fields are held in fixed-width rows of three entries (24 bytes;
+// longer rows, rare, live in an overflow area), so a
 // row's output position is known before the step: no compaction scan, no
 // ordering between wavefronts.  The operator slice is stored column-major,
 // so the k-th neighbours of the 64 rows are one contiguous 512-byte load
@@ -617,6 +617,78 @@ __device__ __forceinline__ EllRow row_regs(const RowBuf<kRowRegs>& r, int cnt) {
   return o;
 }
 
+// A slice flagged interior: when every row still holds one layer c and every
+// neighbour row that same single layer, the update of each row is exact and
+// trivial -- S = {c}, n = 1, every term of d_c cancels, and the normalised
+// value is 1 -- so the rows are written as {c: 1} with the counters and
+// change measures the full path would give (one row of interest, one entry
+// in and out).  Returns false, having written nothing, when some row of the
+// slice no longer qualifies; the caller then takes the full path.
+__device__ __forceinline__ bool interior_slice(const StepArgs& A, const int sl,
+                                               const unsigned poisoned) {
+  const int lane = threadIdx.x;
+  const int i = sl * kSlice + lane;
+  bool ok = true;
+  int32_t c = -1;
+  float ph = 0.f;
+  if (i < A.n_v) {
+    // the first two entries of the own row and of each neighbour row
+    const Ent* own = reinterpret_cast<const Ent*>(reinterpret_cast<const char*>(A.u_in) +
+                                                  (uint32_t)i * (uint32_t)sizeof(EllRow));
+    const Ent e0 = own[0], e1 = own[1];
+    c = e0.col;
+    ph = e0.val;
+    ok = c >= 0 && e1.col < 0;
+    const Ent* ops = A.lell + (int64_t)sl * A.op_w * kSlice + lane;
+#pragma unroll
+    for (int k = 0; k < kOpWidth; ++k) {
+      if (k >= A.op_w) break;
+      const Ent le = ops[k * kSlice];
+      if (le.col >= 0) {
+        const Ent* nb = reinterpret_cast<const Ent*>(reinterpret_cast<const char*>(A.u_in) +
+                                                     (uint32_t)le.col * (uint32_t)sizeof(EllRow));
+        ok = ok && nb[0].col == c && nb[1].col < 0;
+      }
+    }
+    // entries beyond the slice width are not checked here
+    if (A.op_w == kOpWidth && ops[(kOpWidth - 1) * kSlice].col >= 0) ok = false;
+  }
+  if (!__all(ok)) return false;
+  if (poisoned) return true;  // as the full path: a failed chunk writes nothing
+  if (sl == 0 && lane == 0) {
+    *A.ovf_ctr_next = 0u;
+    *A.wide_ctr_next = 0u;
+  }
+  int rows = 0, changed = 0;
+  float dmax = 0.f;
+  if (i < A.n_v) {
+    EllRow o;
+    o.e[0] = Ent{c, 1.0f};
+#pragma unroll
+    for (int p = 1; p < kEll; ++p) o.e[p] = Ent{-1, 0.f};
+    *reinterpret_cast<EllRow*>(reinterpret_cast<char*>(A.u_out) +
+                               (uint32_t)i * (uint32_t)sizeof(EllRow)) = o;
+    rows = 1;
+    if (A.measure) {
+      ChangeAcc a;
+      a.add(c, ph, 1.0f, A.c);
+      changed = a.changed();
+      dmax = a.dmax;
+    }
+  }
+  const int n = wave_sum(rows), ch = A.measure ? wave_sum(changed) : 0;
+  const float dm = A.measure ? wave_max(dmax) : 0.f;
+  if (lane == 0) {
+    StepStats* P = A.parts + (sl & (kParts - 1));
+    atomicAdd(&P->skel, (unsigned long long)n);
+    atomicAdd(&P->out, (unsigned long long)n);
+    atomicAdd(&P->in, (unsigned long long)n);
+    if (ch) atomicAdd(&P->changed, (unsigned long long)ch);
+    if (dm > 0.f) atomicMax(&P->dmax, (unsigned long long)__float_as_uint(dm));
+  }
+  return true;
+}
+
 // One wavefront's slice sl of one step of the fields described by A.
 // TYPED: per-pair coefficients (a separate instance, so that the scalar
 // step keeps its registers).
@@ -630,6 +702,7 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
   const unsigned poisoned =
       *(const __attribute__((address_space(4))) unsigned int*)&A.flags->poisoned;
   const int i = sl * kSlice + lane;
+  if (A.slice_cls && A.slice_cls[sl] && interior_slice(A, sl, poisoned)) return;
 
   RowBuf<kRowRegs> r;
   int cnt = 0, n_keep = 0, n_skel = 0, n_in = 0, ev = 0, rowovf = 0, changed = 0;
@@ -684,11 +757,10 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
       row[0] = Ent{kOvfMark, 0.f};
       row[1] = Ent{fits ? (int32_t)o : 0, 0.f};
       row[2] = Ent{fits ? n_keep : 0, 0.f};
-      row[3] = Ent{-1, 0.f};
       dst = fits ? A.ovf_out + o : nullptr;
     } else if (wide < 0) {
-      // the whole row from registers: two 16-byte stores, contiguous across
-      // the wavefront
+      // the whole row from registers: 24-byte stores, contiguous across the
+      // wavefront
       *reinterpret_cast<EllRow*>(reinterpret_cast<char*>(A.u_out) +
                                  (uint32_t)i * (uint32_t)sizeof(EllRow)) = row_regs(r, cnt);
       dst = nullptr;
