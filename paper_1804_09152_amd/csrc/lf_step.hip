@@ -80,9 +80,10 @@ __device__ __forceinline__ float4 pair_coef(const StepConsts& c, int tj, int tl,
 }
 
 // Update of one row's active layers.  Slots s < cnt hold the row's union of
-// layers (col, phi = U(i,col), lam = field Laplacian).  out_of(r, s)
-// receives the normalised kept value, or -1 (or 0 in register slots beyond
-// the wavefront's largest count).  TYPED = false: one value per coefficient
+// layers (col, phi = U(i,col), lam = field Laplacian); ub is the
+// wavefront's largest cnt in the register path (UNROLL), unused in the wide
+// path.  out_of(r, s) receives the normalised kept value, or -1 (or 0 in
+// register slots beyond ub).  TYPED = false: one value per coefficient
 // matrix, the sums over layers collapse to row totals (closed form above).
 // TYPED: per-pair coefficients from the layer types,
 //   Q_j = sum_{l != j} (a_jl lam_l / 2 + w_jl phi_l),
@@ -90,34 +91,33 @@ __device__ __forceinline__ float4 pair_coef(const StepConsts& c, int tj, int tl,
 //   d_j = -(mu/n) (n Q_j - sum_k Q_k - sqrt(phi_j) G_j),
 // the same sums of Algorithm 1 with the pairs spelled out (O(n^2) per row).
 template <int K, bool UNROLL, bool TYPED, class B>
-__device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, int& n_keep,
-                                           int& n_skel, int& ev) {
+__device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepConsts& c,
+                                           int& n_keep, int& n_skel, int& ev) {
   using M = typename MaskT<K>::type;
   M act = 0;
   int n = 0, nC = 0;
   bool hb = false;
   float sqb = 0.f, T = 0.f, PC = 0.f, RC = 0.f, Pall = 0.f, Rall = 0.f;
-// unrolled: stop at the wavefront's largest slot count (slots at and above
-// cnt keep out = -1, set by the caller); runtime loop for the wide path
+// unrolled: stop at the wavefront's largest slot count ub, a uniform value
+// (slots at and above the row's count hold layer -1 with phi = lam = 0, so
+// they are never active); runtime loop for the wide path
 #define LF_SLOTS                                  \
   _Pragma("unroll") for (int s = 0; s < K; ++s)   \
-    if (!__any(s < cnt)) break;                   \
+    if (s >= ub) break;                           \
     else
 #define LF_SLOTS_RT _Pragma("unroll 1") for (int s = 0; s < K; ++s)
   if constexpr (UNROLL) {
     LF_SLOTS {
-      if (s < cnt) {
-        const float ph = r.phi[s];
-        if (ph > 0.f || (ph == 0.f && r.lam[s] > 0.f)) {
-          act |= (M)1 << s;
-          ++n;
-          T += r.lam[s];
-          const float sq = root(ph);
-          Pall += ph;
-          Rall += sq;
-          if (r.col[s] == c.n_s) { hb = true; sqb = sq; }
-          else { ++nC; PC += ph; RC += sq; }
-        }
+      const float ph = r.phi[s];
+      if (ph > 0.f || (ph == 0.f && r.lam[s] > 0.f)) {
+        act |= (M)1 << s;
+        ++n;
+        T += r.lam[s];
+        const float sq = root(ph);
+        Pall += ph;
+        Rall += sq;
+        if (r.col[s] == c.n_s) { hb = true; sqb = sq; }
+        else { ++nC; PC += ph; RC += sq; }
       }
     }
   } else {
@@ -179,7 +179,7 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
     // inner loops over the other active slots l
 #define LF_INNER                                                  \
   _Pragma("unroll") for (int l = 0; l < (UNROLL ? K : 1); ++l)    \
-    if (!__any(l < cnt)) break;                                   \
+    if (l >= ub) break;                                           \
     else
 #define LF_INNER_RT for (int l = 0; l < cnt; ++l)
     // n Q_j - sqrt(phi_j) G_j per slot: registers in the register path, the workspace row's
@@ -284,16 +284,21 @@ __device__ __forceinline__ void row_update(B& r, int cnt, const StepConsts& c, i
 
 // ---- register path --------------------------------------------------------
 
+// whether the predicate holds on some active lane of the wavefront (the
+// ballot's mask is the compare's own result, with no re-materialisation)
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 // The slot loops below stop at the wavefront's largest slot count (a uniform
 // branch), and are otherwise straight-line selects: no early exits, so the
 // register arrays stay in place instead of being copied per control path.
 #define LF_FOR_USED_SLOTS(bound)                   \
   _Pragma("unroll") for (int s = 0; s < kRowRegs; ++s) \
-    if (!__any(s < (bound))) break;                 \
+    if (!wave_any(s < (bound))) break;              \
     else
 
 // adds w*x into layer c (a new slot when c is not held yet); ovf when the
-// row needs more than kRowRegs slots
+// row needs more than kRowRegs slots.  For the rare entries met under
+// divergent control (overflow rows, operator rows beyond the slice).
 __device__ __forceinline__ void add_regs(RowBuf<kRowRegs>& r, int& cnt, bool& ovf, int c, float w,
                                          float x) {
   bool found = false;
@@ -315,8 +320,15 @@ __device__ __forceinline__ void add_regs(RowBuf<kRowRegs>& r, int& cnt, bool& ov
   }
 }
 
+// the wavefront's largest slot count, from every lane's count
+__device__ __forceinline__ int wave_slots(int cnt) {
+  int ub = 0;
+#pragma unroll
+  for (int s = 0; s < kRowRegs; ++s) ub += wave_any(cnt > s) ? 1 : 0;
+  return ub;
+}
+
 constexpr int kXcds = 8;   // accelerator dies of the MI355X, each with its own L2
-constexpr int kNbPre = 7;  // neighbours whose operator entries are prefetched
 #ifndef LF_WIN
 #define LF_WIN 3
 #endif
@@ -356,6 +368,56 @@ __device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
   return RowView{e, n};
 }
 
+// One inline neighbour row (up to kEll entries, ascending layers, filled
+// from entry 0) scaled by w, merged by every lane at once.  `ub` is the
+// wavefront's largest slot count, kept in a scalar register and updated from
+// the lanes that open a slot, so the slot loops cost no vector compare for
+// their bound; it must stay uniform, so this is called only in
+// wavefront-uniform control flow.  One pass over the slots searches for all
+// of the row's entries (its entries are distinct layers, so at most one
+// matches a slot; a slot that none matches gets fma(w, 0, lam), which leaves
+// it unchanged); then each entry no slot holds opens one, in entry order --
+// the same sums and slot order as add_regs called once per entry.  key[j]
+// is the layer of entry j, or -3 on a lane where entry j does not take part
+// (slot layers are >= -1, so it matches nothing and opens nothing).  NV:
+// the entries that take part on some lane.
+template <int NV>
+__device__ __forceinline__ void add_row_wave(RowBuf<kRowRegs>& r, int& cnt, int& ub, bool& ovf,
+                                             const int (&key)[kEll], const float (&x)[kEll],
+                                             float w) {
+  bool found[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) found[j] = key[j] < 0;
+#pragma unroll
+  for (int s = 0; s < kRowRegs; ++s) {
+    if (s >= ub) break;
+    float xs = 0.f;
+#pragma unroll
+    for (int j = NV - 1; j >= 0; --j) {
+      const bool m = r.col[s] == key[j];
+      xs = m ? x[j] : xs;
+      found[j] = found[j] || m;
+    }
+    r.lam[s] = fmaf(w, xs, r.lam[s]);
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    if (!wave_any(!found[j])) continue;
+    const bool ins = !found[j] && cnt < kRowRegs;
+    const float wx = w * x[j];
+#pragma unroll
+    for (int s = 0; s < kRowRegs; ++s) {
+      if (s > ub) break;
+      const bool m = ins && s == cnt;
+      r.col[s] = m ? key[j] : r.col[s];
+      r.lam[s] = m ? wx : r.lam[s];
+    }
+    ovf = ovf || (!found[j] && !ins);
+    ub += wave_any(ins && cnt == ub) ? 1 : 0;  // cnt <= ub on every lane
+    cnt += ins ? 1 : 0;
+  }
+}
+
 // Row i's gather into register slots: its own layers (lam starts at L_ii *
 // phi) and then every neighbour row scaled by L(i,u), each row in layer
 // order.  The neighbour rows stream through a window of kWin rows (the row
@@ -368,86 +430,107 @@ __device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
 // or kGatherWide when the row touches more than kRowRegs layers.
 constexpr int kGatherOk = 0, kGatherWide = 1;
 
-__device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& n_in, int i,
-                                           const Ent* ops, const StepArgs& A) {
+__device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& ub, int& n_in,
+                                           const int i, const bool live, const Ent* ops,
+                                           const StepArgs& A) {
+  // Every lane runs the gather (a lane past the last row, live false, reads
+  // row 0 and adds nothing), so that the slot bound stays wavefront-uniform.
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   cnt = 0;
-  const EllRow own = row_at(A.u_in, i);
+  const int ic = live ? i : 0;
+  const EllRow own = row_at(A.u_in, ic);
   const float dg = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.ldiag) +
-                                                   (uint32_t)i * 4u);
+                                                   (uint32_t)ic * 4u);
   // entries of U_t in this row (for the counters)
   n_in = 0;
 #pragma unroll
   for (int j = 0; j < kEll; ++j) n_in += own.e[j].col >= 0 ? 1 : 0;
-  if (is_ovf(own.e[0])) n_in = own.e[2].col;
-  Ent le[kNbPre];
+  const bool own_ovf = live && is_ovf(own.e[0]);
+  if (own_ovf) n_in = own.e[2].col;
+  if (!live) n_in = 0;
+  // operator entries: lanes past the last row hold {-1, 0} in the slice
+  Ent le[kOpWidth];
 #pragma unroll
-  for (int k = 0; k < kNbPre; ++k)
+  for (int k = 0; k < kOpWidth; ++k)
     le[k] = k < A.op_w ? ops[k * kSlice] : Ent{-1, 0.f};
   EllRow win[kWin];
 #pragma unroll
-  for (int k = 0; k < kWin; ++k) win[k] = row_at(A.u_in, le[k].col >= 0 ? le[k].col : i);
+  for (int k = 0; k < kWin; ++k) win[k] = row_at(A.u_in, le[k].col >= 0 ? le[k].col : ic);
   bool ovf = false;
   // the entries of an overflow row, scaled by w
   auto merge_ovf = [&](const EllRow& u, float w) {
     const RowView v = ovf_view(A, u);
     for (int p = 0; p < v.n; ++p) add_regs(r, cnt, ovf, v.p[p].col, w, v.p[p].val);
   };
-  // own row: slots 0..3 in layer order (an overflow row is merged last)
-  const bool own_ovf = is_ovf(own.e[0]);
+  // own row: slots 0..kEll-1 in layer order (an overflow row is merged last)
 #pragma unroll
   for (int j = 0; j < kEll; ++j) {
-    if (!own_ovf && own.e[j].col >= 0) {
+    if (live && !own_ovf && own.e[j].col >= 0) {
       r.col[j] = own.e[j].col;
       r.phi[j] = own.e[j].val;
       r.lam[j] = dg * own.e[j].val;
       cnt = j + 1;
     }
   }
-  unsigned onb = 0;  // prefetched neighbours whose rows are overflow rows
+  ub = wave_slots(cnt);
+  unsigned onb = 0;  // neighbours in the slice whose rows are overflow rows
 #pragma unroll
-  for (int k = 0; k < kNbPre; ++k) {
+  for (int k = 0; k < kOpWidth; ++k) {
+    if (k >= A.op_w) break;
     const EllRow u = win[k % kWin];
-    if (k + kWin < kNbPre)
-      win[k % kWin] = row_at(A.u_in, le[k + kWin].col >= 0 ? le[k + kWin].col : i);
-    if (le[k].col < 0) continue;
-    if (is_ovf(u.e[0])) {
-      onb |= 1u << k;
-      continue;
-    }
+    if (k + kWin < kOpWidth && k + kWin < A.op_w)
+      win[k % kWin] = row_at(A.u_in, le[k + kWin].col >= 0 ? le[k + kWin].col : ic);
+    const bool nb = le[k].col >= 0;
+    const bool nb_ovf = nb && is_ovf(u.e[0]);
+    onb |= nb_ovf ? 1u << k : 0u;
+    int key[kEll];
+    float x[kEll];
+    int nv = 0;
 #pragma unroll
-    for (int j = 0; j < kEll; ++j)
-      if (u.e[j].col >= 0) add_regs(r, cnt, ovf, u.e[j].col, le[k].val, u.e[j].val);
+    for (int j = 0; j < kEll; ++j) {
+      const bool v = nb && !nb_ovf && u.e[j].col >= 0;
+      key[j] = v ? u.e[j].col : -3;  // slot layers are >= -1
+      x[j] = u.e[j].val;
+      nv += wave_any(v) ? 1 : 0;
+    }
+    static_assert(kEll == 3, "add_row_wave instances below cover kEll entries");
+    if (nv > 0) add_row_wave<3>(r, cnt, ub, ovf, key, x, le[k].val);
   }
-  auto more = [&](const Ent& l) {  // neighbours beyond the prefetched ones
-    if (l.col < 0) return;
-    const EllRow u = row_at(A.u_in, l.col);
-    if (is_ovf(u.e[0])) {
-      merge_ovf(u, l.val);
-      return;
-    }
+  // the rare entries, under divergent control: the slot bound is counted
+  // again afterwards
+  const bool tail = A.op_w == kOpWidth && le[kOpWidth - 1].col >= 0;  // rows beyond the slices
+  if (wave_any(tail || onb != 0u || own_ovf)) {
+    if (tail) {
+      for (int q = A.lptr[i] + kOpWidth; q < A.lptr[i + 1]; ++q) {
+        const Ent l = A.lent[q];
+        if (l.col < 0) continue;
+        const EllRow u = row_at(A.u_in, l.col);
+        if (is_ovf(u.e[0])) {
+          merge_ovf(u, l.val);
+          continue;
+        }
 #pragma unroll
-    for (int j = 0; j < kEll; ++j)
-      if (u.e[j].col >= 0) add_regs(r, cnt, ovf, u.e[j].col, l.val, u.e[j].val);
-  };
-  for (int k = kNbPre; k < A.op_w; ++k) more(ops[k * kSlice]);
-  if (A.op_w == kOpWidth && ops[(kOpWidth - 1) * kSlice].col >= 0)  // rows beyond the slices
-    for (int q = A.lptr[i] + kOpWidth; q < A.lptr[i + 1]; ++q) more(A.lent[q]);
-  while (onb) {  // the overflow rows among the prefetched neighbours
-    const int k = __builtin_ctz(onb);
-    onb &= onb - 1u;
-    const Ent l = ops[k * kSlice];
-    merge_ovf(row_at(A.u_in, l.col), l.val);
-  }
-  if (own_ovf) {  // own entries: add L_ii * phi and set phi of their slots
-    const RowView o = ovf_view(A, row_at(A.u_in, i));
-    for (int p = 0; p < o.n; ++p) {
-      const Ent e = o.p[p];
-      add_regs(r, cnt, ovf, e.col, dg, e.val);
-#pragma unroll
-      for (int t = 0; t < kRowRegs; ++t) r.phi[t] = r.col[t] == e.col ? e.val : r.phi[t];
+        for (int j = 0; j < kEll; ++j)
+          if (u.e[j].col >= 0) add_regs(r, cnt, ovf, u.e[j].col, l.val, u.e[j].val);
+      }
     }
+    while (onb) {  // the overflow rows among the slice's neighbours
+      const int k = __builtin_ctz(onb);
+      onb &= onb - 1u;
+      const Ent l = ops[k * kSlice];
+      merge_ovf(row_at(A.u_in, l.col), l.val);
+    }
+    if (own_ovf) {  // own entries: add L_ii * phi and set phi of their slots
+      const RowView o = ovf_view(A, row_at(A.u_in, i));
+      for (int p = 0; p < o.n; ++p) {
+        const Ent e = o.p[p];
+        add_regs(r, cnt, ovf, e.col, dg, e.val);
+#pragma unroll
+        for (int t = 0; t < kRowRegs; ++t) r.phi[t] = r.col[t] == e.col ? e.val : r.phi[t];
+      }
+    }
+    ub = wave_slots(cnt);
   }
   return ovf ? kGatherWide : kGatherOk;
 }
@@ -497,7 +580,7 @@ __device__ __forceinline__ int wide_row(int i, const Ent* ops, const StepArgs* A
   }
   for (int s = cnt; s < kRowWide; ++s) { r->col[s] = -1; r->phi[s] = 0.f; r->lam[s] = 0.f; }
   int n_keep = 0;
-  row_update<kRowWide, false, TYPED>(*r, cnt, A->c, n_keep, *n_skel, *ev);
+  row_update<kRowWide, false, TYPED>(*r, cnt, cnt, A->c, n_keep, *n_skel, *ev);
   r->cnt = cnt;
   r->n_keep = n_keep;
   return n_keep;
@@ -519,6 +602,32 @@ __device__ __forceinline__ void wide_write(const WideRow* r, Ent* dst) {
 __device__ __forceinline__ void step_failed(const StepArgs& A, unsigned bit) {
   atomicOr(&A.flags->poisoned, bit);
   atomicMin(&A.flags->fail_step, A.step_idx);
+}
+
+// Sum over the wavefront, complete in lane 63 only: a scan within each row
+// of 16 lanes by DPP row shifts, then the row totals carried on by DPP row
+// broadcasts (lane 15 into row 1 and lane 47 into row 3; then lane 31 into
+// rows 2 and 3).  Lanes shifted in from outside a row, and rows left out by
+// the row mask, add 0.  Needs every lane active.
+__device__ __forceinline__ unsigned dpp_sum63(unsigned x) {
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+// the same for the maximum of non-negative floats (ordered as their bits)
+__device__ __forceinline__ unsigned dpp_max63(unsigned x) {
+  auto mx = [](unsigned a, unsigned b) { return a > b ? a : b; };
+  x = mx(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true));
+  x = mx(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true));
+  x = mx(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true));
+  x = mx(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true));
+  x = mx(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+  x = mx(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
+  return x;
 }
 
 __device__ __forceinline__ int wave_sum(int x) {
@@ -549,12 +658,14 @@ struct ChangeAcc {
 };
 
 // after the update, lam holds the kept output value or a value <= 0
-__device__ __forceinline__ void row_change(const RowBuf<kRowRegs>& r, int cnt,
+// (slots at and above the row's count hold layer -1 and take no part; ub is
+// the wavefront's largest count)
+__device__ __forceinline__ void row_change(const RowBuf<kRowRegs>& r, int ub,
                                            const StepConsts& k, int& changed, float& dmax) {
   ChangeAcc a;
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) {
-    if (!__any(s < cnt)) break;
+    if (s >= ub) break;
     a.add(r.col[s], r.phi[s], r.lam[s], k);
   }
   changed = a.changed();
@@ -576,15 +687,16 @@ __device__ __forceinline__ float wave_max(float x) {
 }
 
 // kept register-path entries in ascending layer order at dst[0..n_keep)
-__device__ __forceinline__ void write_regs(const RowBuf<kRowRegs>& r, int cnt, Ent* dst) {
+// (ub: the wavefront's largest slot count)
+__device__ __forceinline__ void write_regs(const RowBuf<kRowRegs>& r, int ub, Ent* dst) {
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) {
-    if (!__any(s < cnt)) break;
+    if (s >= ub) break;
     if (r.lam[s] > 0.f) {
       int rank = 0;
 #pragma unroll
       for (int t = 0; t < kRowRegs; ++t) {
-        if (!__any(t < cnt)) break;
+        if (t >= ub) break;
         rank += (r.lam[t] > 0.f && r.col[t] < r.col[s]) ? 1 : 0;
       }
       dst[rank] = Ent{r.col[s], r.lam[s]};
@@ -593,17 +705,17 @@ __device__ __forceinline__ void write_regs(const RowBuf<kRowRegs>& r, int cnt, E
 }
 
 // kept register-path entries (at most kEll) as one fixed-width row
-__device__ __forceinline__ EllRow row_regs(const RowBuf<kRowRegs>& r, int cnt) {
+__device__ __forceinline__ EllRow row_regs(const RowBuf<kRowRegs>& r, int ub) {
   EllRow o;
 #pragma unroll
   for (int p = 0; p < kEll; ++p) o.e[p] = Ent{-1, 0.f};
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) {
-    if (!__any(s < cnt)) break;
+    if (s >= ub) break;
     int rank = 0;
 #pragma unroll
     for (int t = 0; t < kRowRegs; ++t) {
-      if (!__any(t < cnt)) break;
+      if (t >= ub) break;
       rank += (r.lam[t] > 0.f && r.col[t] < r.col[s]) ? 1 : 0;
     }
     const bool kept = r.lam[s] > 0.f;
@@ -705,17 +817,12 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
   if (A.slice_cls && A.slice_cls[sl] && interior_slice(A, sl, poisoned)) return;
 
   RowBuf<kRowRegs> r;
-  int cnt = 0, n_keep = 0, n_skel = 0, n_in = 0, ev = 0, rowovf = 0, changed = 0;
+  int cnt = 0, ub = 0, n_keep = 0, n_skel = 0, n_in = 0, ev = 0, rowovf = 0, changed = 0;
   float dmax = 0.f;
   int wide = -1;  // workspace slot of a wide row
-#pragma unroll
-  for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
-  bool in_regs = false;
   // this row's operator entries: column-major in the wavefront's slice
   const Ent* ops = A.lell + (int64_t)sl * A.op_w * kSlice + lane;
-  if (i < A.n_v) {
-    in_regs = gather_regs(r, cnt, n_in, i, ops, A) == kGatherOk;
-  }
+  const bool in_regs = gather_regs(r, cnt, ub, n_in, i, i < A.n_v, ops, A) == kGatherOk;
   // An earlier step of the chunk failed: write nothing (no row, no overflow
   // entry, no workspace slot, no counter), so that the last good fields (the
   // input of the failed step, which this step would overwrite) survive for
@@ -727,8 +834,8 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
   }
   if (i < A.n_v) {
     if (in_regs) {
-      row_update<kRowRegs, true, TYPED>(r, cnt, A.c, n_keep, n_skel, ev);
-      if (A.measure) row_change(r, cnt, A.c, changed, dmax);
+      row_update<kRowRegs, true, TYPED>(r, cnt, ub, A.c, n_keep, n_skel, ev);
+      if (A.measure) row_change(r, ub, A.c, changed, dmax);
     } else {
       const unsigned slot = atomicAdd(A.wide_ctr, 1u);
       if (slot < (unsigned)A.wide_cap) {
@@ -762,23 +869,24 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
       // the whole row from registers: 24-byte stores, contiguous across the
       // wavefront
       *reinterpret_cast<EllRow*>(reinterpret_cast<char*>(A.u_out) +
-                                 (uint32_t)i * (uint32_t)sizeof(EllRow)) = row_regs(r, cnt);
+                                 (uint32_t)i * (uint32_t)sizeof(EllRow)) = row_regs(r, ub);
       dst = nullptr;
     } else {
       for (int p = n_keep; p < kEll; ++p) row[p] = Ent{-1, 0.f};
     }
     if (dst) {
-      if (wide < 0) write_regs(r, cnt, dst);
+      if (wide < 0) write_regs(r, ub, dst);
       else if (!rowovf) wide_write(A.wide + wide, dst);
     }
   }
   // counters of the slice, added into one of kParts slots; per row at most
   // 64 rows of interest and kept entries, so a wavefront's sums fit 16 bits
-  // and travel packed
-  const int so = wave_sum(n_skel | (n_keep << 16)), in = wave_sum(n_in),
-            ec = wave_sum(ev | (changed << 16));
-  const float dm = A.measure ? wave_max(dmax) : 0.f;
-  if (lane == 0) {
+  // and travel packed; the totals are complete in the last lane
+  const unsigned so = dpp_sum63((unsigned)n_skel | ((unsigned)n_keep << 16)),
+                 in = dpp_sum63((unsigned)n_in),
+                 ec = dpp_sum63((unsigned)ev | ((unsigned)changed << 16));
+  const float dm = A.measure ? __uint_as_float(dpp_max63(__float_as_uint(dmax))) : 0.f;
+  if (lane == kSlice - 1) {
     StepStats* P = A.parts + (sl & (kParts - 1));
     atomicAdd(&P->skel, (unsigned long long)(so & 0xffff));
     atomicAdd(&P->out, (unsigned long long)(so >> 16));
