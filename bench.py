@@ -76,16 +76,25 @@ def traffic_from_profile(alg_bytes_per_launch: float):
     return d.get("hbm_bytes_per_launch")
 
 
-def _counter_means(d: str, kernel: str):
-    """Mean per dispatch of each counter of `kernel` in a rocprofv3 CSV folder."""
+def _counter_means(d: str, kernel: str, grid: int = 0):
+    """Mean per dispatch of each counter of `kernel` in a rocprofv3 CSV folder
+    (only the dispatches of that grid size, when grid > 0)."""
     import csv
     import glob
     acc = {}
     for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(fn)):
-            if kernel in r["Kernel_Name"]:
+            if kernel in r["Kernel_Name"] and (grid <= 0 or int(r["Grid_Size"]) == grid):
                 acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def _c3_step_grid(level: int = 9) -> int:
+    """Threads in one step-kernel launch on the C3 mesh (64-row slices, the
+    slice count rounded up to a multiple of 8 dies)."""
+    n_v = 10 * 4 ** level + 2
+    slices = (n_v + 63) // 64
+    return 64 * 8 * ((slices + 7) // 8)
 
 
 def summarize_counters(fetch_dir, write_dir, copyf_dir, copyw_dir, probe_mib, out_path):
@@ -95,8 +104,8 @@ def summarize_counters(fetch_dir, write_dir, copyf_dir, copyw_dir, probe_mib, ou
     probe = probe_mib * (1 << 20)
     cf, _ = _counter_means(copyf_dir, "copyBuffer")
     cw, _ = _counter_means(copyw_dir, "copyBuffer")
-    kf, nf = _counter_means(fetch_dir, "k_step<false>")
-    kw, nw = _counter_means(write_dir, "k_step<false>")
+    kf, nf = _counter_means(fetch_dir, "k_step<false>", _c3_step_grid())
+    kw, nw = _counter_means(write_dir, "k_step<false>", _c3_step_grid())
     f_scale = probe / (cf["FETCH_SIZE"] * 1024)
     w_scale = probe / (cw["WRITE_SIZE"] * 1024)
     fetch = kf["FETCH_SIZE"] * 1024 * f_scale
@@ -182,10 +191,13 @@ def summarize_instructions(pmc_dir: str, out_path: str, last: int = 10):
              f"| SALU instructions | {salu:,.0f} |",
              f"| branch instructions | {m['SQ_INSTS_BRANCH'] / waves:,.0f} |",
              f"| active lanes per VALU instruction | {lanes:.1%} |", "",
+             f"| VALU busy (SQ_ACTIVE_INST_VALU, 4-cycle units) | {m['SQ_ACTIVE_INST_VALU'] / waves:,.0f} |",
+             f"| wavefront lifetime (SQ_WAVE_CYCLES, 4-cycle units) | {m['SQ_WAVE_CYCLES'] / waves:,.0f} |",
+             f"| waiting on an instruction's issue (SQ_WAIT_INST_ANY) | {m['SQ_WAIT_INST_ANY'] / waves:,.0f} |",
+             "",
              f"VALU issue: {valu:,.0f} instructions x {waves:,.0f} wavefronts x 4 cycles / "
-             f"{simds:,} SIMDs / {ghz} GHz = {issue_us:.1f} us per launch, against the step's "
-             "97-99 us", "(kernel trace summary of the same job): the step is bound by "
-             "VALU issue, not by HBM.", ""]
+             f"{simds:,} SIMDs / {ghz} GHz = {issue_us:.1f} us per launch; the step's time is in "
+             "k_step_c3_trace.md.", ""]
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines))
     print(json.dumps({"valu_per_wave": valu, "salu_per_wave": salu, "waves": waves,
@@ -201,7 +213,7 @@ def _kname(name: str) -> str:
 def summarize_trace(trace_dir: str, plain_json: str, traced_json: str, out_dir: str):
     """Writes the kernel-trace summaries of the C3 job (step kernel and the
     post-processing of the last job) from a rocprofv3 --kernel-trace --stats
-    run of `bench.py --no-c2 --no-batch --no-serve --no-typed --no-cpu-baseline`, next
+    run of `bench.py --no-c2 --no-batch --no-graphs --no-serve --no-typed --no-cpu-baseline`, next
     to the bench lines of that run and of a plain run."""
     import collections
     import csv
@@ -210,7 +222,8 @@ def summarize_trace(trace_dir: str, plain_json: str, traced_json: str, out_dir: 
     traced = json.loads(open(traced_json).read().strip().splitlines()[-1])
     cmd = ["```", "cd /tmp && export TMPDIR=/tmp",
            "rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- \\",
-           "    python3 <repo>/bench.py --no-c2 --no-batch --no-serve --no-typed --no-cpu-baseline",
+           "    python3 <repo>/bench.py --no-c2 --no-batch --no-graphs --no-serve --no-typed "
+           "--no-cpu-baseline",
            "python3 <repo>/bench.py --trace-summary <out> <plain bench line> <traced bench line>",
            "```"]
     lines = ["# Kernel trace: C3 job (bench.py C3 section)", "",

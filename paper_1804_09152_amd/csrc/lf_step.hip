@@ -484,18 +484,16 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& u
     const bool nb = le[k].col >= 0;
     const bool nb_ovf = nb && is_ovf(u.e[0]);
     onb |= nb_ovf ? 1u << k : 0u;
+    const bool row_ok = nb && !nb_ovf;
     int key[kEll];
     float x[kEll];
-    int nv = 0;
 #pragma unroll
     for (int j = 0; j < kEll; ++j) {
-      const bool v = nb && !nb_ovf && u.e[j].col >= 0;
-      key[j] = v ? u.e[j].col : -3;  // slot layers are >= -1
+      key[j] = row_ok && u.e[j].col >= 0 ? u.e[j].col : -3;  // slot layers are >= -1
       x[j] = u.e[j].val;
-      nv += wave_any(v) ? 1 : 0;
     }
-    static_assert(kEll == 3, "add_row_wave instances below cover kEll entries");
-    if (nv > 0) add_row_wave<3>(r, cnt, ub, ovf, key, x, le[k].val);
+    // (a row's entries fill from entry 0: none takes part where entry 0 does not)
+    if (wave_any(key[0] >= 0)) add_row_wave<kEll>(r, cnt, ub, ovf, key, x, le[k].val);
   }
   // the rare entries, under divergent control: the slot bound is counted
   // again afterwards
