@@ -158,6 +158,190 @@ def state_probe(level: int, seeds_n: int, warm: int, steps: int):
     m.close()
 
 
+def _row_stats(rp, col, faces, n_v, inline: int = 3):
+    """Entries per row, layers per row neighbourhood (the row and its mesh
+    neighbours: the slots the step's merge fills), and whether the
+    neighbourhood holds a row longer than the `inline` entries a fixed-width
+    row keeps (an overflow row) -- of one mesh's fields."""
+    import numpy as np
+    import scipy.sparse as sp
+    F = np.asarray(faces, np.int64)
+    r = np.concatenate([F[:, 0], F[:, 1], F[:, 2], F[:, 1], F[:, 2], F[:, 0], np.arange(n_v)])
+    c = np.concatenate([F[:, 1], F[:, 2], F[:, 0], F[:, 0], F[:, 1], F[:, 2], np.arange(n_v)])
+    A = sp.csr_matrix((np.ones(r.size, np.float32), (r, c)), shape=(n_v, n_v))
+    ncol = int(col.max()) + 1 if col.size else 1
+    U = sp.csr_matrix((np.ones(col.size, np.float32), col, rp), shape=(n_v, ncol))
+    N = (A @ U).tocsr()
+    nnz = np.diff(rp)
+    reads_ovf = (A @ (nnz > inline).astype(np.float32)) > 0
+    return nnz, np.diff(N.indptr), reads_ovf
+
+
+def _state_stats(parts) -> dict:
+    """Row statistics over (entries, layers per neighbourhood, reads an
+    overflow row) arrays of one or more meshes."""
+    import numpy as np
+    nnz = np.concatenate([p[0] for p in parts])
+    uni = np.concatenate([p[1] for p in parts])
+    ovf = np.concatenate([p[2] for p in parts])
+    return {"entries_per_row": float(nnz.mean()), "layers_per_neighbourhood": float(uni.mean()),
+            "overflow_rows": int((nnz > 3).sum()), "rows_reading_overflow": int(ovf.sum()),
+            "neighbourhood_hist_1_to_8_9plus": [int((uni == q).sum()) for q in range(1, 9)]
+            + [int((uni >= 9).sum())]}
+
+
+def _grid_of(n_rows: int) -> int:
+    """Threads in one step-kernel launch over n_rows rows."""
+    slices = (n_rows + 63) // 64
+    return 64 * 8 * ((slices + 7) // 8)
+
+
+def batch_probe(n_meshes: int, steps: int):
+    """The C3 job at steps 1,000-1,000+steps and the C4 batch at steps
+    250-250+steps (for per-dispatch counters of the step kernel on both), then
+    the row statistics of both states on the host (one JSON line)."""
+    import numpy as np
+    import paper_1804_09152_amd as lfb
+    from paper_1804_09152_amd import inputs as I
+    import torch
+    lfb.load()
+    ctx = lfb.Context(0)
+    out = {}
+    mesh, seeds = I.config_c3()
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, lfb.LF_OP_COTAN)
+    f = lfb.Fields(m, seeds)
+    f.step(1000)
+    torch.cuda.synchronize()
+    f.step(steps)
+    torch.cuda.synchronize()
+    log("batch probe: C3 done")
+    rp, col, _ = f.export()
+    out["c3"] = {"grid": _grid_of(mesh.n_v), "n_v": int(mesh.n_v), "cells": int(seeds.size),
+                 **_state_stats([_row_stats(rp, col, mesh.F, mesh.n_v)])}
+    f.close()
+    m.close()
+    items = I.batch_tori(n_meshes)
+    B = lfb.Batch(ctx, [(mm.V, mm.F) for mm, _ in items], lfb.LF_OP_GRAPH, [sd for _, sd in items])
+    B.step(250)
+    torch.cuda.synchronize()
+    B.step(steps)
+    torch.cuda.synchronize()
+    log("batch probe: C4 done")
+    parts = []
+    for q, (mm, _) in enumerate(items):
+        rp, col, _ = B.export(q)
+        parts.append(_row_stats(rp, col, mm.F, mm.n_v))
+    n_v = int(sum(mm.n_v for mm, _ in items))
+    out["c4"] = {"grid": _grid_of(n_v), "n_v": n_v, "cells": int(sum(sd.size for _, sd in items)),
+                 **_state_stats(parts)}
+    B.close()
+    print(json.dumps(out), flush=True)
+
+
+def summarize_batch(probe_json: str, pmc_dir: str, trace_dir: str, fetch_dir: str, write_dir: str,
+                    out_path: str, last: int = 10):
+    """Per-vertex cost of the batched step against the single-mesh step, from
+    the runs of batch_probe: kernel time (trace), instructions (SQ counters),
+    HBM bytes (FETCH_SIZE x 2 + WRITE_SIZE, the copy-probe scale factors of
+    k_step_c3_counters.json) and the row statistics."""
+    import csv
+    import glob
+    probe = json.loads(open(probe_json).read().strip().splitlines()[-1])
+    cal = json.load(open(os.path.join(ROOT, "profiles", "k_step_c3_counters.json")))
+
+    def per_grid(d, grid):
+        acc = {}
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(fn)):
+                if "k_step<false>" in r["Kernel_Name"] and int(r["Grid_Size"]) == grid:
+                    acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v[-last:]) / len(v[-last:]) for k, v in acc.items()}
+
+    trace = sorted(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv"))),
+                   key=lambda r: int(r["Start_Timestamp"]))
+
+    def trace_us(grid):
+        """Mean of the last launches of the step kernel over `grid` threads,
+        and of the wide-row kernel launched right after each of them."""
+        step, wide = [], []
+        for q, r in enumerate(trace):
+            if "k_step<false>" in r["Kernel_Name"] and int(r["Grid_Size_X"]) == grid:
+                step.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                nxt = trace[q + 1] if q + 1 < len(trace) else None
+                wide.append(int(nxt["End_Timestamp"]) - int(nxt["Start_Timestamp"])
+                            if nxt is not None and "k_wide<false>" in nxt["Kernel_Name"] else 0)
+        return (sum(step[-last:]) / len(step[-last:]) / 1e3,
+                sum(wide[-last:]) / len(wide[-last:]) / 1e3)
+
+    rows = {}
+    for key in ("c3", "c4"):
+        p = probe[key]
+        g = p["grid"]
+        sq, fe, wr = per_grid(pmc_dir, g), per_grid(fetch_dir, g), per_grid(write_dir, g)
+        us_step, us_wide = trace_us(g)
+        us = us_step + us_wide
+        waves = sq["SQ_WAVES"]
+        rows[key] = {
+            "n_v": p["n_v"], "cells": p["cells"], "us": us, "us_wide": us_wide,
+            "us_per_mv": us / (p["n_v"] / 1e6),
+            "ovf": p["overflow_rows"], "reads_ovf": p["rows_reading_overflow"],
+            "waves": waves, "valu": sq["SQ_INSTS_VALU"] / waves, "salu": sq["SQ_INSTS_SALU"] / waves,
+            "valu_us": sq["SQ_INSTS_VALU"] * 4 / 1024 / 2.4e3,
+            "bytes_per_v": (fe["FETCH_SIZE"] * 1024 * cal["fetch_scale"]
+                            + wr["WRITE_SIZE"] * 1024 * cal["write_scale"]) / p["n_v"],
+            "epr": p["entries_per_row"], "lpn": p["layers_per_neighbourhood"],
+            "hist": p["neighbourhood_hist_1_to_8_9plus"]}
+    c3, c4 = rows["c3"], rows["c4"]
+    fr = lambda h: " / ".join(f"{100 * x / sum(h):.0f}%" for x in h)
+    lines = [
+        "# Step kernel per vertex: C4 batch against the C3 mesh", "",
+        "Commands (one MI355X, from the repository root; each a run of its own):", "", "```",
+        "cd /tmp && export TMPDIR=/tmp",
+        "python3 <repo>/bench.py --batch-probe 10 > <probe.json>",
+        "rocprofv3 --kernel-trace --output-format csv -d <t> -o run -- python3 <repo>/bench.py --batch-probe 10",
+        "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU --output-format csv -d <s> -o run -- "
+        "python3 <repo>/bench.py --batch-probe 10",
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <f> -o run -- python3 <repo>/bench.py --batch-probe 10",
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <w> -o run -- python3 <repo>/bench.py --batch-probe 10",
+        "python3 <repo>/bench.py --batch-summary <probe.json> <s> <t> <f> <w>",
+        "```", "",
+        "C3: icosphere level 9, 16,384 seeds, cotangent operator, steps 1,000-1,010.  C4: 256 torus",
+        "grids (vertices and seeds log-uniform), graph operator, one batch, steps 250-260.  Means over",
+        f"the last {last} dispatches of each; HBM bytes scaled as in k_step_c3_counters.md.", "",
+        "| per launch | C3 | C4 batch |", "|---|---|---|",
+        f"| vertices | {c3['n_v']:,} | {c4['n_v']:,} |",
+        f"| cells (vertices per cell) | {c3['cells']:,} ({c3['n_v'] / c3['cells']:.0f}) | "
+        f"{c4['cells']:,} ({c4['n_v'] / c4['cells']:.0f}) |",
+        f"| step (us; of which k_wide, the rows touching more than 8 layers) | {c3['us']:.1f} "
+        f"({c3['us_wide']:.1f}) | {c4['us']:.1f} ({c4['us_wide']:.1f}) |",
+        f"| us per million vertices | {c3['us_per_mv']:.1f} | {c4['us_per_mv']:.1f} |",
+        f"| entries of U per row | {c3['epr']:.2f} | {c4['epr']:.2f} |",
+        f"| layers per row neighbourhood (mean) | {c3['lpn']:.2f} | {c4['lpn']:.2f} |",
+        f"| rows whose neighbourhood holds 1 / 2 / ... / 8 / 9+ layers | {fr(c3['hist'])} | "
+        f"{fr(c4['hist'])} |",
+        f"| rows whose neighbourhood holds 9+ layers (stepped by k_wide) | {c3['hist'][-1]:,} | "
+        f"{c4['hist'][-1]:,} |",
+        f"| overflow rows (more than 3 entries) / rows reading one | {c3['ovf']:,} / "
+        f"{c3['reads_ovf']:,} | {c4['ovf']:,} / {c4['reads_ovf']:,} |",
+        f"| VALU instructions per wavefront | {c3['valu']:,.0f} | {c4['valu']:,.0f} |",
+        f"| SALU instructions per wavefront | {c3['salu']:,.0f} | {c4['salu']:,.0f} |",
+        f"| VALU issue (us; 4 cycles, 1,024 SIMDs, 2.4 GHz) | {c3['valu_us']:.1f} | {c4['valu_us']:.1f} |",
+        f"| HBM bytes per vertex | {c3['bytes_per_v']:.0f} | {c4['bytes_per_v']:.0f} |", "",
+        f"Per vertex the batched step costs {c4['us_per_mv'] / c3['us_per_mv']:.2f} times the C3 "
+        f"step.  Its wavefronts issue {c4['valu'] / c3['valu']:.2f} times the VALU instructions",
+        f"and move {c4['bytes_per_v'] / c3['bytes_per_v']:.2f} times the HBM bytes per vertex; VALU "
+        f"issue is {100 * c3['valu_us'] / c3['us']:.0f}% of the C3 step and "
+        f"{100 * c4['valu_us'] / c4['us']:.0f}% of the batched one.  The",
+        "rest of the batched step is latency: its small meshes with many seeds hold more overflow "
+        "rows (each",
+        "read by its neighbours in an extra dependent load round) and rows whose neighbourhood "
+        "holds many layers,",
+        "whose wavefronts run longest.", ""]
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines))
+    print(json.dumps(rows))
+
+
 def summarize_instructions(pmc_dir: str, out_path: str, last: int = 10):
     """Per-wavefront instruction counts of the step kernel over its last
     `last` dispatches, and the VALU issue time they imply."""
@@ -695,6 +879,12 @@ def main():
                          "profiles/k_step_c3_trace.md and profiles/post_c3_trace.md")
     ap.add_argument("--state-probe", type=int, default=0, metavar="STEPS",
                     help="only advance the C3 job 1,000 steps, then STEPS more (for counters)")
+    ap.add_argument("--batch-probe", type=int, default=0, metavar="STEPS",
+                    help="only step the C3 job to 1,000 and the C4 batch to 250 steps, STEPS more "
+                         "each (for counters), and print both states' row statistics")
+    ap.add_argument("--batch-summary", nargs=5,
+                    metavar=("PROBE_JSON", "PMC_DIR", "TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="only summarize the --batch-probe runs into profiles/k_step_c4_batch.md")
     ap.add_argument("--instr-summary", metavar="PMC_DIR",
                     help="only summarize a rocprofv3 SQ counter run of --state-probe into "
                          "profiles/k_step_c3_instructions.md")
@@ -708,6 +898,13 @@ def main():
         return
     if args.state_probe:
         state_probe(args.level, args.seeds, 1000, args.state_probe)
+        return
+    if args.batch_probe:
+        batch_probe(args.batch_meshes, args.batch_probe)
+        return
+    if args.batch_summary:
+        summarize_batch(*args.batch_summary,
+                        out_path=os.path.join(ROOT, "profiles", "k_step_c4_batch.md"))
         return
     if args.trace_summary:
         summarize_trace(*args.trace_summary, out_dir=os.path.join(ROOT, "profiles"))

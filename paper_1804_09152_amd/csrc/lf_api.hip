@@ -65,6 +65,7 @@ StepArgs step_args(lf_fields* f, int parity) {
   a.pad0_ = 0;
   a.ldiag = f->sldiag;
   a.slice_cls = f->slice_cls;
+  a.wide_rows = f->wide_rows;
   a.u_in = f->ell[parity];
   a.u_out = f->ell[1 - parity];
   a.ovf_in = f->ovf[parity];
@@ -426,6 +427,7 @@ lf_status lf_fields_destroy(lf_fields* f) try {
   (void)hipFree(f->owner);
   (void)hipFree(f->counters);
   (void)hipFree(f->wide);
+  (void)hipFree(f->wide_rows);
   (void)hipFree(f->parts);
   (void)hipFree(f->stats);
   (void)hipFree(f->flags);
@@ -644,7 +646,8 @@ int64_t mesh_bytes(const lf_mesh* m) {
 int64_t fields_bytes(const lf_fields* f) {
   const int64_t nv = f->mesh->n_v;
   return 2 * (int64_t)sizeof(EllRow) * nv + 2 * 8 * f->ovf_cap + 4 * nv + 4ll * f->n_s +
-         (int64_t)sizeof(WideRow) * f->wide_cap + 4 * (nv + 1) + 8 * f->csr_cap +
+         (int64_t)sizeof(WideRow) * f->wide_cap + (f->wide_rows ? 4 * nv : 0) +
+         4 * (nv + 1) + 8 * f->csr_cap +
          8 * scan_tmp_elems(nv) + (int64_t)sizeof(StepStats) * f->stats_cap * (1 + kParts) +
          4ll * (f->n_s + 1) * (f->n_types > 0) + 16ll * f->n_types * f->n_types +
          (f->own_order ? 2 * 4 * nv + 4 * (nv + 1) + 8 * f->mesh->nnz_off + 4 * nv +
@@ -713,6 +716,7 @@ static uint64_t graph_key(const lf_fields* f, int parity) {
   mix((uint64_t)f->ovf_cap);
   mix((uint64_t)(uintptr_t)f->wide);
   mix((uint64_t)f->wide_cap);
+  mix((uint64_t)(uintptr_t)f->wide_rows);
   mix((uint64_t)(uintptr_t)f->parts);
   mix((uint64_t)(uintptr_t)f->stats);
   mix((uint64_t)(uintptr_t)f->types);
@@ -823,6 +827,13 @@ lf_status step_book(lf_fields* f, int64_t n, int64_t* remaining) {
   const int64_t ok = fl.poisoned ? std::min<int64_t>(fl.fail_step, n) : n;
   book_steps(f, f->stats_pinned, ok);
   *remaining = n - ok;
+  if (fl.wide_seen && !f->wide_rows) {
+    // rows touching more than kRowRegs layers occur: from the next chunk on
+    // they are stepped after each step launch, one wavefront per row, so that
+    // no wavefront steps many of them in turn
+    LF_HIP(hipStreamSynchronize(f->mesh->ctx->stream));
+    LF_HIP(dalloc(&f->wide_rows, f->mesh->n_v));
+  }
   if (!fl.poisoned) return LF_OK;
   if (fl.poisoned & 2u) {
     clear_step_state(f);

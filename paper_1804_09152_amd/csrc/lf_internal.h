@@ -47,6 +47,8 @@ struct StepFlags {
                            // bit 3 wide-row workspace exhausted
   unsigned int fail_step;  // index (within the chunk) of the first failed step
   unsigned long long need; // overflow entries needed by a step that ran out
+  unsigned int wide_seen;  // a row touching more than kRowRegs layers was stepped inline
+  unsigned int pad_;
 };
 
 // Per-step counters: each step adds its partial sums into kParts slots
@@ -116,6 +118,10 @@ struct StepArgs {
   // slices check that it still holds and then skip the merge and update
   // (nullptr: no slice is tried)
   const uint8_t* slice_cls;
+  // rows touching more than kRowRegs layers: nullptr, each stepped by its
+  // own lane with a workspace slot; else (capacity n_v) their list, stepped
+  // after the launch by k_wide, one wavefront per row (wide_ctr counts it)
+  int32_t* wide_rows;
 };
 
 // error handling -----------------------------------------------------------
@@ -323,6 +329,10 @@ struct lf_fields {
   int32_t reorder_classes = 4;    // work classes the tiles are sorted into (2..4)
   int64_t next_reorder = 128;     // step count at which the next one happens
   int64_t reorders = 0;
+  // list of the rows touching more than kRowRegs layers in a step (n_v
+  // entries; allocated once a step has met one: from then on such rows are
+  // stepped by k_wide after each step launch)
+  int32_t* wide_rows = nullptr;
   int32_t* d_seeds;
   int32_t* owner;              // scratch n_v
   lf::EllRow* ell[2];          // fields, double-buffered

@@ -260,7 +260,8 @@ lf_status issue_tick(lf_server* s) {
       int32_t slices = 0;
       for (Job* j : js) {
         if (j->tick_steps <= k || (j->n_types > 0) != (typed == 1)) continue;
-        s->h_args[a++] = lf::chunk_step_args(j->f, k, j->tick_steps);
+        s->h_args[a] = lf::chunk_step_args(j->f, k, j->tick_steps);
+        s->h_args[a++].wide_rows = nullptr;  // a grouped launch steps wide rows in place
         s->h_first[fi++] = slices;
         slices += j->mesh->n_slices;
         ++g.n;

@@ -79,6 +79,51 @@ __device__ __forceinline__ float4 pair_coef(const StepConsts& c, int tj, int tl,
   return k;
 }
 
+// The update of one slot j of a row from the row totals (TYPED = false):
+//   Q_j = a/2 (T - lam_j) + w (P_C - phi_j)             (w term for cells only)
+//   G_j = e (R_C - sqrt phi_j) + e sqrt(phi_base)       (cell; base term if in S)
+//   G_b = -e R_C                                        (base)
+//   v_j = clamp(phi_j - dt (mu/n) (n Q_j - sum Q - sqrt(phi_j) G_j), 0, 1)
+// (base_mode 1: every layer a cell of the sums over all of S, no base term).
+struct RowTotals {
+  float ha, fn, sumQ, mun, gb, T, PC, RC, Pall, Rall;
+};
+__device__ __forceinline__ RowTotals row_totals(int n, int nC, bool hb, float sqb, float T,
+                                                float PC, float RC, float Pall, float Rall,
+                                                const StepConsts& c) {
+  RowTotals t;
+  t.ha = 0.5f * c.a;
+  t.fn = (float)n;
+  t.sumQ = (c.base_mode == 0) ? t.ha * (float)(n - 1) * T + c.w * (float)(nC - 1) * PC
+                              : t.ha * (float)(n - 1) * T + c.w * (float)(n - 1) * Pall;
+  t.mun = c.mu / t.fn;
+  t.gb = hb ? c.e * sqb : 0.f;
+  t.T = T;
+  t.PC = PC;
+  t.RC = RC;
+  t.Pall = Pall;
+  t.Rall = Rall;
+  return t;
+}
+__device__ __forceinline__ float slot_update(float ph, float la, int col, const RowTotals& t,
+                                             const StepConsts& c) {
+  const float sq = root(ph);
+  const bool base = col == c.n_s;
+  float Q, G;
+  if (c.base_mode == 0) {
+    Q = t.ha * (t.T - la) + (base ? 0.f : c.w * (t.PC - ph));
+    G = base ? -c.e * t.RC : c.e * (t.RC - sq) + t.gb;
+  } else {
+    Q = t.ha * (t.T - la) + c.w * (t.Pall - ph);
+    G = c.e * (t.Rall - sq);
+  }
+  const float d = -t.mun * (t.fn * Q - t.sumQ - sq * G);
+  float v = ph + c.dt * d;
+  if (v > 1.f) v = 1.f;
+  if (v <= 0.f) v = 0.f;
+  return v;
+}
+
 // Update of one row's active layers.  Slots s < cnt hold the row's union of
 // layers (col, phi = U(i,col), lam = field Laplacian); ub is the
 // wavefront's largest cnt in the register path (UNROLL), unused in the wide
@@ -148,30 +193,11 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
     }
     return;
   }
-  const float ha = 0.5f * c.a;
-  const float fn = (float)n;
-  const float sumQ = (c.base_mode == 0)
-                         ? ha * (float)(n - 1) * T + c.w * (float)(nC - 1) * PC
-                         : ha * (float)(n - 1) * T + c.w * (float)(n - 1) * Pall;
-  const float mun = c.mu / fn;
-  const float gb = hb ? c.e * sqb : 0.f;
+  const RowTotals t = row_totals(n, nC, hb, sqb, T, PC, RC, Pall, Rall, c);
+  const float fn = t.fn, mun = t.mun;
   float V = 0.f;
   auto upd = [&](int s) {
-    const float ph = r.phi[s], la = r.lam[s];
-    const float sq = root(ph);
-    const bool base = r.col[s] == c.n_s;
-    float Q, G;
-    if (c.base_mode == 0) {
-      Q = ha * (T - la) + (base ? 0.f : c.w * (PC - ph));
-      G = base ? -c.e * RC : c.e * (RC - sq) + gb;
-    } else {
-      Q = ha * (T - la) + c.w * (Pall - ph);
-      G = c.e * (Rall - sq);
-    }
-    const float d = -mun * (fn * Q - sumQ - sq * G);
-    float v = ph + c.dt * d;
-    if (v > 1.f) v = 1.f;
-    if (v <= 0.f) v = 0.f;
+    const float v = slot_update(r.phi[s], r.lam[s], r.col[s], t, c);
     out_of(r, s) = v;
     V += v;
   };
@@ -329,6 +355,7 @@ __device__ __forceinline__ int wave_slots(int cnt) {
 }
 
 constexpr int kXcds = 8;   // accelerator dies of the MI355X, each with its own L2
+constexpr int kWideBlocks = 2048;  // wavefronts of a k_wide launch (rows beyond: in turn)
 #ifndef LF_WIN
 #define LF_WIN 3
 #endif
@@ -684,6 +711,178 @@ __device__ __forceinline__ float wave_max(float x) {
   return x;
 }
 
+// ---- rows touching more than kRowRegs layers, one wavefront per row ----------
+
+// Lane masks (one bit per lane of the wavefront, in scalar registers) and
+// the value of a register on one lane.
+using Mask = unsigned long long;
+__device__ __forceinline__ Mask ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool lane_in(Mask m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+__device__ __forceinline__ int lane_i32(int x, int s) { return __builtin_amdgcn_readlane(x, s); }
+__device__ __forceinline__ float lane_f32(float x, int s) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), s));
+}
+
+struct WideResult {
+  int n_keep, n_skel, ev, changed;
+  float dmax;
+};
+
+// A row touching more than kRowRegs layers, stepped by the whole wavefront:
+// lane s holds the row's slot s (up to kRowWide = 64 slots, one per lane).
+// The neighbourhood is merged in a fixed order (own entries, then each
+// neighbour row in the operator's column order, each row in layer order; a
+// slot already holding the layer takes fma(L(i,u), U(u,l), lam), a new layer
+// opens the next slot); the row totals and the normalisation sum run over
+// the slots in slot order, as in the register path, and each slot's update
+// runs on its own lane.  i: the row (its operator entries are column
+// i / kSlice's operator slice).  Called with every lane active (all values
+// below that do not depend on the lane are uniform); writes the row, inline
+// or in the overflow area.
+template <bool TYPED>
+__device__ __forceinline__ WideResult wide_row_wave(const StepArgs& A, const int i) {
+  const int lane = threadIdx.x;
+  const Ent* ops = A.lell + (int64_t)(i / kSlice) * A.op_w * kSlice + i % kSlice;
+  WideResult res{0, 0, 0, 0, 0.f};
+  int col = -1;  // slot `lane`: layer, U_t value, field Laplacian
+  float phi = 0.f, lam = 0.f;
+  int cnt = 0;
+  bool full = false;  // more than kRowWide layers
+  const float dg = A.ldiag[i];
+  const RowView own = row_view(&A, i);
+  for (int p = 0; p < own.n; ++p) {  // own entries: distinct layers
+    if (cnt == kRowWide) {
+      full = true;
+      break;
+    }
+    const Ent e = own.p[p];
+    if (lane == cnt) {
+      col = e.col;
+      phi = e.val;
+      lam = dg * e.val;
+    }
+    ++cnt;
+  }
+  const int q0 = A.lptr[i], deg = A.lptr[i + 1] - q0;
+  for (int k = 0; k < deg && !full; ++k) {
+    const Ent le = k < A.op_w ? ops[k * kSlice] : A.lent[q0 + k];
+    if (le.col < 0) continue;
+    const RowView v = row_view(&A, le.col);
+    for (int p = 0; p < v.n; ++p) {
+      const Ent e = v.p[p];
+      const Mask m = ballot(col == e.col);
+      if (m != 0) {
+        if (lane_in(m)) lam = fmaf(le.val, e.val, lam);
+      } else {
+        if (cnt == kRowWide) {
+          full = true;
+          break;
+        }
+        if (lane == cnt) {
+          col = e.col;
+          phi = 0.f;
+          lam = le.val * e.val;
+        }
+        ++cnt;
+      }
+    }
+  }
+  Ent* row = A.u_out[i].e;
+  if (full) {  // the step fails; the row is written empty
+    if (lane == 0) step_failed(A, 2u);
+    if (lane < kEll) row[lane] = Ent{-1, 0.f};
+    return res;
+  }
+  // rows of interest and row totals, over the slots in slot order
+  const bool act = lane < cnt && (phi > 0.f || (phi == 0.f && lam > 0.f));
+  const float sq = root(phi);
+  const Mask am = ballot(act);
+  int n = 0, nC = 0;
+  bool hb = false;
+  float sqb = 0.f, T = 0.f, PC = 0.f, RC = 0.f, Pall = 0.f, Rall = 0.f;
+  for (int s = 0; s < cnt; ++s) {
+    if (!((am >> s) & 1)) continue;
+    const float ph_s = lane_f32(phi, s), sq_s = lane_f32(sq, s);
+    ++n;
+    T += lane_f32(lam, s);
+    Pall += ph_s;
+    Rall += sq_s;
+    if (lane_i32(col, s) == A.c.n_s) { hb = true; sqb = sq_s; }
+    else { ++nC; PC += ph_s; RC += sq_s; }
+  }
+  res.n_skel = n;
+  float out = -1.f;
+  if (n > 0) {
+    const RowTotals t = row_totals(n, nC, hb, sqb, T, PC, RC, Pall, Rall, A.c);
+    float v;
+    if constexpr (TYPED) {
+      const int ty = A.c.types[act ? col : 0];
+      const bool sb = col == A.c.n_s;
+      float Q = 0.f, G = 0.f;
+      for (int l = 0; l < cnt; ++l) {
+        if (!((am >> l) & 1)) continue;
+        const int col_l = lane_i32(col, l);
+        const float4 k = pair_coef(A.c, ty, A.c.types[col_l], sb, col_l == A.c.n_s);
+        if (lane != l) {
+          Q += 0.5f * k.x * lane_f32(lam, l) + k.y * lane_f32(phi, l);
+          G += k.z * lane_f32(sq, l);
+        }
+      }
+      const float q = t.fn * Q - sq * G;
+      float sQ = 0.f;
+      for (int s = 0; s < cnt; ++s)
+        if ((am >> s) & 1) sQ += lane_f32(Q, s);
+      v = phi + A.c.dt * (-t.mun * (q - sQ));
+      if (v > 1.f) v = 1.f;
+      if (v <= 0.f) v = 0.f;
+    } else {
+      v = slot_update(phi, lam, col, t, A.c);
+    }
+    float V = 0.f;
+    for (int s = 0; s < cnt; ++s)
+      if ((am >> s) & 1) V += lane_f32(v, s);
+    if (!(V > 0.f)) {
+      res.ev = 1;
+    } else {
+      // one division per row; a single active layer normalises to exactly 1
+      const float inv = 1.f / V;
+      const float o = n == 1 ? 1.f : v * inv;
+      out = act && o > 0.f && o >= A.c.theta ? o : -1.f;
+    }
+  }
+  if (A.measure) {
+    ChangeAcc a;
+    for (int s = 0; s < cnt; ++s) a.add(lane_i32(col, s), lane_f32(phi, s), lane_f32(out, s), A.c);
+    res.changed = a.changed();
+    res.dmax = a.dmax;
+  }
+  // kept entries in ascending layer order
+  const Mask km = ballot(out > 0.f);
+  const int n_keep = __builtin_popcountll(km);
+  res.n_keep = n_keep;
+  int rank = 0;
+  for (int s = 0; s < cnt; ++s)
+    if ((km >> s) & 1) rank += lane_i32(col, s) < col ? 1 : 0;
+  if (n_keep > kEll) {
+    unsigned o32 = 0;
+    if (lane == 0) o32 = atomicAdd(A.ovf_ctr, (unsigned)n_keep);
+    const long long o = (long long)(unsigned)__builtin_amdgcn_readfirstlane((int)o32);
+    const bool fits = o + n_keep <= A.ovf_cap;
+    if (lane == 0 && !fits) {
+      atomicMax(&A.flags->need, (unsigned long long)(o + n_keep));
+      step_failed(A, 1u);  // the step is replayed with a larger area
+    }
+    if (lane == 0) row[0] = Ent{kOvfMark, 0.f};
+    if (lane == 1) row[1] = Ent{fits ? (int32_t)o : 0, 0.f};
+    if (lane == 2) row[2] = Ent{fits ? n_keep : 0, 0.f};
+    if (fits && lane_in(km)) A.ovf_out[o + rank] = Ent{col, out};
+  } else {
+    if (lane_in(km)) row[rank] = Ent{col, out};
+    if (lane >= n_keep && lane < kEll) row[lane] = Ent{-1, 0.f};
+  }
+  return res;
+}
+
 // kept register-path entries in ascending layer order at dst[0..n_keep)
 // (ub: the wavefront's largest slot count)
 __device__ __forceinline__ void write_regs(const RowBuf<kRowRegs>& r, int ub, Ent* dst) {
@@ -818,6 +1017,7 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
   int cnt = 0, ub = 0, n_keep = 0, n_skel = 0, n_in = 0, ev = 0, rowovf = 0, changed = 0;
   float dmax = 0.f;
   int wide = -1;  // workspace slot of a wide row
+  bool deferred = false;  // a wide row left to k_wide
   // this row's operator entries: column-major in the wavefront's slice
   const Ent* ops = A.lell + (int64_t)sl * A.op_w * kSlice + lane;
   const bool in_regs = gather_regs(r, cnt, ub, n_in, i, i < A.n_v, ops, A) == kGatherOk;
@@ -834,7 +1034,12 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
     if (in_regs) {
       row_update<kRowRegs, true, TYPED>(r, cnt, ub, A.c, n_keep, n_skel, ev);
       if (A.measure) row_change(r, ub, A.c, changed, dmax);
+    } else if (A.wide_rows) {
+      // stepped after this launch by k_wide, one wavefront per row
+      A.wide_rows[atomicAdd(A.wide_ctr, 1u)] = i;
+      deferred = true;
     } else {
+      atomicOr(&A.flags->wide_seen, 1u);
       const unsigned slot = atomicAdd(A.wide_ctr, 1u);
       if (slot < (unsigned)A.wide_cap) {
         wide = (int)slot;
@@ -852,7 +1057,9 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
     // the row: inline, or in the overflow area of U_{t+1}
     Ent* row = A.u_out[i].e;
     Ent* dst = row;
-    if (n_keep > kEll) {
+    if (deferred) {
+      dst = nullptr;
+    } else if (n_keep > kEll) {
       const long long o = (long long)atomicAdd(A.ovf_ctr, (unsigned)n_keep);
       const bool fits = o + n_keep <= A.ovf_cap;
       if (!fits) {
@@ -931,12 +1138,33 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   step_slice<TYPED>(G[lo], g - first[lo]);
 }
 
+// The rows a k_step launch left to it (wide_rows[0 .. *wide_ctr)), each
+// stepped by one wavefront; their counters join the step's partial slots.
+// Nothing is done when an earlier step of the chunk failed.
+template <bool TYPED>
+__global__ __launch_bounds__(kSlice) void k_wide(StepArgs A) {
+  if (*(const __attribute__((address_space(4))) unsigned int*)&A.flags->poisoned) return;
+  const unsigned n = *A.wide_ctr;
+  for (unsigned q = blockIdx.x; q < n; q += gridDim.x) {
+    const WideResult o = wide_row_wave<TYPED>(A, A.wide_rows[q]);
+    if (threadIdx.x == 0) {
+      StepStats* P = A.parts + (q & (kParts - 1));
+      atomicAdd(&P->skel, (unsigned long long)o.n_skel);
+      atomicAdd(&P->out, (unsigned long long)o.n_keep);
+      if (o.ev) atomicAdd(&P->events, (unsigned long long)o.ev);
+      if (o.changed) atomicAdd(&P->changed, (unsigned long long)o.changed);
+      if (o.dmax > 0.f) atomicMax(&P->dmax, (unsigned long long)__float_as_uint(o.dmax));
+    }
+  }
+}
+
 __global__ void k_reset_flags(StepFlags* f, StepStats* parts, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0) {
     f->poisoned = 0;
     f->fail_step = 0xffffffffu;
     f->need = 0;
+    f->wide_seen = 0;
   }
   if (parts && k < n) parts[k] = StepStats{0, 0, 0, 0, 0, 0};
 }
@@ -974,6 +1202,18 @@ __global__ __launch_bounds__(kParts) void k_reduce_parts(const StepStats* parts,
 
 hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   const dim3 grid((unsigned)(kXcds * ((a.n_slices + kXcds - 1) / kXcds)));
+  if (a.wide_rows) {  // the step kernel, then its wide rows (timed together)
+    hipError_t e = (t0 && t1) ? hipEventRecord(t0, s) : hipSuccess;
+    if (e != hipSuccess) return e;
+    if (a.c.n_types > 0) hipLaunchKernelGGL(k_step<true>, grid, dim3(kSlice), 0, s, a);
+    else hipLaunchKernelGGL(k_step<false>, grid, dim3(kSlice), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const dim3 wgrid((unsigned)(a.n_v < kWideBlocks ? a.n_v : kWideBlocks));
+    if (a.c.n_types > 0) hipLaunchKernelGGL(k_wide<true>, wgrid, dim3(kSlice), 0, s, a);
+    else hipLaunchKernelGGL(k_wide<false>, wgrid, dim3(kSlice), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return (t0 && t1) ? hipEventRecord(t1, s) : hipSuccess;
+  }
   if (t0 && t1) {
     if (a.c.n_types > 0) hipExtLaunchKernelGGL(k_step<true>, grid, dim3(kSlice), 0, s, t0, t1, 0, a);
     else hipExtLaunchKernelGGL(k_step<false>, grid, dim3(kSlice), 0, s, t0, t1, 0, a);

@@ -24,21 +24,26 @@ def _write(path, header, rows):
         w.writerows(rows)
 
 
-def _counters(d, counter, per_kernel):
+def _counters(d, counter, per_kernel, grid=None):
+    """per_kernel: name -> values, or name -> [(grid size, value), ...]."""
     rows = []
     for name, values in per_kernel.items():
-        rows += [[name, counter, v] for v in values]
+        for v in values:
+            g, v = v if isinstance(v, tuple) else (grid or bench._c3_step_grid(), v)
+            rows.append([name, g, counter, v])
     _write(os.path.join(d, "run_counter_collection.csv"),
-           ["Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+           ["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"], rows)
 
 
 def test_counter_summary_scales_by_the_copy_probe(tmp_path):
     """FETCH_SIZE and WRITE_SIZE of the scalar step kernel only (not the
-    typed instance), each scaled so that the copy probe reads its known
-    size."""
+    typed instance, and only its launches over the C3 mesh), each scaled so
+    that the copy probe reads its known size."""
     kib = 1024
-    _counters(tmp_path / "f", "FETCH_SIZE", {STEP: [100.0, 300.0], TYPED: [9e9]})
-    _counters(tmp_path / "w", "WRITE_SIZE", {STEP: [50.0, 50.0]})
+    other = bench._c3_step_grid(7)  # launches on another mesh do not count
+    _counters(tmp_path / "f", "FETCH_SIZE",
+              {STEP: [100.0, 300.0, (other, 7e9)], TYPED: [9e9]})
+    _counters(tmp_path / "w", "WRITE_SIZE", {STEP: [50.0, 50.0, (other, 7e9)]})
     probe_mib = 1
     _counters(tmp_path / "cf", "FETCH_SIZE", {COPY: [512.0]})  # half of 1 MiB: scale 2
     _counters(tmp_path / "cw", "WRITE_SIZE", {COPY: [1024.0]})  # scale 1
@@ -110,7 +115,9 @@ def test_instruction_summary(tmp_path):
     for waves in [10.0, 40968.0, 40968.0]:  # the first is not among the last 2
         for name, v in [("SQ_WAVES", waves), ("SQ_INSTS_VALU", 1000.0 * waves),
                         ("SQ_INSTS_SALU", 500.0 * waves), ("SQ_INSTS_BRANCH", 300.0 * waves),
-                        ("SQ_THREAD_CYCLES_VALU", 0.5 * 64 * 1000.0 * waves)]:
+                        ("SQ_THREAD_CYCLES_VALU", 0.5 * 64 * 1000.0 * waves),
+                        ("SQ_ACTIVE_INST_VALU", 1010.0 * waves), ("SQ_WAVE_CYCLES", 6000.0 * waves),
+                        ("SQ_WAIT_INST_ANY", 1400.0 * waves)]:
             rows.append([STEP, name, v])
             rows.append([TYPED, name, 7 * v])
     _write(str(d / "run_counter_collection.csv"), ["Kernel_Name", "Counter_Name", "Counter_Value"],
@@ -120,6 +127,7 @@ def test_instruction_summary(tmp_path):
     text = out.read_text()
     assert "| VALU instructions | 1,000 |" in text and "| SALU instructions | 500 |" in text
     assert "| active lanes per VALU instruction | 50.0% |" in text
+    assert "| wavefront lifetime (SQ_WAVE_CYCLES, 4-cycle units) | 6,000 |" in text
     issue = 1000 * 40968 * 4 / 1024 / 2400
     assert f"= {issue:.1f} us per launch" in text
 
