@@ -144,3 +144,41 @@ def test_cpu_baseline_legs():
     assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
     b = out["batch_one_mesh_per_thread"]
     assert b["value"] > 0 and b["cores"] == out["cores"]
+
+
+def test_batch_summary(tmp_path):
+    """Per-vertex comparison of the batched and the single-mesh step: each
+    mesh's launches picked by grid size, the wide-row kernel right after a
+    step launch added to it, counters per wavefront, bytes scaled as the
+    committed copy-probe factors."""
+    WIDE = "void lf::(anonymous namespace)::k_wide<false>(lf::StepArgs)"
+    g3, g4 = bench._grid_of(1000), bench._grid_of(4000)
+    stats = {"entries_per_row": 1.4, "layers_per_neighbourhood": 2.0, "overflow_rows": 10,
+             "rows_reading_overflow": 70, "neighbourhood_hist_1_to_8_9plus": [5, 4, 1, 0, 0, 0, 0, 0, 0]}
+    probe = {"c3": {"grid": g3, "n_v": 1000, "cells": 10, **stats},
+             "c4": {"grid": g4, "n_v": 4000, "cells": 50, **dict(stats, overflow_rows=80)}}
+    (tmp_path / "probe.json").write_text("log line\n" + json.dumps(probe) + "\n")
+    # trace: C3 launches of 10 us; C4 launches of 30 us, each followed by a 5 us k_wide
+    rows, t = [], 0
+    for name, grid, dur in [(STEP, g3, 10), (STEP, g3, 10), (STEP, g4, 30), (WIDE, 64 * 2048, 5),
+                            (STEP, g4, 30), (WIDE, 64 * 2048, 5)]:
+        rows.append([name, grid, t, t + dur * 1000])
+        t += 100000
+    _write(str(tmp_path / "t" / "run_kernel_trace.csv"),
+           ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp"], rows)
+    for d, counters in (("s", {"SQ_WAVES": 2.0, "SQ_INSTS_VALU": 2000.0, "SQ_INSTS_SALU": 1000.0}),
+                        ("f", {"FETCH_SIZE": 100.0}), ("w", {"WRITE_SIZE": 50.0})):
+        _write(str(tmp_path / d / "run_counter_collection.csv"),
+               ["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"],
+               [[STEP, g, k, v * (1 if g == g3 else 4)] for g in (g3, g4) for k, v in counters.items()])
+    out = tmp_path / "b.md"
+    bench.summarize_batch(str(tmp_path / "probe.json"), str(tmp_path / "s"), str(tmp_path / "t"),
+                          str(tmp_path / "f"), str(tmp_path / "w"), str(out))
+    text = out.read_text()
+    assert "| step (us; of which k_wide, the rows touching more than 8 layers) | 10.0 (0.0) | 35.0 (5.0) |" in text
+    assert "| us per million vertices | 10000.0 | 8750.0 |" in text
+    assert "| VALU instructions per wavefront | 1,000 | 1,000 |" in text
+    cal = json.load(open(os.path.join(bench.ROOT, "profiles", "k_step_c3_counters.json")))
+    b3 = (100 * 1024 * cal["fetch_scale"] + 50 * 1024 * cal["write_scale"]) / 1000
+    assert f"| HBM bytes per vertex | {b3:.0f} | {b3:.0f} |" in text
+    assert "hold 2.0 times more overflow rows per vertex" in text

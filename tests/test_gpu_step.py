@@ -492,6 +492,49 @@ def test_wide_workspace_growth(lf, orc):
     check_step(as_oracle(f.export()), O, info, 1e-3, max_skel_guarded_frac=0.05, what="wide growth")
 
 
+def test_wide_rows_after_the_step_launch(lf, orc):
+    """Once a step has met rows touching more than 8 layers, later steps hand
+    them to a kernel of their own (one wavefront per row) after the step
+    launch: the same rows and counters, bit for bit, as stepping them in the
+    step kernel, also with per-pair coefficients, and against the oracle."""
+    lfb, ctx = lf
+    mesh = I.torus_grid(64, 64)
+    n_s = 40
+    U = f32(_three_layer_state(mesh, n_s, 5))
+    L = orc.operator(mesh.V, mesh.F, 0)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    seeds = I.seeds_uniform(mesh.n_v, n_s, np.random.default_rng(5))
+    rng = np.random.default_rng(8)
+    types = rng.integers(0, 3, n_s + 1).astype(np.int32)
+    tab = rng.uniform(0.5, 1.5, (3, 3, 3)) * np.array([0.04, 0.2, 1.0])
+    for typed in (False, True):
+        say("wide rows after the launch", typed)
+        a = lfb.Fields(m, seeds)  # first chunk: wide rows in the step kernel
+        b = lfb.Fields(m, seeds)
+        if typed:
+            a.set_coefficients(types, tab)
+            b.set_coefficients(types, tab)
+        gpu_load(b, U)
+        b.step(1)  # meets wide rows: later chunks hand them on
+        for f in (a, b):
+            gpu_load(f, U)
+            f.step(1)
+        for x, y in zip(a.export(), b.export()):
+            assert np.array_equal(x, y)
+        assert a.last_change() == b.last_change()
+        gpu_load(b, U)
+        b.step(3)  # three steps, each handing its wide rows on, against the oracle
+        P = orc.default_params(types=types, table=tab) if typed else orc.default_params()
+        O = U
+        for _ in range(2):
+            O = orc.step(L, O, n_s, P)
+        O, info = orc.step(L, O, n_s, P, want_info=True)
+        check_step(as_oracle(b.export()), O, info, 1e-3, max_skel_guarded_frac=0.05,
+                   what=f"wide after launch typed={typed}")
+        a.close()
+        b.close()
+
+
 def test_determinism(lf):
     lfb, ctx = lf
     mesh, seeds = I.config_c2(level=5, n_seeds=64, seed=2)
