@@ -763,27 +763,48 @@ __device__ __forceinline__ WideResult wide_row_wave(const StepArgs& A, const int
     }
     ++cnt;
   }
+  // adds x scaled by wgt into layer c (a new slot when no lane holds it)
+  auto add = [&](int c, float wgt, float x) {
+    const Mask m = ballot(col == c);
+    if (m != 0) {
+      if (lane_in(m)) lam = fmaf(wgt, x, lam);
+    } else if (cnt == kRowWide) {
+      full = true;
+    } else {
+      if (lane == cnt) {
+        col = c;
+        phi = 0.f;
+        lam = wgt * x;
+      }
+      ++cnt;
+    }
+  };
+  // the neighbours' operator entries and inline rows are loaded one
+  // neighbour per lane, together, and then merged in column order
   const int q0 = A.lptr[i], deg = A.lptr[i + 1] - q0;
-  for (int k = 0; k < deg && !full; ++k) {
-    const Ent le = k < A.op_w ? ops[k * kSlice] : A.lent[q0 + k];
-    if (le.col < 0) continue;
-    const RowView v = row_view(&A, le.col);
-    for (int p = 0; p < v.n; ++p) {
-      const Ent e = v.p[p];
-      const Mask m = ballot(col == e.col);
-      if (m != 0) {
-        if (lane_in(m)) lam = fmaf(le.val, e.val, lam);
-      } else {
-        if (cnt == kRowWide) {
-          full = true;
-          break;
-        }
-        if (lane == cnt) {
-          col = e.col;
-          phi = 0.f;
-          lam = le.val * e.val;
-        }
-        ++cnt;
+  for (int k0 = 0; k0 < deg && !full; k0 += kSlice) {
+    const int k = k0 + lane;
+    Ent le{-1, 0.f};
+    if (k < deg) le = k < A.op_w ? ops[k * kSlice] : A.lent[q0 + k];
+    EllRow u;
+#pragma unroll
+    for (int j = 0; j < kEll; ++j) u.e[j] = Ent{-1, 0.f};
+    if (le.col >= 0) u = row_at(A.u_in, le.col);
+    const int kn = deg - k0 < kSlice ? deg - k0 : kSlice;
+    for (int q = 0; q < kn && !full; ++q) {
+      const int nb = lane_i32(le.col, q);
+      if (nb < 0) continue;
+      const float wgt = lane_f32(le.val, q);
+      if (lane_i32(u.e[0].col, q) == kOvfMark) {
+        const RowView v = row_view(&A, nb);
+        for (int p = 0; p < v.n && !full; ++p) add(v.p[p].col, wgt, v.p[p].val);
+        continue;
+      }
+#pragma unroll
+      for (int j = 0; j < kEll; ++j) {
+        const int c = lane_i32(u.e[j].col, q);
+        if (c < 0 || full) break;
+        add(c, wgt, lane_f32(u.e[j].val, q));
       }
     }
   }
