@@ -1140,6 +1140,13 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
   step_slice<TYPED>(A, sl);
 }
 
+// p as a pointer into the global address space (from its integer value, so
+// that the compiler does not fold the conversion away)
+template <class T>
+__device__ __forceinline__ T* to_global(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
 // One step of several independent field objects in one launch: their slices
 // follow one another (job j owns slices [first[j], first[j+1]) of the
 // launch, first[n_jobs] = total), each with its own arguments G[j]; the XCD
@@ -1156,7 +1163,30 @@ __global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (first[mid] <= g) lo = mid;
     else hi = mid - 1;
   }
-  step_slice<TYPED>(G[lo], g - first[lo]);
+  // the job's arguments, every pointer rebuilt in the global address space
+  // (pointers read from memory are generic to the compiler, which would then
+  // use flat accesses, and a flat access also waits on the LDS counter)
+  StepArgs a = G[lo];
+  a.lell = to_global(a.lell);
+  a.lptr = to_global(a.lptr);
+  a.lent = to_global(a.lent);
+  a.ldiag = to_global(a.ldiag);
+  a.u_in = to_global(a.u_in);
+  a.u_out = to_global(a.u_out);
+  a.ovf_in = to_global(a.ovf_in);
+  a.ovf_out = to_global(a.ovf_out);
+  a.ovf_ctr = to_global(a.ovf_ctr);
+  a.ovf_ctr_next = to_global(a.ovf_ctr_next);
+  a.c.types = to_global(a.c.types);
+  a.c.tab = to_global(a.c.tab);
+  a.wide = to_global(a.wide);
+  a.wide_ctr = to_global(a.wide_ctr);
+  a.wide_ctr_next = to_global(a.wide_ctr_next);
+  a.flags = to_global(a.flags);
+  a.parts = to_global(a.parts);
+  a.slice_cls = to_global(a.slice_cls);
+  a.wide_rows = to_global(a.wide_rows);
+  step_slice<TYPED>(a, g - first[lo]);
 }
 
 // The rows a k_step launch left to it (wide_rows[0 .. *wide_ctr)), each
