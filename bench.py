@@ -746,7 +746,7 @@ def _mono_ms() -> float:
 
 
 def run_serving(lfb, I, n_jobs: int, rates, steps: int, rounds: int, max_active: int,
-                budget_gib: float):
+                budget_gib: float, chunk: int = 64):
     """The serving stream at each offered rate, then the same jobs one at a
     time with the plain calls.  Latency runs from a job's Poisson arrival to
     its completion (the library's monotonic timestamps), so time the loop
@@ -763,7 +763,7 @@ def run_serving(lfb, I, n_jobs: int, rates, steps: int, rounds: int, max_active:
         inputs.append((m, I.seeds_uniform(m.n_v, j["n_seeds"], rng)))
     budget = int(budget_gib * (1 << 30))
     log(f"serving: {n_jobs} jobs, levels {np.bincount([j['level'] for j in jobs], minlength=10)[5:]}")
-    S = lfb.Server(0, budget, max_active, 64)
+    S = lfb.Server(0, budget, max_active, chunk)
     wm, ws = inputs[0]  # one small job first: loads the kernels, warms the allocator
     w = S.submit(wm.V, wm.F, ws, 50, 1, True, lfb.LF_OP_COTAN)
     S.run()
@@ -772,10 +772,11 @@ def run_serving(lfb, I, n_jobs: int, rates, steps: int, rounds: int, max_active:
     out = {"workload": (f"Poisson arrivals of {n_jobs} jobs, jittered icospheres levels 5-9, "
                         f"64*4^(level-5) seeds, cotangent operator, {steps} steps + {rounds} "
                         f"Lloyd rounds + labels + dual mesh each"),
-           "max_active": max_active, "hbm_budget_gib": budget_gib, "rates": []}
+           "max_active": max_active, "hbm_budget_gib": budget_gib, "steps_per_tick": chunk,
+           "rates": []}
     for qps in rates:
         arrivals = np.cumsum(np.random.default_rng(1).exponential(1.0 / qps, n_jobs)) * 1e3
-        S = lfb.Server(0, budget, max_active, 64)
+        S = lfb.Server(0, budget, max_active, chunk)
         ids = [None] * n_jobs
         t0 = _mono_ms()
         nxt, done = 0, 0
@@ -865,6 +866,7 @@ def main():
     ap.add_argument("--serve-qps", type=float, nargs="+", default=[4.0, 8.0])
     ap.add_argument("--serve-steps", type=int, default=1000)
     ap.add_argument("--serve-rounds", type=int, default=3)
+    ap.add_argument("--serve-chunk", type=int, default=64, help="steps per job per server tick")
     ap.add_argument("--serve-active", type=int, default=16)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--no-c2", action="store_true")
@@ -1046,7 +1048,8 @@ def main():
         out["graphs"] = run_graphs(lfb, I)
     if not args.no_serve:
         out["serving"] = run_serving(lfb, I, args.serve_jobs, args.serve_qps, args.serve_steps,
-                                     args.serve_rounds, args.serve_active, args.serve_budget_gib)
+                                     args.serve_rounds, args.serve_active, args.serve_budget_gib,
+                                     args.serve_chunk)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, seeds, args.cpu_seconds,
                                            I.batch_tori(args.batch_meshes))

@@ -535,6 +535,38 @@ def test_wide_rows_after_the_step_launch(lf, orc):
         b.close()
 
 
+def test_dense_seeds_theta_zero(lf, orc):
+    """Dense seeds (about three vertices per cell) with theta = 0: rows of
+    up to ten entries (overflow area) and neighbourhoods of up to twelve
+    layers (rows stepped by k_wide once the first step has met them),
+    teacher-forced at points of a 100-step oracle trajectory."""
+    lfb, ctx = lf
+    mesh = I.torus_grid(24, 24)
+    n_s = 200
+    seeds = I.seeds_uniform(mesh.n_v, n_s, np.random.default_rng(3))
+    L = orc.operator(mesh.V, mesh.F, 0)
+    P = orc.default_params(theta=0.0)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, seeds, lfb.default_params(theta=0.0))
+    U = orc.init(mesh.n_v, seeds)
+    wide_seen = 0
+    for t in range(101):
+        if t in (0, 1, 2, 5, 20, 100):
+            rp, c = U[0], U[1]
+            wide = sum(len(set(c[rp[v]:rp[v + 1]]).union(
+                *[set(c[rp[u]:rp[u + 1]]) for u in L[1][L[0][v]:L[0][v + 1]]])) > 8
+                for v in range(mesh.n_v))
+            wide_seen += wide
+            say("dense theta 0", t, wide)
+            gpu_load(f, f32(U))
+            f.step(1)
+            O, info = orc.step(L, f32(U), n_s, P, want_info=True)
+            check_step(as_oracle(f.export()), O, info, 0.0, what=f"dense theta0 t={t}",
+                       max_skel_guarded_frac=0.05)
+        U = orc.step(L, U, n_s, P)
+    assert wide_seen > 0
+
+
 def test_determinism(lf):
     lfb, ctx = lf
     mesh, seeds = I.config_c2(level=5, n_seeds=64, seed=2)
