@@ -156,6 +156,14 @@ lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_
  * vertex touches more layers than the row limit (64) or storage cannot
  * grow. */
 lf_status lf_step(lf_fields* f, int32_t n_steps);
+/* lf_step without waiting: enqueues the first min(n_steps, 256) steps on
+ * the context stream and returns at once (the GPU works while the caller
+ * does).  The next call on these fields -- lf_sync, an export, labels, a
+ * step, any other lf_fields / lf_lloyd / lf_dual / lf_batch call on them --
+ * first waits for those steps, books them (growing storage and stepping
+ * again what an overflow stopped) and runs the remaining steps; it returns
+ * their errors.  lf_fields_destroy waits only for the enqueued steps. */
+lf_status lf_step_async(lf_fields* f, int32_t n_steps);
 /* Convergence (the paper's fields "until converged", Sections 4 and 7,
  * made concrete).  A step changes a row when the row's label (argmax over
  * the cells) or its set of layers at or above params.tau changes.  The
@@ -175,6 +183,8 @@ lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t che
  * lf_step_until and on the last step of every chunk of lf_step (at most 256
  * steps; so always for the last step of a call). */
 lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta);
+/* Completes what lf_step_async left (see there), then waits for the
+ * context stream. */
 lf_status lf_sync(lf_fields* f);
 /* Work-class ordering of the step's rows: every `every` steps (first 128
  * steps after an initialisation), lf_step re-orders the rows within tiles of

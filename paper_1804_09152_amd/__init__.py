@@ -54,7 +54,7 @@ EXPORTS = [
     "lf_mesh_destroy", "lf_mesh_operator", "lf_fields_create", "lf_fields_destroy",
     "lf_fields_reset", "lf_fields_create_rings", "lf_fields_create_regions", "lf_fields_reset_regions", "lf_fields_seeds", "lf_fields_set_coefficients", "lf_step", "lf_sync", "lf_fields_use_graphs", "lf_fields_set_reorder", "lf_fields_reorders", "lf_fields_export",
     "lf_fields_import", "lf_labels", "lf_step_until", "lf_last_change", "lf_lloyd_reseed", "lf_lloyd", "lf_dual_mesh", "lf_dual_matrix",
-    "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing",
+    "lf_dual_candidates", "lf_stats", "lf_traffic", "lf_step_timing", "lf_step_async",
     "lf_batch_create", "lf_batch_destroy", "lf_batch_fields", "lf_batch_export", "lf_batch_labels",
     "lf_server_create", "lf_server_destroy", "lf_server_submit", "lf_server_poll", "lf_server_cancel",
     "lf_server_result", "lf_server_release", "lf_server_memory", "lf_server_times",
@@ -123,6 +123,7 @@ def load(path: str | None = None):
         "lf_stats": (C.c_int, [V, V, V, V, V, V]),
         "lf_traffic": (C.c_int, [V, V, V]),
         "lf_step_timing": (C.c_int, [V, I32, V, V]),
+        "lf_step_async": (C.c_int, [V, I32]),
         "lf_batch_create": (C.c_int, [V, I32, V, V, V, V, I32, V, V, C.POINTER(lf_params), PV]),
         "lf_batch_destroy": (C.c_int, [V]),
         "lf_batch_fields": (C.c_int, [V, PV]),
@@ -674,6 +675,14 @@ class Fields:
 
     def step(self, n: int = 1):
         lf_step(self.h, n)
+
+    def step_async(self, n: int = 1):
+        """Enqueue the first min(n, 256) steps and return; the next call on
+        these fields (sync, export, ...) completes all n."""
+        _check(load().lf_step_async(self.h, int(n)))
+
+    def sync(self):
+        _check(load().lf_sync(self.h))
 
     def use_graphs(self, on: bool = True):
         _check(load().lf_fields_use_graphs(self.h, int(bool(on))))

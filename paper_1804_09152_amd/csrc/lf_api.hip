@@ -417,6 +417,9 @@ static lf_status init_fields(lf_fields* f) {
 lf_status lf_fields_destroy(lf_fields* f) try {
   if (!f) return LF_OK;
   (void)hipSetDevice(f->mesh->ctx->device);
+  // steps still in flight (lf_step_async) finish before their buffers go;
+  // those not issued yet are dropped
+  if (f->pending) (void)hipStreamSynchronize(f->mesh->ctx->stream);
   drop_graphs(f);
   fields_order_reset(f);
   for (int k = 0; k < 2; ++k) {
@@ -515,6 +518,7 @@ lf_status lf_fields_create_regions(lf_mesh* m, const int32_t* region_ptr,
 lf_status lf_fields_reset_regions(lf_fields* f, const int32_t* region_ptr,
                                   const int32_t* region_vertices) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   std::vector<int32_t> owner, first;
   lf_status st = check_regions(region_ptr, region_vertices, f->n_s, f->mesh->n_v, owner, first);
   if (st) return st;
@@ -589,6 +593,7 @@ extern "C" {
 
 lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   lf_status st = check_seeds(seeds, f->n_s, f->mesh->n_v);
   if (st) return st;
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
@@ -601,6 +606,7 @@ lf_status lf_fields_reset(lf_fields* f, const int32_t* seeds) try {
 
 lf_status lf_fields_seeds(lf_fields* f, int32_t* seeds) try {
   if (!f || !seeds) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   memcpy(seeds, f->seeds.data(), sizeof(int32_t) * f->n_s);
   return LF_OK;
 } catch (const std::bad_alloc&) {
@@ -885,6 +891,7 @@ extern "C" {
 lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_t* layer_types,
                                      const double* table) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   if (n_types < 0 || n_types > 65536) return fail(LF_EINVAL, "n_types out of range");
   if (n_types > 0 && (!layer_types || !table)) return fail(LF_EINVAL, "NULL argument");
   const int64_t n_r = (int64_t)f->n_s + 1, n_pairs = (int64_t)n_types * n_types;
@@ -936,6 +943,7 @@ lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_
 
 lf_status lf_last_change(lf_fields* f, int64_t* changed_rows, double* max_delta) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   if (changed_rows) *changed_rows = (int64_t)f->last_changed;
   if (max_delta) *max_delta = (double)f->last_dmax;
   return LF_OK;
@@ -947,6 +955,7 @@ lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t che
                         int64_t* steps_done, int64_t* converged_at) try {
   if (!f || max_steps < 0 || check_every < 1 || check_every > kMaxChunk || !(eps >= 0))
     return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
   int64_t done = 0, conv = 0;
   int grows = 0;
   f->measure_all = true;
@@ -979,8 +988,12 @@ lf_status lf_step_until(lf_fields* f, int32_t max_steps, double eps, int32_t che
   return lf::host_oom();
 }
 
-lf_status lf_step(lf_fields* f, int32_t n) try {
-  if (!f || n < 0) return fail(LF_EINVAL, "invalid argument");
+}  // extern "C"
+
+namespace lf {
+
+// steps n steps in chunks, each waited for and booked
+static lf_status step_blocking(lf_fields* f, int64_t n) {
   int64_t left = n;
   int grows = 0;
   while (left > 0) {
@@ -996,6 +1009,39 @@ lf_status lf_step(lf_fields* f, int32_t n) try {
     if (rem > 0 && ++grows > 32) return fail(LF_ECAPACITY, "field storage keeps overflowing");
   }
   return LF_OK;
+}
+
+lf_status fields_settle(lf_fields* f) {
+  if (f->pending == 0 && f->async_left == 0) return LF_OK;
+  int64_t rem = 0;
+  lf_status st = step_complete(f, &rem);
+  const int64_t left = rem + f->async_left;
+  f->async_left = 0;
+  if (st) return st;
+  return step_blocking(f, left);
+}
+
+}  // namespace lf
+
+extern "C" {
+
+lf_status lf_step_async(lf_fields* f, int32_t n) try {
+  if (!f || n < 0) return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
+  if (n == 0) return LF_OK;
+  const int64_t m = std::min<int64_t>(n, kMaxChunk);
+  lf_status st = step_issue(f, m);
+  if (st) return st;
+  f->async_left = n - m;
+  return LF_OK;
+} catch (const std::bad_alloc&) {
+  return lf::host_oom();
+}
+
+lf_status lf_step(lf_fields* f, int32_t n) try {
+  if (!f || n < 0) return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
+  return step_blocking(f, n);
 } catch (const std::bad_alloc&) {
   return lf::host_oom();
 }
@@ -1005,6 +1051,7 @@ lf_status lf_fields_set_reorder(lf_fields* f, int32_t every, int32_t tile_rows,
   if (!f || every < 0 || tile_rows < 256 || tile_rows > kTileRows || tile_rows % 256 ||
       classes < 2 || classes > 4)
     return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
   f->reorder_every = every;
   f->reorder_tile = tile_rows;
   f->reorder_classes = classes;
@@ -1016,6 +1063,7 @@ lf_status lf_fields_set_reorder(lf_fields* f, int32_t every, int32_t tile_rows,
 
 lf_status lf_fields_reorders(lf_fields* f, int64_t* n) try {
   if (!f || !n) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   *n = f->reorders;
   return LF_OK;
 } catch (const std::bad_alloc&) {
@@ -1024,6 +1072,7 @@ lf_status lf_fields_reorders(lf_fields* f, int64_t* n) try {
 
 lf_status lf_fields_use_graphs(lf_fields* f, int32_t on) try {
   if (!f || (on != 0 && on != 1)) return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   if (!on) drop_graphs(f);
   f->use_graphs = on == 1;
@@ -1034,6 +1083,7 @@ lf_status lf_fields_use_graphs(lf_fields* f, int32_t on) try {
 
 lf_status lf_sync(lf_fields* f) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   LF_HIP(hipStreamSynchronize(f->mesh->ctx->stream));
   return LF_OK;
 } catch (const std::bad_alloc&) {
@@ -1043,6 +1093,7 @@ lf_status lf_sync(lf_fields* f) try {
 lf_status lf_fields_export(lf_fields* f, int64_t* nnz, int32_t* rowptr, int32_t* col, float* val,
                            int32_t is_dev) try {
   if (!f || !nnz) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   *nnz = f->nnz;
   if (!rowptr && !col && !val) return LF_OK;
   if (!rowptr || !col || !val) return fail(LF_EINVAL, "rowptr, col and val must all be given");
@@ -1078,6 +1129,7 @@ lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, con
                            const float* val, int32_t is_dev) try {
   if (!f || !rowptr || (nnz > 0 && (!col || !val)) || nnz < 0)
     return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
   if (nnz > (1ll << 31) - 1) return fail(LF_EINVAL, "more than 2^31 entries");
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   hipStream_t s = f->mesh->ctx->stream;
@@ -1140,6 +1192,7 @@ lf_status lf_fields_import(lf_fields* f, int64_t nnz, const int32_t* rowptr, con
 
 lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_dev) try {
   if (!f || !labels) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   hipStream_t s = f->mesh->ctx->stream;
   const int32_t n_v = f->mesh->n_v;
@@ -1166,6 +1219,7 @@ lf_status lf_labels(lf_fields* f, int32_t* labels, int32_t is_dev) try {
 lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skel, int64_t* steps, int64_t* empty,
                    int64_t* grows) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   LF_HIP(hipSetDevice(f->mesh->ctx->device));
   if (nnz_u) *nnz_u = f->nnz;
   if (skel) *skel = (int64_t)f->skel_total;
@@ -1179,6 +1233,7 @@ lf_status lf_stats(lf_fields* f, int64_t* nnz_u, int64_t* skel, int64_t* steps, 
 
 lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   if (entries_in) *entries_in = (int64_t)f->in_total;
   if (entries_out) *entries_out = (int64_t)f->out_total;
   return LF_OK;
@@ -1188,6 +1243,7 @@ lf_status lf_traffic(lf_fields* f, int64_t* entries_in, int64_t* entries_out) tr
 
 lf_status lf_step_timing(lf_fields* f, int32_t enable, double* total_ms, int64_t* launches) try {
   if (!f) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   if (total_ms) *total_ms = f->timed_ms;
   if (launches) *launches = f->timed_launches;
   if (enable >= 0) {

@@ -158,6 +158,7 @@ lf_status lf_batch_fields(lf_batch* b, lf_fields** f) try {
 lf_status lf_batch_export(lf_batch* b, int32_t m, int64_t* nnz, int32_t* rowptr, int32_t* col,
                           float* val) try {
   if (!b || !nnz || m < 0 || m >= b->n) return bfail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(b->fields);
   lf_fields* f = b->fields;
   LF_HIP(hipSetDevice(b->ctx->device));
   hipStream_t s = b->ctx->stream;
@@ -193,6 +194,7 @@ lf_status lf_batch_export(lf_batch* b, int32_t m, int64_t* nnz, int32_t* rowptr,
 
 lf_status lf_batch_labels(lf_batch* b, int32_t m, int32_t* labels) try {
   if (!b || !labels || m < 0 || m >= b->n) return bfail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(b->fields);
   lf_fields* f = b->fields;
   LF_HIP(hipSetDevice(b->ctx->device));
   hipStream_t s = b->ctx->stream;

@@ -234,6 +234,15 @@ lf_status fields_csr(lf_fields* f, const int32_t** uptr, const Ent** uent);
 lf_status step_issue(lf_fields* f, int64_t n);
 bool step_ready(lf_fields* f);
 lf_status step_complete(lf_fields* f, int64_t* remaining);
+// completes what lf_step_async left in flight or to run (books the issued
+// chunk, steps again what had to be replayed, runs the rest); every entry
+// point that reads or changes the fields calls it first
+lf_status fields_settle(lf_fields* f);
+#define LF_SETTLE(f)                               \
+  do {                                             \
+    lf_status s_ = lf::fields_settle(f);           \
+    if (s_ != LF_OK) return s_;                    \
+  } while (0)
 // whether all of the first n steps booked by the last step_complete were
 // quiet: no row changed its label or its layers at or above tau, and no
 // value moved by more than eps
@@ -351,6 +360,7 @@ struct lf_fields {
   lf::StepStats* stats_pinned; // host copy of stats
   int64_t stats_pinned_cap;
   int64_t pending;             // steps issued and not yet booked
+  int64_t async_left = 0;      // steps of lf_step_async not issued yet (run when settled)
   hipEvent_t done_ev;          // recorded after the copies of an issued chunk
   size_t ev_issued;            // timing events used by the issued chunk
   // CSR view of the current fields, for export and post-processing

@@ -983,6 +983,7 @@ extern "C" {
 
 lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out) try {
   if (!f || !seeds_out) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   lf_mesh* m = f->mesh;
   LF_HIP(hipSetDevice(m->ctx->device));
   hipStream_t s = m->ctx->stream;
@@ -1069,6 +1070,7 @@ lf_status lf_lloyd_reseed(lf_fields* f, int32_t* seeds_out, int32_t* status_out)
 
 lf_status lf_lloyd(lf_fields* f, int32_t rounds, int32_t steps_per_round, int32_t* seeds_out) try {
   if (!f || rounds < 0 || steps_per_round < 0) return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
   std::vector<int32_t> seeds((size_t)f->n_s);
   for (int32_t r = 0; r < rounds; ++r) {
     lf_status st = lf_lloyd_reseed(f, seeds.data(), nullptr);
@@ -1085,6 +1087,7 @@ lf_status lf_lloyd(lf_fields* f, int32_t rounds, int32_t steps_per_round, int32_
 lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, int64_t* adj_nnz,
                        int32_t* adj_rowptr, int32_t* adj_col) try {
   if (!f || !n_tri || !adj_nnz) return fail(LF_EINVAL, "NULL argument");
+  LF_SETTLE(f);
   if (!(tau > 0.0 && tau <= 1.0)) return fail(LF_EINVAL, "tau must be in (0, 1]");
   lf_mesh* m = f->mesh;
   // a repeated call with output buffers returns the previous result
@@ -1320,6 +1323,7 @@ lf_status lf_dual_mesh(lf_fields* f, double tau, int64_t* n_tri, int32_t* tris, 
 
 lf_status lf_dual_matrix(lf_fields* f, int32_t which, int64_t* nnz, int32_t* rowptr, int32_t* col) try {
   if (!f || !nnz || (which != 0 && which != 1)) return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
   if (!f->dual) return fail(LF_EINVAL, "no dual mesh computed yet");
   const std::vector<int32_t>& rp = which == 0 ? f->dual->av_rp : f->dual->at_rp;
   const std::vector<int32_t>& c = which == 0 ? f->dual->av_col : f->dual->at_col;
@@ -1333,6 +1337,7 @@ lf_status lf_dual_matrix(lf_fields* f, int32_t which, int64_t* nnz, int32_t* row
 
 lf_status lf_dual_candidates(lf_fields* f, int64_t* n_cand, int32_t* pairs, int32_t* state) try {
   if (!f || !n_cand) return fail(LF_EINVAL, "invalid argument");
+  LF_SETTLE(f);
   if (!f->dual) return fail(LF_EINVAL, "no dual mesh computed yet");
   *n_cand = (int64_t)f->dual->cand_state.size();
   if (pairs) memcpy(pairs, f->dual->cand.data(), sizeof(int32_t) * f->dual->cand.size());

@@ -567,6 +567,47 @@ def test_dense_seeds_theta_zero(lf, orc):
     assert wide_seen > 0
 
 
+def test_step_async(lf):
+    """lf_step_async returns before its steps are done; the next call on the
+    fields completes them: the same fields, counters and measures as lf_step,
+    also when the overflow area must grow during the asynchronous steps."""
+    import time
+    lfb, ctx = lf
+    mesh, seeds = I.config_c2(level=6, n_seeds=256, seed=4)
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 1)
+    say("step async")
+    for hint in (0, 1):
+        a = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=hint))
+        b = lfb.Fields(m, seeds, lfb.default_params(capacity_hint=hint))
+        t0 = time.perf_counter()
+        a.step_async(600)
+        t_issue = time.perf_counter() - t0
+        b.step(600)
+        for x, y in zip(a.export(), b.export()):
+            assert np.array_equal(x, y)
+        assert a.stats() == b.stats() and a.stats()["steps"] == 600
+        assert a.last_change() == b.last_change()
+        # a step_async followed by steps, labels and the dual mesh
+        a.step_async(7)
+        b.step(7)
+        a.step(5)
+        b.step(5)
+        a.step_async(3)
+        b.step(3)
+        assert np.array_equal(a.labels(), b.labels())
+        ta, (ra, ca) = a.dual_mesh(0.25)
+        tb, (rb, cb) = b.dual_mesh(0.25)
+        assert np.array_equal(ta, tb) and np.array_equal(ra, rb) and np.array_equal(ca, cb)
+        a.step_async(100)
+        a.sync()
+        b.step(100)
+        assert a.stats() == b.stats()
+        a.step_async(50)  # destroyed with steps in flight and steps not issued
+        a.close()
+        b.close()
+    say("step async issue time", t_issue)
+
+
 def test_determinism(lf):
     lfb, ctx = lf
     mesh, seeds = I.config_c2(level=5, n_seeds=64, seed=2)
