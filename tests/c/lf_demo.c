@@ -59,7 +59,10 @@ int main(int argc, char** argv) {
   CHECK(lf_ctx_create(0, NULL, &ctx));
   CHECK(lf_mesh_create(ctx, V, n_v, F, n_f, op, &mesh));
   CHECK(lf_fields_create(mesh, seeds, n_s, &P, &f));
-  CHECK(lf_step(f, steps));
+  /* the steps run while the host goes on; lf_sync (or any later call on f)
+     completes them */
+  CHECK(lf_step_async(f, steps));
+  CHECK(lf_sync(f));
   CHECK(lf_labels(f, labels, 0));
 
   int64_t n_tri = 0, adj_nnz = 0;
