@@ -138,8 +138,6 @@ __device__ __forceinline__ float slot_update(float ph, float la, int col, const 
 template <int K, bool UNROLL, bool TYPED, class B>
 __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepConsts& c,
                                            int& n_keep, int& n_skel, int& ev) {
-  using M = typename MaskT<K>::type;
-  M act = 0;
   int n = 0, nC = 0;
   bool hb = false;
   float sqb = 0.f, T = 0.f, PC = 0.f, RC = 0.f, Pall = 0.f, Rall = 0.f;
@@ -154,8 +152,9 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
   if constexpr (UNROLL) {
     LF_SLOTS {
       const float ph = r.phi[s];
-      if (ph > 0.f || (ph == 0.f && r.lam[s] > 0.f)) {
-        act |= (M)1 << s;
+      const bool a = ph > 0.f || (ph == 0.f && r.lam[s] > 0.f);
+      r.phi[s] = a ? ph : -1.f;  // an inactive slot is marked by phi = -1
+      if (a) {
         ++n;
         T += r.lam[s];
         const float sq = root(ph);
@@ -169,8 +168,9 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
     LF_SLOTS_RT {
       if (s < cnt) {
         const float ph = r.phi[s];
-        if (ph > 0.f || (ph == 0.f && r.lam[s] > 0.f)) {
-          act |= (M)1 << s;
+        const bool a = ph > 0.f || (ph == 0.f && r.lam[s] > 0.f);
+        r.phi[s] = a ? ph : -1.f;  // an inactive slot is marked by phi = -1
+        if (a) {
           ++n;
           T += r.lam[s];
           const float sq = root(ph);
@@ -221,7 +221,7 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
     float sbuf[UNROLL ? K : 1];
     if constexpr (UNROLL) {
       LF_SLOTS {
-        tbuf[s] = ((act >> s) & 1) ? c.types[r.col[s]] : 0;
+        tbuf[s] = r.phi[s] >= 0.f ? c.types[r.col[s]] : 0;
         sbuf[s] = root(r.phi[s]);
       }
     }
@@ -241,7 +241,7 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
       const bool sb = r.col[s] == c.n_s;
       float Q = 0.f, G = 0.f;
       auto term = [&](int l) {
-        if (l == s || !((act >> l) & 1)) return;
+        if (l == s || !(r.phi[l] >= 0.f)) return;
         const float4 k = pair_coef(c, ts, type_of(l), sb, r.col[l] == c.n_s);
         Q += 0.5f * k.x * r.lam[l] + k.y * r.phi[l];
         G += k.z * sqrt_of(l);
@@ -269,16 +269,16 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
       V += v;
     };
     if constexpr (UNROLL) {
-      LF_SLOTS if ((act >> s) & 1) pass_q(s);
-      LF_SLOTS if ((act >> s) & 1) pass_v(s); else out_of(r, s) = -1.f;
+      LF_SLOTS if (r.phi[s] >= 0.f) pass_q(s);
+      LF_SLOTS if (r.phi[s] >= 0.f) pass_v(s); else out_of(r, s) = -1.f;
     } else {
-      LF_SLOTS_RT if ((act >> s) & 1) pass_q(s);
-      LF_SLOTS_RT if ((act >> s) & 1) pass_v(s); else out_of(r, s) = -1.f;
+      LF_SLOTS_RT if (r.phi[s] >= 0.f) pass_q(s);
+      LF_SLOTS_RT if (r.phi[s] >= 0.f) pass_v(s); else out_of(r, s) = -1.f;
     }
   } else if constexpr (UNROLL) {
-    LF_SLOTS if ((act >> s) & 1) upd(s); else out_of(r, s) = -1.f;
+    LF_SLOTS if (r.phi[s] >= 0.f) upd(s); else out_of(r, s) = -1.f;
   } else {
-    LF_SLOTS_RT if ((act >> s) & 1) upd(s); else out_of(r, s) = -1.f;
+    LF_SLOTS_RT if (r.phi[s] >= 0.f) upd(s); else out_of(r, s) = -1.f;
   }
   if (!(V > 0.f)) {
     ev = 1;
@@ -299,9 +299,9 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
     k += keep ? 1 : 0;
   };
   if constexpr (UNROLL) {
-    LF_SLOTS if ((act >> s) & 1) fin(s);
+    LF_SLOTS if (r.phi[s] >= 0.f) fin(s);
   } else {
-    LF_SLOTS_RT if ((act >> s) & 1) fin(s);
+    LF_SLOTS_RT if (r.phi[s] >= 0.f) fin(s);
   }
   n_keep = k;
 #undef LF_SLOTS
@@ -309,6 +309,8 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
 }
 
 // ---- register path --------------------------------------------------------
+
+constexpr int kNoLayer = -2147483647 - 1;  // layer of an empty register slot
 
 // whether the predicate holds on some active lane of the wavefront (the
 // ballot's mask is the compare's own result, with no re-materialisation)
@@ -405,9 +407,9 @@ __device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
 // matches a slot; a slot that none matches gets fma(w, 0, lam), which leaves
 // it unchanged); then each entry no slot holds opens one, in entry order --
 // the same sums and slot order as add_regs called once per entry.  key[j]
-// is the layer of entry j, or -3 on a lane where entry j does not take part
-// (slot layers are >= -1, so it matches nothing and opens nothing).  NV:
-// the entries that take part on some lane.
+// is the layer of entry j, or a negative value on a lane where entry j does
+// not take part (a slot holds a layer >= 0 or kNoLayer, so it matches
+// nothing and opens nothing).  NV: the entries that take part on some lane.
 template <int NV>
 __device__ __forceinline__ void add_row_wave(RowBuf<kRowRegs>& r, int& cnt, int& ub, bool& ovf,
                                              const int (&key)[kEll], const float (&x)[kEll],
@@ -463,7 +465,7 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& u
   // Every lane runs the gather (a lane past the last row, live false, reads
   // row 0 and adds nothing), so that the slot bound stays wavefront-uniform.
 #pragma unroll
-  for (int s = 0; s < kRowRegs; ++s) { r.col[s] = -1; r.phi[s] = 0.f; r.lam[s] = 0.f; }
+  for (int s = 0; s < kRowRegs; ++s) { r.col[s] = kNoLayer; r.phi[s] = 0.f; r.lam[s] = 0.f; }
   cnt = 0;
   const int ic = live ? i : 0;
   const EllRow own = row_at(A.u_in, ic);
@@ -511,12 +513,15 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& u
     const bool nb = le[k].col >= 0;
     const bool nb_ovf = nb && is_ovf(u.e[0]);
     onb |= nb_ovf ? 1u << k : 0u;
+    // an unused entry of a row holds layer -1 and a row not taking part
+    // gives -3: neither matches a slot (an empty slot holds kNoLayer), and
+    // neither opens one
     const bool row_ok = nb && !nb_ovf;
     int key[kEll];
     float x[kEll];
 #pragma unroll
     for (int j = 0; j < kEll; ++j) {
-      key[j] = row_ok && u.e[j].col >= 0 ? u.e[j].col : -3;  // slot layers are >= -1
+      key[j] = row_ok ? u.e[j].col : -3;
       x[j] = u.e[j].val;
     }
     // (a row's entries fill from entry 0: none takes part where entry 0 does not)
@@ -691,7 +696,7 @@ __device__ __forceinline__ void row_change(const RowBuf<kRowRegs>& r, int ub,
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) {
     if (s >= ub) break;
-    a.add(r.col[s], r.phi[s], r.lam[s], k);
+    a.add(r.col[s], fmaxf(r.phi[s], 0.f), r.lam[s], k);
   }
   changed = a.changed();
   dmax = a.dmax;
@@ -700,7 +705,7 @@ __device__ __forceinline__ void row_change(const RowBuf<kRowRegs>& r, int ub,
 __device__ __forceinline__ void wide_change(const WideRow* r, const StepConsts& k, int& changed,
                                             float& dmax) {
   ChangeAcc a;
-  for (int s = 0; s < r->cnt; ++s) a.add(r->col[s], r->phi[s], r->out[s], k);
+  for (int s = 0; s < r->cnt; ++s) a.add(r->col[s], fmaxf(r->phi[s], 0.f), r->out[s], k);
   changed = a.changed();
   dmax = a.dmax;
 }
