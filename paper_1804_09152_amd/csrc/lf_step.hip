@@ -142,8 +142,10 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
   bool hb = false;
   float sqb = 0.f, T = 0.f, PC = 0.f, RC = 0.f, Pall = 0.f, Rall = 0.f;
 // unrolled: stop at the wavefront's largest slot count ub, a uniform value
-// (slots at and above the row's count hold layer -1 with phi = lam = 0, so
-// they are never active); runtime loop for the wide path
+// (register slots at and above the row's count hold no layer and phi = lam =
+// 0, so they are never active); runtime loop over the workspace row for the
+// wide path.  The first loop marks every inactive slot by phi = -1 for the
+// later ones.
 #define LF_SLOTS                                  \
   _Pragma("unroll") for (int s = 0; s < K; ++s)   \
     if (s >= ub) break;                           \
@@ -179,6 +181,8 @@ __device__ __forceinline__ void row_update(B& r, int cnt, int ub, const StepCons
           if (r.col[s] == c.n_s) { hb = true; sqb = sq; }
           else { ++nC; PC += ph; RC += sq; }
         }
+      } else {
+        r.phi[s] = -1.f;  // the workspace slots past the row's count: inactive too
       }
     }
   }
