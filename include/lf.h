@@ -154,7 +154,8 @@ lf_status lf_fields_set_coefficients(lf_fields* f, int32_t n_types, const int32_
  * area is detected on the GPU, the area grows by 20% or more and the step is
  * replayed, so results never depend on capacities.  LF_ECAPACITY if a
  * vertex touches more layers than the row limit (64) or storage cannot
- * grow. */
+ * grow; the steps before the failing one stay done, and the fields hold
+ * their state from before it. */
 lf_status lf_step(lf_fields* f, int32_t n_steps);
 /* lf_step without waiting: enqueues the first min(n_steps, 256) steps on
  * the context stream and returns at once (the GPU works while the caller

@@ -560,7 +560,7 @@ static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const
   ALLOC(f->d_seeds, n_s);
   ALLOC(f->owner, m->n_v);
   for (int k = 0; k < 2; ++k) {
-    ALLOC(f->ell[k], m->n_v);
+    ALLOC(f->ell[k], m->n_v + 1);
     ALLOC(f->ovf[k], f->ovf_cap);
   }
   ALLOC(f->counters, 4);
@@ -576,6 +576,11 @@ static lf_status fields_new(lf_mesh* m, const int32_t* seeds, int32_t n_s, const
     return hip_fail(e, "allocating field state");
   }
   e = launch_reset_flags(f->flags, nullptr, 0, m->ctx->stream);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    // row n_v: the empty row read in place of a missing neighbour
+    static const EllRow empty{{Ent{-1, 0.f}, Ent{-1, 0.f}, Ent{-1, 0.f}}};
+    e = hipMemcpy(f->ell[k] + m->n_v, &empty, sizeof(EllRow), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     lf_fields_destroy(f);
     return hip_fail(e, "reset flags");
@@ -651,7 +656,7 @@ int64_t mesh_bytes(const lf_mesh* m) {
 
 int64_t fields_bytes(const lf_fields* f) {
   const int64_t nv = f->mesh->n_v;
-  return 2 * (int64_t)sizeof(EllRow) * nv + 2 * 8 * f->ovf_cap + 4 * nv + 4ll * f->n_s +
+  return 2 * (int64_t)sizeof(EllRow) * (nv + 1) + 2 * 8 * f->ovf_cap + 4 * nv + 4ll * f->n_s +
          (int64_t)sizeof(WideRow) * f->wide_cap + (f->wide_rows ? 4 * nv : 0) +
          4 * (nv + 1) + 8 * f->csr_cap +
          8 * scan_tmp_elems(nv) + (int64_t)sizeof(StepStats) * f->stats_cap * (1 + kParts) +

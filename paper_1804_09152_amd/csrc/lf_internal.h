@@ -28,10 +28,15 @@ constexpr int kTileRows = 4096;     // rows per re-ordering tile (64 slices)
 
 // One row of the fields in fixed-width form: up to kEll entries, ascending
 // layers, unused slots {-1, 0}.  A row with more entries keeps them in the
-// overflow area: e[0] = {kOvfMark, 0}, e[1].col = offset, e[2].col = count.
+// overflow area: e[0] = {kOvfMark, 0}, e[1].col = ~offset, e[2].col = ~count
+// (bit-inverted, so negative: no column of a header reads as a layer), values
+// 0.  The field buffers hold one row more than the mesh has vertices: row n_v
+// is an empty row, never written, that stands in for missing neighbours.
 struct __attribute__((aligned(8))) EllRow {
   Ent e[kEll];
 };
+__host__ __device__ inline int32_t ovf_enc(int64_t v) { return ~(int32_t)v; }
+__host__ __device__ inline int64_t ovf_dec(int32_t c) { return (int64_t)~c; }
 
 // The operator's off-diagonal entries for the step, in slices of kSlice
 // rows stored column-major with one width w for all slices: entry k < w of

@@ -90,7 +90,7 @@ __global__ void k_ell_count(const EllRow* u, const int32_t* inv, int32_t n_v, in
   const EllRow r = u[inv[i]];
   int n = 0;
   if (r.e[0].col == kOvfMark) {
-    n = r.e[2].col;
+    n = (int)ovf_dec(r.e[2].col);
   } else {
 #pragma unroll
     for (int j = 0; j < kEll; ++j) n += r.e[j].col >= 0 ? 1 : 0;
@@ -105,7 +105,7 @@ __global__ void k_ell_fill(const EllRow* u, const Ent* ovf, const int32_t* inv, 
   const EllRow r = u[inv[i]];
   const int32_t o = uptr[i], n = uptr[i + 1] - o;
   if (r.e[0].col == kOvfMark) {
-    const Ent* src = ovf + r.e[1].col;
+    const Ent* src = ovf + ovf_dec(r.e[1].col);
     for (int j = 0; j < n; ++j) uent[o + j] = src[j];
   } else {
     for (int j = 0; j < n; ++j) uent[o + j] = r.e[j];
@@ -120,8 +120,8 @@ __global__ void k_csr_to_ell(const int32_t* uptr, const Ent* uent, const int32_t
   EllRow r;
   if (n > kEll) {
     r.e[0] = Ent{kOvfMark, 0.f};
-    r.e[1] = Ent{a, 0.f};
-    r.e[2] = Ent{n, 0.f};
+    r.e[1] = Ent{ovf_enc(a), 0.f};
+    r.e[2] = Ent{ovf_enc(n), 0.f};
     for (int j = 0; j < n; ++j) ovf[a + j] = uent[a + j];
   } else {
 #pragma unroll

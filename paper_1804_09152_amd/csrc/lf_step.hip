@@ -387,7 +387,7 @@ struct RowView {
 // the entries of an overflow row (bounds-checked, so that a row written by
 // a failed step reads as empty)
 __device__ __forceinline__ RowView ovf_view(const StepArgs& A, const EllRow& u) {
-  const long long o = u.e[1].col, n = u.e[2].col;
+  const long long o = ovf_dec(u.e[1].col), n = ovf_dec(u.e[2].col);
   if (o < 0 || n < 0 || o + n > A.ovf_cap) return RowView{A.ovf_in, 0};
   return RowView{A.ovf_in + o, (int)n};
 }
@@ -418,9 +418,14 @@ template <int NV>
 __device__ __forceinline__ void add_row_wave(RowBuf<kRowRegs>& r, int& cnt, int& ub, bool& ovf,
                                              const int (&key)[kEll], const float (&x)[kEll],
                                              float w) {
-  bool found[NV];
+  // found[j]: the lanes whose entry j is held by a slot (or takes no part),
+  // as a wavefront mask in scalar registers
+  unsigned long long found[NV];
 #pragma unroll
-  for (int j = 0; j < NV; ++j) found[j] = key[j] < 0;
+  for (int j = 0; j < NV; ++j) found[j] = __builtin_amdgcn_ballot_w64(key[j] < 0);
+  const unsigned long long lanes = __builtin_amdgcn_read_exec();
+  // a row's entries fill from entry 0: none takes part where entry 0 does not
+  if ((lanes & ~found[0]) == 0ull) return;
 #pragma unroll
   for (int s = 0; s < kRowRegs; ++s) {
     if (s >= ub) break;
@@ -429,14 +434,16 @@ __device__ __forceinline__ void add_row_wave(RowBuf<kRowRegs>& r, int& cnt, int&
     for (int j = NV - 1; j >= 0; --j) {
       const bool m = r.col[s] == key[j];
       xs = m ? x[j] : xs;
-      found[j] = found[j] || m;
+      found[j] |= __builtin_amdgcn_ballot_w64(m);
     }
     r.lam[s] = fmaf(w, xs, r.lam[s]);
   }
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
-    if (!wave_any(!found[j])) continue;
-    const bool ins = !found[j] && cnt < kRowRegs;
+    const unsigned long long nf = lanes & ~found[j];
+    if (nf == 0ull) continue;
+    const unsigned long long im = nf & __builtin_amdgcn_ballot_w64(cnt < kRowRegs);
+    const bool ins = __builtin_amdgcn_inverse_ballot_w64(im);
     const float wx = w * x[j];
 #pragma unroll
     for (int s = 0; s < kRowRegs; ++s) {
@@ -445,8 +452,8 @@ __device__ __forceinline__ void add_row_wave(RowBuf<kRowRegs>& r, int& cnt, int&
       r.col[s] = m ? key[j] : r.col[s];
       r.lam[s] = m ? wx : r.lam[s];
     }
-    ovf = ovf || (!found[j] && !ins);
-    ub += wave_any(ins && cnt == ub) ? 1 : 0;  // cnt <= ub on every lane
+    if (nf & ~im) ovf = ovf || __builtin_amdgcn_inverse_ballot_w64(nf & ~im);
+    ub += (im & __builtin_amdgcn_ballot_w64(cnt == ub)) ? 1 : 0;  // cnt <= ub on every lane
     cnt += ins ? 1 : 0;
   }
 }
@@ -480,7 +487,7 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& u
 #pragma unroll
   for (int j = 0; j < kEll; ++j) n_in += own.e[j].col >= 0 ? 1 : 0;
   const bool own_ovf = live && is_ovf(own.e[0]);
-  if (own_ovf) n_in = own.e[2].col;
+  if (own_ovf) n_in = (int)ovf_dec(own.e[2].col);
   if (!live) n_in = 0;
   // operator entries: lanes past the last row hold {-1, 0} in the slice
   Ent le[kOpWidth];
@@ -489,17 +496,18 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& u
     le[k] = k < A.op_w ? ops[k * kSlice] : Ent{-1, 0.f};
   EllRow win[kWin];
 #pragma unroll
-  for (int k = 0; k < kWin; ++k) win[k] = row_at(A.u_in, le[k].col >= 0 ? le[k].col : ic);
+  for (int k = 0; k < kWin; ++k) win[k] = row_at(A.u_in, le[k].col >= 0 ? le[k].col : A.n_v);
   bool ovf = false;
   // the entries of an overflow row, scaled by w
   auto merge_ovf = [&](const EllRow& u, float w) {
     const RowView v = ovf_view(A, u);
     for (int p = 0; p < v.n; ++p) add_regs(r, cnt, ovf, v.p[p].col, w, v.p[p].val);
   };
-  // own row: slots 0..kEll-1 in layer order (an overflow row is merged last)
+  // own row: slots 0..kEll-1 in layer order (an overflow row is merged
+  // last; its header's columns are negative)
 #pragma unroll
   for (int j = 0; j < kEll; ++j) {
-    if (live && !own_ovf && own.e[j].col >= 0) {
+    if (live && own.e[j].col >= 0) {
       r.col[j] = own.e[j].col;
       r.phi[j] = own.e[j].val;
       r.lam[j] = dg * own.e[j].val;
@@ -507,29 +515,29 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& u
     }
   }
   ub = wave_slots(cnt);
-  unsigned onb = 0;  // neighbours in the slice whose rows are overflow rows
+  // neighbours in the slice whose rows are overflow rows: neighbour k at bit
+  // nk - 1 - k (one doubling add per neighbour)
+  unsigned onb = 0;
+  int nk = 0;
 #pragma unroll
   for (int k = 0; k < kOpWidth; ++k) {
     if (k >= A.op_w) break;
     const EllRow u = win[k % kWin];
     if (k + kWin < kOpWidth && k + kWin < A.op_w)
-      win[k % kWin] = row_at(A.u_in, le[k + kWin].col >= 0 ? le[k + kWin].col : ic);
-    const bool nb = le[k].col >= 0;
-    const bool nb_ovf = nb && is_ovf(u.e[0]);
-    onb |= nb_ovf ? 1u << k : 0u;
-    // an unused entry of a row holds layer -1 and a row not taking part
-    // gives -3: neither matches a slot (an empty slot holds kNoLayer), and
-    // neither opens one
-    const bool row_ok = nb && !nb_ovf;
+      win[k % kWin] = row_at(A.u_in, le[k + kWin].col >= 0 ? le[k + kWin].col : A.n_v);
+    onb = onb + onb + (is_ovf(u.e[0]) ? 1u : 0u);
+    nk = k + 1;
+    // a missing neighbour reads the empty row (layers -1) and an overflow
+    // row's header has negative columns: neither matches a slot (an empty
+    // slot holds kNoLayer) and neither opens one
     int key[kEll];
     float x[kEll];
 #pragma unroll
     for (int j = 0; j < kEll; ++j) {
-      key[j] = row_ok ? u.e[j].col : -3;
+      key[j] = u.e[j].col;
       x[j] = u.e[j].val;
     }
-    // (a row's entries fill from entry 0: none takes part where entry 0 does not)
-    if (wave_any(key[0] >= 0)) add_row_wave<kEll>(r, cnt, ub, ovf, key, x, le[k].val);
+    add_row_wave<kEll>(r, cnt, ub, ovf, key, x, le[k].val);
   }
   // the rare entries, under divergent control: the slot bound is counted
   // again afterwards
@@ -549,9 +557,10 @@ __device__ __forceinline__ int gather_regs(RowBuf<kRowRegs>& r, int& cnt, int& u
           if (u.e[j].col >= 0) add_regs(r, cnt, ovf, u.e[j].col, l.val, u.e[j].val);
       }
     }
-    while (onb) {  // the overflow rows among the slice's neighbours
-      const int k = __builtin_ctz(onb);
-      onb &= onb - 1u;
+    while (onb) {  // the overflow rows among the slice's neighbours, in column order
+      const int b = 31 - __builtin_clz(onb);
+      const int k = nk - 1 - b;
+      onb &= ~(1u << b);
       const Ent l = ops[k * kSlice];
       merge_ovf(row_at(A.u_in, l.col), l.val);
     }
@@ -903,8 +912,8 @@ __device__ __forceinline__ WideResult wide_row_wave(const StepArgs& A, const int
       step_failed(A, 1u);  // the step is replayed with a larger area
     }
     if (lane == 0) row[0] = Ent{kOvfMark, 0.f};
-    if (lane == 1) row[1] = Ent{fits ? (int32_t)o : 0, 0.f};
-    if (lane == 2) row[2] = Ent{fits ? n_keep : 0, 0.f};
+    if (lane == 1) row[1] = Ent{ovf_enc(fits ? o : 0), 0.f};
+    if (lane == 2) row[2] = Ent{ovf_enc(fits ? n_keep : 0), 0.f};
     if (fits && lane_in(km)) A.ovf_out[o + rank] = Ent{col, out};
   } else {
     if (lane_in(km)) row[rank] = Ent{col, out};
@@ -1097,8 +1106,8 @@ __device__ __forceinline__ void step_slice(const StepArgs& A, const int sl) {
         step_failed(A, 1u);  // the step is replayed with a larger area
       }
       row[0] = Ent{kOvfMark, 0.f};
-      row[1] = Ent{fits ? (int32_t)o : 0, 0.f};
-      row[2] = Ent{fits ? n_keep : 0, 0.f};
+      row[1] = Ent{ovf_enc(fits ? o : 0), 0.f};
+      row[2] = Ent{ovf_enc(fits ? n_keep : 0), 0.f};
       dst = fits ? A.ovf_out + o : nullptr;
     } else if (wide < 0) {
       // the whole row from registers: 24-byte stores, contiguous across the

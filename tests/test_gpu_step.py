@@ -492,6 +492,61 @@ def test_wide_workspace_growth(lf, orc):
     check_step(as_oracle(f.export()), O, info, 1e-3, max_skel_guarded_frac=0.05, what="wide growth")
 
 
+def test_more_than_64_layers_fails_cleanly(lf, orc):
+    """A vertex whose row and neighbour rows hold 70 distinct layers (the
+    wide path keeps one slot per layer, 64 at most): the step fails with
+    LF_ECAPACITY and leaves the fields as they were, on the first call
+    (workspace path of the step kernel) and on the second (the wide rows'
+    own kernel, enabled by the first call); a state within the limit then
+    steps as the oracle does."""
+    lfb, ctx = lf
+    mesh = I.torus_grid(16, 16)
+    L = orc.operator(mesh.V, mesh.F, 0)
+    n_s = 72
+    nb = lambda v: [int(c) for c in L[1][L[0][v]:L[0][v + 1]] if c != v]
+
+    def state(per):
+        rows = [{n_s: 1.0} for _ in range(mesh.n_v)]
+        rows[0] = {c: 0.1 for c in range(10)}
+        for j, u in enumerate(nb(0)):
+            rows[u] = {10 + 10 * j + k: 1.0 / per for k in range(per)}
+        seen = set()
+        for u in [0] + nb(0):
+            seen |= set(rows[u])
+        ptr = np.zeros(mesh.n_v + 1, np.int64)
+        col, val = [], []
+        for i, r in enumerate(rows):
+            for c in sorted(r):
+                col.append(c)
+                val.append(r[c])
+            ptr[i + 1] = len(col)
+        return f32((ptr, np.array(col, np.int32), np.array(val))), len(seen)
+
+    assert len(nb(0)) == 6
+    U, n_union = state(10)
+    assert n_union == 70
+    m = lfb.Mesh(ctx, mesh.V, mesh.F, 0)
+    f = lfb.Fields(m, np.arange(n_s, dtype=np.int32) * 3)
+    gpu_load(f, U)
+    before = f.export()
+    for call in range(2):
+        say("more than 64 layers, call", call)
+        with pytest.raises(lfb.LFError) as e:
+            f.step(1)
+        assert e.value.status == 4  # LF_ECAPACITY
+        for x, y in zip(f.export(), before):
+            assert np.array_equal(x, y)
+    U, n_union = state(5)
+    assert n_union == 40
+    say("more than 64 layers: a state within the limit afterwards")
+    gpu_load(f, U)
+    f.step(1)
+    O, info = orc.step(L, U, n_s, orc.default_params(), want_info=True)
+    check_step(as_oracle(f.export()), O, info, 1e-3, max_skel_guarded_frac=0.05,
+               what="after the capacity failure")
+    f.close()
+
+
 def test_wide_rows_after_the_step_launch(lf, orc):
     """Once a step has met rows touching more than 8 layers, later steps hand
     them to a kernel of their own (one wavefront per row) after the step
