@@ -1150,9 +1150,15 @@ __device__ __forceinline__ int xcd_slice(int n) {
   return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
 }
 
+// Scalar registers bound the step kernel's residency on gfx950: with the 104
+// the compiler would use, six wavefronts per SIMD are resident (6,144 on
+// 1,024 SIMDs, measured with per-wavefront clock stamps), with 78 eight;
+// capped at 88, seven (the vector registers, at most 72, allow seven).  The
+// cap costs a few scalar values kept in vector-register lanes instead.
+#define LF_STEP_REGS __attribute__((amdgpu_waves_per_eu(4), amdgpu_num_sgpr(88)))
+
 template <bool TYPED>
-__global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step(
-    StepArgs A) {
+__global__ __launch_bounds__(kSlice) LF_STEP_REGS void k_step(StepArgs A) {
   const int sl = xcd_slice(A.n_slices);
   if (sl >= A.n_slices) return;
   step_slice<TYPED>(A, sl);
@@ -1170,7 +1176,7 @@ __device__ __forceinline__ T* to_global(T* p) {
 // launch, first[n_jobs] = total), each with its own arguments G[j]; the XCD
 // order runs over the whole launch.
 template <bool TYPED>
-__global__ __launch_bounds__(kSlice) __attribute__((amdgpu_waves_per_eu(4))) void k_step_group(
+__global__ __launch_bounds__(kSlice) LF_STEP_REGS void k_step_group(
     const StepArgs* __restrict__ G, const int32_t* __restrict__ first, int32_t n_jobs) {
   const int total = first[n_jobs];
   const int g = xcd_slice(total);
