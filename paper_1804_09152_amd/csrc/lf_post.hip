@@ -792,9 +792,11 @@ __global__ void k_seed_normals(const double* V, const int32_t* F, int32_t n_f, c
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= n_f) return;
   const int32_t* fv = F + 3 * (int64_t)f;
+  const int32_t ow[3] = {owner[fv[0]], owner[fv[1]], owner[fv[2]]};
+  if (ow[0] >= n_s && ow[1] >= n_s && ow[2] >= n_s) return;  // no seed: no geometry read
   const Vec3 c = vcross(vsub(vload(V, fv[1]), vload(V, fv[0])), vsub(vload(V, fv[2]), vload(V, fv[0])));
   for (int k = 0; k < 3; ++k) {
-    const int32_t o = owner[fv[k]];
+    const int32_t o = ow[k];
     if (o < n_s) {
       atomicAdd(&vn[3 * (int64_t)o], c.x);
       atomicAdd(&vn[3 * (int64_t)o + 1], c.y);
