@@ -412,8 +412,11 @@ __device__ __forceinline__ RowView row_view(const StepArgs* A, int u) {
 // it unchanged); then each entry no slot holds opens one, in entry order --
 // the same sums and slot order as add_regs called once per entry.  key[j]
 // is the layer of entry j, or a negative value on a lane where entry j does
-// not take part (a slot holds a layer >= 0 or kNoLayer, so it matches
-// nothing and opens nothing).  NV: the entries that take part on some lane.
+// not take part: a negative key opens no slot and matches none (slots hold
+// layers >= 0, empty ones kNoLayer; an overflow header's column that equals
+// kNoLayer carries the value 0, so its match adds nothing).  Which entries
+// the slots hold is kept as wavefront masks (ballots) in scalar registers.
+// NV: the entries that take part on some lane.
 template <int NV>
 __device__ __forceinline__ void add_row_wave(RowBuf<kRowRegs>& r, int& cnt, int& ub, bool& ovf,
                                              const int (&key)[kEll], const float (&x)[kEll],
