@@ -770,20 +770,6 @@ __device__ __forceinline__ WideResult wide_row_wave(const StepArgs& A, const int
   int cnt = 0;
   bool full = false;  // more than kRowWide layers
   const float dg = A.ldiag[i];
-  const RowView own = row_view(&A, i);
-  for (int p = 0; p < own.n; ++p) {  // own entries: distinct layers
-    if (cnt == kRowWide) {
-      full = true;
-      break;
-    }
-    const Ent e = own.p[p];
-    if (lane == cnt) {
-      col = e.col;
-      phi = e.val;
-      lam = dg * e.val;
-    }
-    ++cnt;
-  }
   // adds x scaled by wgt into layer c (a new slot when no lane holds it)
   auto add = [&](int c, float wgt, float x) {
     const Mask m = ballot(col == c);
@@ -800,10 +786,14 @@ __device__ __forceinline__ WideResult wide_row_wave(const StepArgs& A, const int
       ++cnt;
     }
   };
-  // the neighbours' operator entries and inline rows are loaded one
-  // neighbour per lane, together, and then merged in column order
+  // The neighbours' operator entries and rows are loaded one neighbour per
+  // lane, and a neighbour row kept in the overflow area has its first kPre
+  // entries loaded by its lane too, all before the own row is merged; the
+  // merge then runs in the fixed order on values already in registers (a
+  // longer overflow row reads the rest from memory).
+  constexpr int kPre = 6;
   const int q0 = A.lptr[i], deg = A.lptr[i + 1] - q0;
-  for (int k0 = 0; k0 < deg && !full; k0 += kSlice) {
+  for (int k0 = 0; k0 == 0 || k0 < deg; k0 += kSlice) {
     const int k = k0 + lane;
     Ent le{-1, 0.f};
     if (k < deg) le = k < A.op_w ? ops[k * kSlice] : A.lent[q0 + k];
@@ -811,14 +801,49 @@ __device__ __forceinline__ WideResult wide_row_wave(const StepArgs& A, const int
 #pragma unroll
     for (int j = 0; j < kEll; ++j) u.e[j] = Ent{-1, 0.f};
     if (le.col >= 0) u = row_at(A.u_in, le.col);
+    int pre_n = 0;
+    Ent pre[kPre];
+#pragma unroll
+    for (int p = 0; p < kPre; ++p) pre[p] = Ent{-1, 0.f};
+    if (le.col >= 0 && u.e[0].col == kOvfMark) {
+      const RowView v = ovf_view(A, u);
+      pre_n = v.n;
+#pragma unroll
+      for (int p = 0; p < kPre; ++p)
+        if (p < v.n) pre[p] = v.p[p];
+    }
+    if (k0 == 0) {  // own entries first: distinct layers
+      const RowView own = row_view(&A, i);
+      for (int p = 0; p < own.n; ++p) {
+        if (cnt == kRowWide) {
+          full = true;
+          break;
+        }
+        const Ent e = own.p[p];
+        if (lane == cnt) {
+          col = e.col;
+          phi = e.val;
+          lam = dg * e.val;
+        }
+        ++cnt;
+      }
+    }
     const int kn = deg - k0 < kSlice ? deg - k0 : kSlice;
     for (int q = 0; q < kn && !full; ++q) {
       const int nb = lane_i32(le.col, q);
       if (nb < 0) continue;
       const float wgt = lane_f32(le.val, q);
       if (lane_i32(u.e[0].col, q) == kOvfMark) {
-        const RowView v = row_view(&A, nb);
-        for (int p = 0; p < v.n && !full; ++p) add(v.p[p].col, wgt, v.p[p].val);
+        const int n = lane_i32(pre_n, q);
+#pragma unroll
+        for (int p = 0; p < kPre; ++p) {
+          if (p >= n || full) break;
+          add(lane_i32(pre[p].col, q), wgt, lane_f32(pre[p].val, q));
+        }
+        if (n > kPre) {
+          const RowView v = row_view(&A, nb);
+          for (int p = kPre; p < v.n && !full; ++p) add(v.p[p].col, wgt, v.p[p].val);
+        }
         continue;
       }
 #pragma unroll
@@ -828,6 +853,7 @@ __device__ __forceinline__ WideResult wide_row_wave(const StepArgs& A, const int
         add(c, wgt, lane_f32(u.e[j].val, q));
       }
     }
+    if (full) break;
   }
   Ent* row = A.u_out[i].e;
   if (full) {  // the step fails; the row is written empty
